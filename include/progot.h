@@ -1,0 +1,204 @@
+/*
+ * progot.h -- C ABI of the MI355X (gfx950) progressive entropic OT hot path.
+ *
+ * The library computes, on one GPU, the steps of progressive entropic optimal
+ * transport (ProgOT, Kassraie et al. 2024):
+ *   - log-domain Sinkhorn between two weighted point clouds under the cost
+ *     h(x - y) = |x - y|^2 (Alg. 1 "Sink"; the entropic dual, eq. entdual);
+ *   - the entropic map / barycentric projection and the McCann-type step
+ *     x <- (1 - alpha) x + alpha T(x) (eq. Tent; Alg. 2, projection lines);
+ *   - ProgOT itself (Alg. 2) and the progressive map T_Prog (Alg. 3).
+ *
+ * Conventions (readings of the paper; the same in the FP64 oracle):
+ *   coupling  P_ij = exp((f_i + g_j - C_ij)/eps),  P 1 = a,  P^T 1 = b
+ *   f-update  f_i = eps log a_i - eps LSE_j((g_j - C_ij)/eps)
+ *   g-update  g_j = eps log b_j - eps LSE_i((f_i - C_ij)/eps)
+ *   stop rule after each full (f, g) iteration, when |P 1 - a|_1 <= tau;
+ *             the (f, g) of that iteration is returned
+ *   map       T(x) = sum_j softmax_j((g_j - |x - y_j|^2)/eps) y_j
+ *   K         number of Sinkhorn solves, k = 0..K-1, constant speed
+ *             alpha_k = 1/(K - k) (alpha_{K-1} = 1)
+ *
+ * Memory and ownership.  Every pointer named "device" is device memory owned
+ * by the caller.  The library never allocates device memory: all scratch
+ * lives in a caller-provided workspace of pot_workspace_bytes() bytes.  The
+ * pot_clouds struct is a host POD owned by the caller, valid while its
+ * workspace lives.  X, Y, a, b are never written.  Layouts are row-major:
+ * a cloud of n points in R^d is n*d floats, point i at [i*d, (i+1)*d).
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Work is enqueued on it.  pot_prepare_clouds, pot_sinkhorn_solve,
+ * pot_progot_solve and pot_marginal_check block the calling host thread
+ * (convergence checks and scalar read-backs); pot_entropic_map and
+ * pot_progot_map do not.
+ *
+ * Errors.  Arguments are validated on the host before any launch; invalid
+ * arguments return POT_ERR_INVALID and enqueue nothing.  A positive status is
+ * a warning with valid outputs.  No C++ exception crosses the ABI.
+ */
+#ifndef PROGOT_H
+#define PROGOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define POT_API __attribute__((visibility("default")))
+#else
+#define POT_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    POT_OK = 0,
+    POT_WARN_NOT_CONVERGED = 1, /* stopped at max_iter with err > tau; outputs valid   */
+    POT_ERR_INVALID = -1,       /* bad sizes, null pointers, eps <= 0, K out of range  */
+    POT_ERR_NOMEM = -2,         /* workspace smaller than pot_workspace_bytes()        */
+    POT_ERR_NUMERIC = -3,       /* a non-finite marginal error or mean cost was seen    */
+    POT_ERR_DEVICE = -4         /* a HIP runtime call failed                           */
+} pot_status;
+
+/* Arithmetic of the cross term <x_i, y_j> of the cost.  FP32: FP32 MFMA with
+ * FP32 accumulation.  BF16: BF16 MFMA (inputs rounded to nearest even) with
+ * FP32 accumulation; norms, log-sum-exp, potentials and marginal errors stay
+ * FP32 in both. */
+typedef enum { POT_PREC_FP32 = 0, POT_PREC_BF16 = 1 } pot_precision;
+
+#define POT_MAX_D 256      /* largest supported dimension d                    */
+#define POT_MAX_K 64       /* largest number of ProgOT steps K                  */
+
+/* Device-resident pair of clouds with their precomputed per-point data
+ * (filled by pot_prepare_clouds; all pointers are views into the caller's
+ * inputs and workspace). */
+typedef struct pot_clouds {
+    int64_t n, m;          /* source and target sizes                           */
+    int32_t d, precision;  /* dimension, pot_precision                          */
+    const float *X, *Y;    /* caller inputs (device), n*d and m*d               */
+    const float *a, *b;    /* caller weights (device) or NULL for uniform       */
+    float *xk;             /* current source iterate X^(k) (device, n*d)        */
+    float *x_sqn, *y_sqn;  /* |x_i|^2, |y_j|^2 (device, FP32, from FP64 sums)   */
+    float *log_a, *log_b;  /* log weights (device)                              */
+    void *x_lp, *y_lp;     /* BF16 copies of xk and Y (device; BF16 form only)  */
+    double mean_cost;      /* (1/nm) sum_ij |x_i - y_j|^2 for the current xk    */
+    void *ws;              /* workspace base (device)                           */
+    size_t ws_bytes;
+} pot_clouds;
+
+/* Bytes of device workspace pot_prepare_clouds needs for these sizes (the
+ * same workspace serves every later call on the pair).  0 if invalid. */
+POT_API size_t pot_workspace_bytes(int64_t n, int64_t m, int32_t d, int32_t precision);
+
+/* Step "prepare" of the path: squared norms (FP64 sums rounded to FP32), log
+ * weights, the working copy xk = X, BF16 copies in the BF16 form, and the
+ * mean cost (1/nm) sum_ij |x_i - y_j|^2 that sets eps_0 (Alg. 4, first set
+ * line) and the per-step eps (App. C).
+ *   X (device, n*d), Y (device, m*d); a (device, n) / b (device, m) are
+ *   probability weights, or NULL for uniform 1/n, 1/m.
+ *   ws (device, ws_bytes >= pot_workspace_bytes) is owned by the caller.
+ * Blocks until the mean cost is on the host.  1 <= d <= POT_MAX_D. */
+POT_API int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
+                       int32_t d, const float *a, const float *b, int32_t precision,
+                       void *ws, size_t ws_bytes, void *stream);
+
+typedef struct {
+    int32_t iters;         /* full (f, g) iterations of the returned iterate     */
+    int32_t converged;     /* 1 if err <= tau                                    */
+    float err;             /* |P 1 - a|_1 of the returned (f, g)                 */
+    double seconds;        /* host wall time of the call                         */
+} pot_sinkhorn_info;
+
+/* Alg. 1 Sink(a, X^(k), b, Y, eps, tau, f_init, g_init) on the current source
+ * iterate c->xk.  Each iteration runs the f-update then the g-update (fused
+ * cost + streaming log-sum-exp kernels, the n x m cost is never stored); the
+ * row-marginal error of iteration t comes free from the f-update of t + 1.
+ *   eps > 0; tau >= 0.  tau == 0 selects fixed-iteration mode: exactly
+ *   max_iter iterations, status POT_OK.  max_iter >= 1.
+ *   f_init (device, n) may be NULL: it cannot change the iterates because the
+ *   first f-update overwrites f; g_init (device, m) NULL means zero.
+ *   f (device, n) and g (device, m) receive the result; they may alias the
+ *   init buffers.
+ * Returns POT_WARN_NOT_CONVERGED when max_iter is hit with err > tau. */
+POT_API int pot_sinkhorn_solve(pot_clouds *c, float eps, float tau, int32_t max_iter,
+                       const float *f_init, const float *g_init, float *f, float *g,
+                       pot_sinkhorn_info *info, void *stream);
+
+/* The entropic map of eq. Tent against the target cloud of c with potential
+ * g (device, m) at eps, followed by the McCann-type step:
+ *   Xout_i = (1 - alpha) Xq_i + alpha sum_j softmax_j((g_j - |Xq_i - y_j|^2)/eps) y_j
+ * Xq (device, nq*d) are arbitrary query points; Xout (device, nq*d) may alias
+ * Xq.  0 <= alpha <= 1.  nq == 0 is a no-op. */
+POT_API int pot_entropic_map(const pot_clouds *c, const float *g, float eps, const float *Xq,
+                     int64_t nq, float alpha, float *Xout, void *stream);
+
+typedef struct {
+    int32_t K;             /* number of Sinkhorn solves, 1..POT_MAX_K            */
+    int32_t alpha_sched;   /* 0 constant speed, 1 decelerated, 2 accelerated    */
+    int32_t eps_mode;      /* 0: eps_k = theta * meancost(X^(k), Y)/20 (App. C);
+                              1: eps_k = eps_explicit[k] (e.g. Alg. 4 output)   */
+    float theta;
+    const double *eps_explicit;  /* host, K values, eps_mode == 1 only          */
+    float tau_first, tau_last;   /* tau_k linear from first to last (Sec. 4)    */
+    int32_t max_iter;            /* per solve                                   */
+    int32_t warm_start;          /* 0: (1 - alpha_k) as in Alg. 2; 1: (1 - alpha_{k-1}) */
+} pot_progot_params;
+
+typedef struct {
+    int32_t K;
+    int32_t iters[POT_MAX_K];    /* Sinkhorn iterations of each solve           */
+    int32_t converged;           /* 1 if every solve met its tau                */
+    float eps[POT_MAX_K], alpha[POT_MAX_K], err[POT_MAX_K];
+    double seconds;
+} pot_progot_info;
+
+/* Alg. 2 ProgOT(a, X, b, Y, (eps_k, alpha_k, tau_k)_k).  Resets c->xk to X,
+ * then for k = 0..K-1: eps_k, warm start, Sinkhorn to tau_k, store g^(k) in
+ * G[k], and (k < K-1) move c->xk in place along the McCann-type step.  On
+ * return c->xk holds X^(K-1), the source of the returned coupling
+ * P = exp((f (+) g^(K-1) - C(X^(K-1), Y))/eps_{K-1}); c->mean_cost matches it.
+ *   f (device, n): the last solve's f.  G (device, K*m): g^(0..K-1).
+ *   TX (device, n*d) or NULL: X^(K) = T_{K-1}(X^(K-1)) (alpha_{K-1} = 1).
+ * The fitted map of Alg. 3 is (Y, G, info->eps, info->alpha). */
+POT_API int pot_progot_solve(pot_clouds *c, const pot_progot_params *p, float *f, float *G,
+                     float *TX, pot_progot_info *info, void *stream);
+
+/* Alg. 3 T_Prog[b, Y, (g^(k), eps_k, alpha_k)_k] at nq query points: y <- x,
+ * then y <- (1 - alpha_k) y + alpha_k T_k(y) for k = 0..K-1 with alpha_{K-1}
+ * reset to 1.  G (device, K*m); eps, alpha (host, K floats); Xq, Yout
+ * (device, nq*d), may alias. */
+POT_API int pot_progot_map(const pot_clouds *c, int32_t K, const float *G, const float *eps,
+                   const float *alpha, const float *Xq, int64_t nq, float *Yout, void *stream);
+
+/* Final check in FP64 on the current source iterate c->xk: with C_ij =
+ * |x_i - y_j|^2 evaluated in FP64 by direct differences,
+ *   out[0] = |P 1 - a|_1, out[1] = |P^T 1 - b|_1,
+ *   out[2] = <f, a> + <g, b> - eps sum_ij P_ij   (the dual of eq. entdual),
+ * the marginal criterion of the coupling experiments (Sec. 5.2).
+ * f (device, n), g (device, m); out (host, 3 doubles).  Blocks. */
+POT_API int pot_marginal_check(const pot_clouds *c, const float *f, const float *g, float eps,
+                       double *out, void *stream);
+
+/* Kernel timing, a tracing aid.  While enabled (process-wide), every launch
+ * of the fused cost + log-sum-exp kernel (the f- and g-update) and of the
+ * entropic-map kernel is bracketed by HIP timing events on the stream it is
+ * launched on.  pot_timing_enable(1) clears the counters; pot_timing_read
+ * waits for the recorded events and returns the summed kernel milliseconds
+ * and launch counts (any pointer may be NULL).  Calls are serialised by a
+ * mutex; timing adds two event records per launch. */
+POT_API int pot_timing_enable(int on);
+POT_API int pot_timing_read(double *lse_ms, int64_t *lse_launches, double *map_ms,
+                            int64_t *map_launches);
+
+/* Message for a pot_status code (static string). */
+POT_API const char *pot_status_string(int code);
+
+/* Library version, "major.minor.patch". */
+POT_API const char *pot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROGOT_H */

@@ -1,0 +1,440 @@
+// C ABI and host driver of the progressive entropic OT hot path (gfx950).
+//
+// The driver owns no device memory: every buffer is a view into the caller's
+// workspace, laid out by plan() from (n, m, d, precision).  Host-side state is
+// limited to a small per-thread pinned buffer for scalar read-backs.
+
+#include "../../include/progot.h"
+#include "progot_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+using pot::LseArgs;
+using pot::MapArgs;
+
+struct Layout {
+    size_t xk, xsq, ysq, la, lb, xlp, ylp, f0, f1, g0, g1, pm, ps, errp, errd, xst, yst, chr, chc;
+    size_t total;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t nm = (size_t)std::max(n, m);
+    L.xk = take((size_t)n * d * 4);
+    L.xsq = take((size_t)n * 4);
+    L.ysq = take((size_t)m * 4);
+    L.la = take((size_t)n * 4);
+    L.lb = take((size_t)m * 4);
+    const size_t lpx = precision == POT_PREC_BF16 ? (size_t)n * d * 2 : 0;
+    const size_t lpy = precision == POT_PREC_BF16 ? (size_t)m * d * 2 : 0;
+    L.xlp = take(lpx);
+    L.ylp = take(lpy);
+    L.f0 = take((size_t)n * 4);
+    L.f1 = take((size_t)n * 4);
+    L.g0 = take((size_t)m * 4);
+    L.g1 = take((size_t)m * 4);
+    L.pm = take((size_t)pot::kMaxSplit * nm * 4);
+    L.ps = take((size_t)pot::kMaxSplit * nm * 4);
+    L.errp = take(((nm + 255) / 256) * 4);
+    L.errd = take(64);
+    L.xst = take((size_t)pot::cloud_stat_blocks(n) * (d + 1) * 8);
+    L.yst = take((size_t)pot::cloud_stat_blocks(m) * (d + 1) * 8);
+    L.chr = take((size_t)pot::fp64_check_blocks(n) * 3 * 8);
+    L.chc = take((size_t)pot::fp64_check_blocks(m) * 3 * 8);
+    L.total = off;
+    return L;
+}
+
+template <typename T> T *at(const pot_clouds *c, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(c->ws) + off);
+}
+
+bool valid_sizes(int64_t n, int64_t m, int32_t d, int32_t precision) {
+    return n >= 1 && m >= 1 && d >= 1 && d <= POT_MAX_D &&
+           (precision == POT_PREC_FP32 || precision == POT_PREC_BF16) &&
+           n <= (int64_t(1) << 31) && m <= (int64_t(1) << 31);
+}
+
+bool valid_clouds(const pot_clouds *c) {
+    if (!c || !c->ws || !c->X || !c->Y || !c->xk) return false;
+    if (!valid_sizes(c->n, c->m, c->d, c->precision)) return false;
+    return c->ws_bytes >= plan(c->n, c->m, c->d, c->precision).total;
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
+
+#define POT_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return POT_ERR_DEVICE;          \
+    } while (0)
+
+// Per-thread pinned landing zone for scalar read-backs.
+struct Pinned {
+    float *buf = nullptr;
+    ~Pinned() { if (buf) (void)hipHostFree(buf); }
+};
+thread_local Pinned g_pinned;
+
+float *pinned_slot() {
+    if (!g_pinned.buf) {
+        if (hipHostMalloc(reinterpret_cast<void **>(&g_pinned.buf), 64 * sizeof(float),
+                          hipHostMallocDefault) != hipSuccess) {
+            g_pinned.buf = nullptr;
+        }
+    }
+    return g_pinned.buf;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// mean_ij |x_i - y_j|^2 from the FP64 first and second moments:
+// (1/n) sum |x|^2 + (1/m) sum |y|^2 - 2 xbar . ybar.
+int refresh_mean_cost(pot_clouds *c, const Layout &L, bool with_y, hipStream_t s) {
+    const int d = c->d;
+    const int nbx = pot::cloud_stat_blocks(c->n);
+    POT_TRY(pot::launch_cloud_prep(c->xk, c->n, d, c->x_sqn, c->x_lp, at<double>(c, L.xst), nbx, s));
+    if (with_y) {
+        const int nby = pot::cloud_stat_blocks(c->m);
+        POT_TRY(pot::launch_cloud_prep(c->Y, c->m, d, c->y_sqn, c->y_lp, at<double>(c, L.yst), nby, s));
+    }
+    std::vector<double> sx(d + 1), sy(d + 1);
+    POT_TRY(hipMemcpyAsync(sx.data(), at<double>(c, L.xst), (d + 1) * 8, hipMemcpyDeviceToHost, s));
+    POT_TRY(hipMemcpyAsync(sy.data(), at<double>(c, L.yst), (d + 1) * 8, hipMemcpyDeviceToHost, s));
+    POT_TRY(hipStreamSynchronize(s));
+    const double n = (double)c->n, m = (double)c->m;
+    double dot = 0.0;
+    for (int k = 0; k < d; ++k) dot += (sx[k] / n) * (sy[k] / m);
+    c->mean_cost = sx[d] / n + sy[d] / m - 2.0 * dot;
+    if (!std::isfinite(c->mean_cost)) return POT_ERR_NUMERIC;
+    return POT_OK;
+}
+
+LseArgs f_update_args(const pot_clouds *c, const Layout &L, float eps) {
+    LseArgs a{};
+    a.U = c->xk; a.U_lp = c->x_lp; a.nu = c->n; a.usq = c->x_sqn; a.logw = c->log_a;
+    a.V = c->Y; a.V_lp = c->y_lp; a.nv = c->m; a.vsq = c->y_sqn;
+    a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
+    a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = at<float>(c, L.errp);
+    return a;
+}
+
+LseArgs g_update_args(const pot_clouds *c, const Layout &L, float eps) {
+    LseArgs a{};
+    a.U = c->Y; a.U_lp = c->y_lp; a.nu = c->m; a.usq = c->y_sqn; a.logw = c->log_b;
+    a.V = c->xk; a.V_lp = c->x_lp; a.nv = c->n; a.vsq = c->x_sqn;
+    a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
+    a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = nullptr;
+    return a;
+}
+
+struct SinkResult {
+    int iters = 0;
+    float err = 0.f;
+    bool converged = false;
+    const float *f = nullptr, *g = nullptr;
+};
+
+// Enqueue err = sum of the error partials and its copy to the pinned slot.
+int enqueue_err_readback(const pot_clouds *c, const Layout &L, int nparts, float *host,
+                         hipEvent_t ev, hipStream_t s) {
+    float *dev = at<float>(c, L.errd);
+    POT_TRY(pot::launch_sum_f32(at<float>(c, L.errp), nparts, dev, s));
+    POT_TRY(hipMemcpyAsync(host, dev, sizeof(float), hipMemcpyDeviceToHost, s));
+    POT_TRY(hipEventRecord(ev, s));
+    return POT_OK;
+}
+
+// Alg. 1 on c->xk.  Iteration t: f_t from g_{t-1} (whose error partials are
+// the row-marginal error of iterate t-1), then g_t from f_t.  While g_t runs
+// the host reads err_{t-1}; the ping-pong buffers keep iterate t-1 intact
+// so it can be returned.
+int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, int max_iter,
+                  const float *g_init, float gamma, SinkResult *out, hipStream_t s) {
+    float *fb[2] = {at<float>(c, L.f0), at<float>(c, L.f1)};
+    float *gb[2] = {at<float>(c, L.g0), at<float>(c, L.g1)};
+    float *host = pinned_slot();
+    if (!host) return POT_ERR_DEVICE;
+    hipEvent_t ev;
+    POT_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    int status = POT_OK;
+    LseArgs fa = f_update_args(c, L, eps);
+    LseArgs ga = g_update_args(c, L, eps);
+    for (int t = 1;; ++t) {
+        fa.vpot = t == 1 ? g_init : gb[(t - 1) & 1];
+        fa.gamma = t == 1 ? gamma : 1.f;
+        fa.pot_old = t == 1 ? nullptr : fb[(t - 1) & 1];
+        fa.pot_out = fb[t & 1];
+        int nparts = 0;
+        if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) { status = POT_ERR_DEVICE; break; }
+        if (t > 1 && (status = enqueue_err_readback(c, L, nparts, host, ev, s)) != POT_OK) break;
+        ga.vpot = fb[t & 1];
+        ga.pot_out = gb[t & 1];
+        if (pot::launch_lse_update(ga, s, nullptr) != hipSuccess) { status = POT_ERR_DEVICE; break; }
+        if (t > 1) {
+            if (hipEventSynchronize(ev) != hipSuccess) { status = POT_ERR_DEVICE; break; }
+            const float err = *host;
+            if (!std::isfinite(err)) { status = POT_ERR_NUMERIC; break; }
+            if (tau > 0.f && err <= tau) {
+                out->iters = t - 1; out->err = err; out->converged = true;
+                out->f = fb[(t - 1) & 1]; out->g = gb[(t - 1) & 1];
+                break;
+            }
+        }
+        if (t == max_iter) {
+            // err of the last iterate: one more f-update into the spare buffer.
+            fa.vpot = gb[t & 1]; fa.gamma = 1.f;
+            fa.pot_old = fb[t & 1]; fa.pot_out = fb[(t + 1) & 1];
+            if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) { status = POT_ERR_DEVICE; break; }
+            if ((status = enqueue_err_readback(c, L, nparts, host, ev, s)) != POT_OK) break;
+            if (hipEventSynchronize(ev) != hipSuccess) { status = POT_ERR_DEVICE; break; }
+            const float err = *host;
+            if (!std::isfinite(err)) { status = POT_ERR_NUMERIC; break; }
+            out->iters = t; out->err = err;
+            out->converged = tau > 0.f ? err <= tau : true;
+            out->f = fb[t & 1]; out->g = gb[t & 1];
+            break;
+        }
+    }
+    (void)hipEventDestroy(ev);
+    return status;
+}
+
+void alpha_schedule(int K, int kind, float *alpha) {
+    for (int k = 0; k < K; ++k) {
+        double a;
+        if (kind == 1) {
+            a = 1.0 / std::exp(1.0);
+        } else {
+            const double tk = kind == 2 ? std::pow((double)k / K, 2.0) : (double)k / K;
+            const double t1 = kind == 2 ? std::pow((double)(k + 1) / K, 2.0) : (double)(k + 1) / K;
+            a = (t1 - tk) / (1.0 - tk);
+        }
+        alpha[k] = (float)a;
+    }
+    alpha[K - 1] = 1.f;
+}
+
+int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
+            float alpha, float *Xout, float *out_sqn, void *out_lp, hipStream_t s) {
+    MapArgs a{};
+    a.Xq = Xq; a.nq = nq; a.Y = c->Y; a.Y_lp = c->y_lp; a.m = c->m; a.ysq = c->y_sqn; a.g = g;
+    a.eps = eps; a.alpha = alpha; a.d = c->d; a.precision = c->precision;
+    a.Xout = Xout; a.out_sqn = out_sqn; a.out_lp = out_lp;
+    POT_TRY(pot::launch_entropic_map(a, s));
+    return POT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pot_status_string(int code) {
+    switch (code) {
+        case POT_OK: return "ok";
+        case POT_WARN_NOT_CONVERGED: return "not converged: max_iter reached with err > tau";
+        case POT_ERR_INVALID: return "invalid argument";
+        case POT_ERR_NOMEM: return "workspace too small";
+        case POT_ERR_NUMERIC: return "non-finite marginal error or mean cost";
+        case POT_ERR_DEVICE: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char *pot_version(void) { return "0.1.0"; }
+
+size_t pot_workspace_bytes(int64_t n, int64_t m, int32_t d, int32_t precision) {
+    if (!valid_sizes(n, m, d, precision)) return 0;
+    return plan(n, m, d, precision).total;
+}
+
+int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
+                       int32_t d, const float *a, const float *b, int32_t precision, void *ws,
+                       size_t ws_bytes, void *stream) {
+    if (!c || !X || !Y || !ws || !valid_sizes(n, m, d, precision)) return POT_ERR_INVALID;
+    const Layout L = plan(n, m, d, precision);
+    if (ws_bytes < L.total) return POT_ERR_NOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // Weights, when given, must be positive and sum to 1 within 1e-5.
+    for (int side = 0; side < 2; ++side) {
+        const float *w = side ? b : a;
+        const int64_t len = side ? m : n;
+        if (!w) continue;
+        std::vector<float> h(len);
+        POT_TRY(hipMemcpyAsync(h.data(), w, len * sizeof(float), hipMemcpyDeviceToHost, s));
+        POT_TRY(hipStreamSynchronize(s));
+        double tot = 0.0;
+        for (float v : h) {
+            if (!(v > 0.f) || !std::isfinite(v)) return POT_ERR_INVALID;
+            tot += v;
+        }
+        if (std::fabs(tot - 1.0) > 1e-5) return POT_ERR_INVALID;
+    }
+    std::memset(c, 0, sizeof(*c));
+    c->n = n; c->m = m; c->d = d; c->precision = precision;
+    c->X = X; c->Y = Y; c->a = a; c->b = b; c->ws = ws; c->ws_bytes = ws_bytes;
+    c->xk = at<float>(c, L.xk);
+    c->x_sqn = at<float>(c, L.xsq);
+    c->y_sqn = at<float>(c, L.ysq);
+    c->log_a = at<float>(c, L.la);
+    c->log_b = at<float>(c, L.lb);
+    c->x_lp = precision == POT_PREC_BF16 ? at<void>(c, L.xlp) : nullptr;
+    c->y_lp = precision == POT_PREC_BF16 ? at<void>(c, L.ylp) : nullptr;
+    POT_TRY(hipMemcpyAsync(c->xk, X, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, s));
+    POT_TRY(pot::launch_log_weights(a, n, c->log_a, s));
+    POT_TRY(pot::launch_log_weights(b, m, c->log_b, s));
+    return refresh_mean_cost(c, L, true, s);
+}
+
+int pot_sinkhorn_solve(pot_clouds *c, float eps, float tau, int32_t max_iter, const float *f_init,
+                       const float *g_init, float *f, float *g, pot_sinkhorn_info *info,
+                       void *stream) {
+    (void)f_init;  // the first f-update overwrites f (Alg. 1): f_init cannot matter
+    if (!valid_clouds(c) || !f || !g || !finite_pos(eps) || !(tau >= 0.f) || !std::isfinite(tau) ||
+        max_iter < 1)
+        return POT_ERR_INVALID;
+    const double t0 = now_s();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout L = plan(c->n, c->m, c->d, c->precision);
+    SinkResult r;
+    int st = sinkhorn_core(c, L, eps, tau, max_iter, g_init, 1.f, &r, s);
+    if (st != POT_OK) return st;
+    POT_TRY(hipMemcpyAsync(f, r.f, c->n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    POT_TRY(hipMemcpyAsync(g, r.g, c->m * sizeof(float), hipMemcpyDeviceToDevice, s));
+    POT_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->iters = r.iters; info->converged = r.converged ? 1 : 0; info->err = r.err;
+        info->seconds = now_s() - t0;
+    }
+    return r.converged ? POT_OK : POT_WARN_NOT_CONVERGED;
+}
+
+int pot_entropic_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
+                     float alpha, float *Xout, void *stream) {
+    if (!valid_clouds(c) || !g || !finite_pos(eps) || nq < 0 || !(alpha >= 0.f && alpha <= 1.f))
+        return POT_ERR_INVALID;
+    if (nq == 0) return POT_OK;
+    if (!Xq || !Xout || nq > (int64_t(1) << 31)) return POT_ERR_INVALID;
+    return run_map(c, g, eps, Xq, nq, alpha, Xout, nullptr, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int pot_progot_solve(pot_clouds *c, const pot_progot_params *p, float *f, float *G, float *TX,
+                     pot_progot_info *info, void *stream) {
+    if (!valid_clouds(c) || !p || !f || !G) return POT_ERR_INVALID;
+    if (p->K < 1 || p->K > POT_MAX_K || p->max_iter < 1 || p->alpha_sched < 0 || p->alpha_sched > 2)
+        return POT_ERR_INVALID;
+    if (p->eps_mode == 0) {
+        if (!finite_pos(p->theta)) return POT_ERR_INVALID;
+    } else if (p->eps_mode == 1) {
+        if (!p->eps_explicit) return POT_ERR_INVALID;
+        for (int k = 0; k < p->K; ++k)
+            if (!(p->eps_explicit[k] > 0.0) || !std::isfinite(p->eps_explicit[k])) return POT_ERR_INVALID;
+    } else {
+        return POT_ERR_INVALID;
+    }
+    if (!(p->tau_first >= 0.f) || !(p->tau_last >= 0.f) || !std::isfinite(p->tau_first) ||
+        !std::isfinite(p->tau_last))
+        return POT_ERR_INVALID;
+    const double t0 = now_s();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout L = plan(c->n, c->m, c->d, c->precision);
+    const int K = p->K;
+    const int64_t n = c->n, m = c->m;
+    float alpha[POT_MAX_K];
+    alpha_schedule(K, p->alpha_sched, alpha);
+
+    POT_TRY(hipMemcpyAsync(c->xk, c->X, (size_t)n * c->d * sizeof(float), hipMemcpyDeviceToDevice, s));
+    int st = refresh_mean_cost(c, L, false, s);
+    if (st != POT_OK) return st;
+
+    pot_progot_info loc{};
+    loc.K = K;
+    loc.converged = 1;
+    for (int k = 0; k < K; ++k) {
+        const float eps = p->eps_mode == 0 ? (float)(p->theta * c->mean_cost / 20.0)
+                                           : (float)p->eps_explicit[k];
+        if (!finite_pos(eps)) return POT_ERR_NUMERIC;
+        const float tau = K == 1 ? p->tau_last
+                                 : p->tau_first + (p->tau_last - p->tau_first) * (float)k / (float)(K - 1);
+        const float w = (p->warm_start == 0 || k == 0) ? alpha[k] : alpha[k - 1];
+        const float *g_init = k == 0 ? nullptr : G + (size_t)(k - 1) * m;
+        SinkResult r;
+        st = sinkhorn_core(c, L, eps, tau, p->max_iter, g_init, 1.f - w, &r, s);
+        if (st != POT_OK) return st;
+        POT_TRY(hipMemcpyAsync(G + (size_t)k * m, r.g, m * sizeof(float), hipMemcpyDeviceToDevice, s));
+        loc.iters[k] = r.iters; loc.err[k] = r.err; loc.eps[k] = eps; loc.alpha[k] = alpha[k];
+        if (!r.converged) loc.converged = 0;
+        if (k + 1 < K) {
+            st = run_map(c, G + (size_t)k * m, eps, c->xk, n, alpha[k], c->xk, nullptr, nullptr, s);
+            if (st != POT_OK) return st;
+            st = refresh_mean_cost(c, L, false, s);  // norms, BF16 copy and mean cost of X^(k+1)
+            if (st != POT_OK) return st;
+        } else {
+            POT_TRY(hipMemcpyAsync(f, r.f, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+            if (TX) {
+                st = run_map(c, G + (size_t)k * m, eps, c->xk, n, 1.f, TX, nullptr, nullptr, s);
+                if (st != POT_OK) return st;
+            }
+        }
+    }
+    POT_TRY(hipStreamSynchronize(s));
+    loc.seconds = now_s() - t0;
+    if (info) *info = loc;
+    return loc.converged ? POT_OK : POT_WARN_NOT_CONVERGED;
+}
+
+int pot_progot_map(const pot_clouds *c, int32_t K, const float *G, const float *eps,
+                   const float *alpha, const float *Xq, int64_t nq, float *Yout, void *stream) {
+    if (!valid_clouds(c) || K < 1 || K > POT_MAX_K || !G || !eps || !alpha || nq < 0)
+        return POT_ERR_INVALID;
+    for (int k = 0; k < K; ++k) {
+        if (!finite_pos(eps[k])) return POT_ERR_INVALID;
+        if (k + 1 < K && !(alpha[k] >= 0.f && alpha[k] <= 1.f)) return POT_ERR_INVALID;
+    }
+    if (nq == 0) return POT_OK;
+    if (!Xq || !Yout || nq > (int64_t(1) << 31)) return POT_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < K; ++k) {
+        const float a = k + 1 == K ? 1.f : alpha[k];
+        const int st = run_map(c, G + (size_t)k * c->m, eps[k], k == 0 ? Xq : Yout, nq, a, Yout,
+                               nullptr, nullptr, s);
+        if (st != POT_OK) return st;
+    }
+    return POT_OK;
+}
+
+int pot_marginal_check(const pot_clouds *c, const float *f, const float *g, float eps, double *out,
+                       void *stream) {
+    if (!valid_clouds(c) || !f || !g || !out || !finite_pos(eps)) return POT_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout L = plan(c->n, c->m, c->d, c->precision);
+    const int nbr = pot::fp64_check_blocks(c->n), nbc = pot::fp64_check_blocks(c->m);
+    POT_TRY(pot::launch_fp64_check(c->xk, c->n, c->Y, c->m, c->d, f, g, c->a, c->b, eps,
+                                   at<double>(c, L.chr), at<double>(c, L.chc), s));
+    std::vector<double> hr(3 * (size_t)nbr), hc(3 * (size_t)nbc);
+    POT_TRY(hipMemcpyAsync(hr.data(), at<double>(c, L.chr), hr.size() * 8, hipMemcpyDeviceToHost, s));
+    POT_TRY(hipMemcpyAsync(hc.data(), at<double>(c, L.chc), hc.size() * 8, hipMemcpyDeviceToHost, s));
+    POT_TRY(hipStreamSynchronize(s));
+    double row = 0, mass = 0, fa = 0, col = 0, gb = 0;
+    for (int b = 0; b < nbr; ++b) { row += hr[3 * b]; mass += hr[3 * b + 1]; fa += hr[3 * b + 2]; }
+    for (int b = 0; b < nbc; ++b) { col += hc[3 * b]; gb += hc[3 * b + 2]; }
+    out[0] = row;
+    out[1] = col;
+    out[2] = fa + gb - (double)eps * mass;
+    if (!std::isfinite(row) || !std::isfinite(col)) return POT_ERR_NUMERIC;
+    return POT_OK;
+}
+
+}  // extern "C"

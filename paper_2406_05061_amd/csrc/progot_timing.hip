@@ -1,0 +1,127 @@
+// Launch timing for the tracing aid of the C ABI (pot_timing_enable /
+// pot_timing_read): HIP timing events around kernel launches, resolved
+// lazily when read.
+
+#include "../../include/progot.h"
+#include "progot_internal.h"
+
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+struct Rec {
+    hipEvent_t start, stop;
+    int kind;
+};
+
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    int64_t next_id = 0;
+    std::unordered_map<int64_t, Rec> open;  // start recorded, stop pending
+    std::vector<Rec> live;                  // both recorded, not yet resolved
+    std::vector<hipEvent_t> pool;
+    double ms[2] = {0.0, 0.0};
+    int64_t count[2] = {0, 0};
+};
+
+Timing &T() {
+    static Timing t;
+    return t;
+}
+
+hipEvent_t take(Timing &t) {
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Fold finished records into the totals (caller holds the mutex).
+int resolve(Timing &t) {
+    int status = POT_OK;
+    for (Rec &r : t.live) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) != hipSuccess ||
+            hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+            status = POT_ERR_DEVICE;
+        } else {
+            t.ms[r.kind] += ms;
+            t.count[r.kind] += 1;
+        }
+        t.pool.push_back(r.start);
+        t.pool.push_back(r.stop);
+    }
+    t.live.clear();
+    return status;
+}
+
+}  // namespace
+
+namespace pot {
+
+int64_t timing_begin(int kind, hipStream_t s) {
+    Timing &t = T();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.on) return -1;
+    Rec r{take(t), take(t), kind};
+    if (!r.start || !r.stop || hipEventRecord(r.start, s) != hipSuccess) {
+        if (r.start) t.pool.push_back(r.start);
+        if (r.stop) t.pool.push_back(r.stop);
+        return -1;
+    }
+    const int64_t id = t.next_id++;
+    t.open.emplace(id, r);
+    return id;
+}
+
+void timing_end(int64_t slot, hipStream_t s) {
+    if (slot < 0) return;
+    Timing &t = T();
+    std::lock_guard<std::mutex> lk(t.mu);
+    auto it = t.open.find(slot);
+    if (it == t.open.end()) return;
+    Rec r = it->second;
+    t.open.erase(it);
+    if (hipEventRecord(r.stop, s) == hipSuccess) {
+        t.live.push_back(r);
+    } else {
+        t.pool.push_back(r.start);
+        t.pool.push_back(r.stop);
+    }
+}
+
+}  // namespace pot
+
+extern "C" {
+
+int pot_timing_enable(int on) {
+    Timing &t = T();
+    std::lock_guard<std::mutex> lk(t.mu);
+    int st = resolve(t);
+    if (on) {
+        t.ms[0] = t.ms[1] = 0.0;
+        t.count[0] = t.count[1] = 0;
+    }
+    t.on = on != 0;
+    return st;
+}
+
+int pot_timing_read(double *lse_ms, int64_t *lse_launches, double *map_ms, int64_t *map_launches) {
+    Timing &t = T();
+    std::lock_guard<std::mutex> lk(t.mu);
+    const int st = resolve(t);
+    if (lse_ms) *lse_ms = t.ms[0];
+    if (lse_launches) *lse_launches = t.count[0];
+    if (map_ms) *map_ms = t.ms[1];
+    if (map_launches) *map_launches = t.count[1];
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,330 @@
+"""Python binding of libprogot.so (the C ABI declared in include/progot.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+Tensors must be contiguous float32 CUDA (HIP) tensors on the current device;
+work is enqueued on torch's current stream.  PyTorch provides device memory
+and the stream handle, nothing else.  There is no CPU fallback: without the
+built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import re
+from dataclasses import dataclass
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libprogot.so"
+HEADER = _PKG.parent / "include" / "progot.h"
+
+POT_OK = 0
+POT_WARN_NOT_CONVERGED = 1
+POT_ERR_INVALID = -1
+POT_ERR_NOMEM = -2
+POT_ERR_NUMERIC = -3
+POT_ERR_DEVICE = -4
+PREC = {"fp32": 0, "bf16": 1}
+ALPHA_SCHED = {"constant": 0, "decelerated": 1, "accelerated": 2}
+MAX_K = 64
+
+
+class PotError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} ({code})")
+
+
+class pot_clouds(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("m", C.c_int64), ("d", C.c_int32), ("precision", C.c_int32),
+        ("X", C.c_void_p), ("Y", C.c_void_p), ("a", C.c_void_p), ("b", C.c_void_p),
+        ("xk", C.c_void_p),
+        ("x_sqn", C.c_void_p), ("y_sqn", C.c_void_p),
+        ("log_a", C.c_void_p), ("log_b", C.c_void_p),
+        ("x_lp", C.c_void_p), ("y_lp", C.c_void_p),
+        ("mean_cost", C.c_double), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
+    ]
+
+
+class pot_sinkhorn_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("err", C.c_float),
+                ("seconds", C.c_double)]
+
+
+class pot_progot_params(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32), ("alpha_sched", C.c_int32), ("eps_mode", C.c_int32),
+        ("theta", C.c_float), ("eps_explicit", C.POINTER(C.c_double)),
+        ("tau_first", C.c_float), ("tau_last", C.c_float), ("max_iter", C.c_int32),
+        ("warm_start", C.c_int32),
+    ]
+
+
+class pot_progot_info(C.Structure):
+    _fields_ = [
+        ("K", C.c_int32), ("iters", C.c_int32 * MAX_K), ("converged", C.c_int32),
+        ("eps", C.c_float * MAX_K), ("alpha", C.c_float * MAX_K), ("err", C.c_float * MAX_K),
+        ("seconds", C.c_double),
+    ]
+
+
+_lib = None
+_vp, _i64, _i32, _f32 = C.c_void_p, C.c_int64, C.c_int32, C.c_float
+_SIGS = {
+    "pot_workspace_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32]),
+    "pot_prepare_clouds": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _vp, _i64, _i32, _vp, _vp,
+                                     _i32, _vp, C.c_size_t, _vp]),
+    "pot_sinkhorn_solve": (C.c_int, [C.POINTER(pot_clouds), _f32, _f32, _i32, _vp, _vp, _vp, _vp,
+                                     C.POINTER(pot_sinkhorn_info), _vp]),
+    "pot_entropic_map": (C.c_int, [C.POINTER(pot_clouds), _vp, _f32, _vp, _i64, _f32, _vp, _vp]),
+    "pot_progot_solve": (C.c_int, [C.POINTER(pot_clouds), C.POINTER(pot_progot_params), _vp, _vp,
+                                   _vp, C.POINTER(pot_progot_info), _vp]),
+    "pot_progot_map": (C.c_int, [C.POINTER(pot_clouds), _i32, _vp, C.POINTER(C.c_float),
+                                 C.POINTER(C.c_float), _vp, _i64, _vp, _vp]),
+    "pot_marginal_check": (C.c_int, [C.POINTER(pot_clouds), _vp, _vp, _f32, C.POINTER(C.c_double),
+                                     _vp]),
+    "pot_timing_enable": (C.c_int, [C.c_int]),
+    "pot_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "pot_status_string": (C.c_char_p, [C.c_int]),
+    "pot_version": (C.c_char_p, []),
+}
+
+
+def lib() -> C.CDLL:
+    """Load libprogot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2406_05061_amd.build`")
+        L = C.CDLL(str(LIB_PATH))
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/progot.h."""
+    txt = HEADER.read_text()
+    return sorted(set(re.findall(r"^POT_API\s+[\w\s\*]*?\b(pot_\w+)\s*\(", txt, flags=re.M)))
+
+
+def status_string(code: int) -> str:
+    return lib().pot_status_string(int(code)).decode()
+
+
+def version() -> str:
+    return lib().pot_version().decode()
+
+
+def workspace_bytes(n: int, m: int, d: int, precision: str = "fp32") -> int:
+    return int(lib().pot_workspace_bytes(n, m, d, PREC[precision]))
+
+
+def _check(code: int, where: str, allow_warn: bool = True) -> int:
+    if code < 0 or (code > 0 and not allow_warn):
+        raise PotError(code, where)
+    return code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def _dev_f32(t, name: str, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Clouds:
+    """A prepared pair of clouds: inputs, workspace and the pot_clouds POD.
+    Keeps references to every tensor the library points into."""
+
+    def __init__(self, X, Y, a=None, b=None, precision: str = "fp32"):
+        torch = _torch()
+        _dev_f32(X, "X")
+        _dev_f32(Y, "Y")
+        if X.dim() != 2 or Y.dim() != 2 or X.shape[1] != Y.shape[1]:
+            raise ValueError("X (n x d) and Y (m x d) must share d")
+        n, d = X.shape
+        m = Y.shape[0]
+        if a is not None:
+            _dev_f32(a, "a", (n,))
+        if b is not None:
+            _dev_f32(b, "b", (m,))
+        nbytes = workspace_bytes(n, m, d, precision)
+        if nbytes == 0:
+            raise PotError(POT_ERR_INVALID, "workspace_bytes")
+        self.X, self.Y, self.a, self.b = X, Y, a, b
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+        self.c = pot_clouds()
+        self.n, self.m, self.d, self.precision = n, m, d, precision
+        _check(lib().pot_prepare_clouds(C.byref(self.c), _ptr(X), n, _ptr(Y), m, d, _ptr(a),
+                                        _ptr(b), PREC[precision], _ptr(self.ws), nbytes,
+                                        C.c_void_p(_stream())), "prepare_clouds", False)
+
+    @property
+    def mean_cost(self) -> float:
+        return float(self.c.mean_cost)
+
+    def xk(self):
+        """A copy of the current source iterate X^(k) (n x d), taken on the
+        current stream after the library's work."""
+        torch = _torch()
+        off = self.c.xk - self.ws.data_ptr()
+        nbytes = self.n * self.d * 4
+        return self.ws[off:off + nbytes].view(torch.float32).view(self.n, self.d).clone()
+
+
+def prepare_clouds(X, Y, a=None, b=None, precision: str = "fp32") -> Clouds:
+    return Clouds(X, Y, a, b, precision)
+
+
+@dataclass
+class SinkhornInfo:
+    iters: int
+    converged: bool
+    err: float
+    seconds: float
+    status: int
+
+
+def sinkhorn_solve(cl: Clouds, eps: float, tau: float, max_iter: int = 10_000,
+                   f_init=None, g_init=None, f=None, g=None):
+    """Alg. 1 on the current source iterate; returns (f, g, SinkhornInfo)."""
+    torch = _torch()
+    dev = cl.X.device
+    f = torch.empty(cl.n, dtype=torch.float32, device=dev) if f is None else _dev_f32(f, "f", (cl.n,))
+    g = torch.empty(cl.m, dtype=torch.float32, device=dev) if g is None else _dev_f32(g, "g", (cl.m,))
+    if f_init is not None:
+        _dev_f32(f_init, "f_init", (cl.n,))
+    if g_init is not None:
+        _dev_f32(g_init, "g_init", (cl.m,))
+    info = pot_sinkhorn_info()
+    st = _check(lib().pot_sinkhorn_solve(C.byref(cl.c), float(eps), float(tau), int(max_iter),
+                                         _ptr(f_init), _ptr(g_init), _ptr(f), _ptr(g),
+                                         C.byref(info), C.c_void_p(_stream())), "sinkhorn_solve")
+    return f, g, SinkhornInfo(info.iters, bool(info.converged), float(info.err), info.seconds, st)
+
+
+def entropic_map(cl: Clouds, g, eps: float, Xq, alpha: float = 1.0, out=None):
+    """(1 - alpha) Xq + alpha T(Xq) with T the entropic map to cl.Y (eq. Tent)."""
+    torch = _torch()
+    _dev_f32(g, "g", (cl.m,))
+    _dev_f32(Xq, "Xq")
+    if Xq.dim() != 2 or Xq.shape[1] != cl.d:
+        raise ValueError("Xq must be nq x d")
+    out = torch.empty_like(Xq) if out is None else _dev_f32(out, "out", tuple(Xq.shape))
+    _check(lib().pot_entropic_map(C.byref(cl.c), _ptr(g), float(eps), _ptr(Xq), Xq.shape[0],
+                                  float(alpha), _ptr(out), C.c_void_p(_stream())), "entropic_map",
+           False)
+    return out
+
+
+@dataclass
+class ProgOTInfo:
+    K: int
+    iters: list
+    converged: bool
+    eps: list
+    alpha: list
+    err: list
+    seconds: float
+    status: int
+
+
+def progot_solve(cl: Clouds, K: int, *, alpha_sched: str = "constant", theta: float = 1.0,
+                 eps=None, tau_first: float = 1e-3, tau_last: float = 1e-3,
+                 max_iter: int = 10_000, warm_start: str = "alpha_k", want_TX: bool = True):
+    """Alg. 2; returns (f, G, TX or None, ProgOTInfo).  eps=None uses the
+    per-step mean-cost rule with theta; an array gives an explicit schedule."""
+    torch = _torch()
+    dev = cl.X.device
+    p = pot_progot_params()
+    p.K = int(K)
+    p.alpha_sched = ALPHA_SCHED[alpha_sched]
+    keep = None
+    if eps is None:
+        p.eps_mode, p.theta = 0, float(theta)
+    else:
+        keep = (C.c_double * int(K))(*[float(e) for e in eps])
+        p.eps_mode, p.theta, p.eps_explicit = 1, float(theta), C.cast(keep, C.POINTER(C.c_double))
+    p.tau_first, p.tau_last = float(tau_first), float(tau_last)
+    p.max_iter = int(max_iter)
+    p.warm_start = 0 if warm_start == "alpha_k" else 1
+    f = torch.empty(cl.n, dtype=torch.float32, device=dev)
+    G = torch.empty((K, cl.m), dtype=torch.float32, device=dev)
+    TX = torch.empty((cl.n, cl.d), dtype=torch.float32, device=dev) if want_TX else None
+    info = pot_progot_info()
+    st = _check(lib().pot_progot_solve(C.byref(cl.c), C.byref(p), _ptr(f), _ptr(G), _ptr(TX),
+                                       C.byref(info), C.c_void_p(_stream())), "progot_solve")
+    del keep
+    k = info.K
+    return f, G, TX, ProgOTInfo(k, list(info.iters[:k]), bool(info.converged), list(info.eps[:k]),
+                                list(info.alpha[:k]), list(info.err[:k]), info.seconds, st)
+
+
+def progot_map(cl: Clouds, G, eps, alpha, Xq, out=None):
+    """Alg. 3 T_Prog at the rows of Xq (last alpha reset to 1)."""
+    torch = _torch()
+    K = len(eps)
+    _dev_f32(G, "G", (K, cl.m))
+    _dev_f32(Xq, "Xq")
+    out = torch.empty_like(Xq) if out is None else _dev_f32(out, "out", tuple(Xq.shape))
+    e = (C.c_float * K)(*[float(x) for x in eps])
+    a = (C.c_float * K)(*[float(x) for x in alpha])
+    _check(lib().pot_progot_map(C.byref(cl.c), K, _ptr(G), e, a, _ptr(Xq), Xq.shape[0], _ptr(out),
+                                C.c_void_p(_stream())), "progot_map", False)
+    return out
+
+
+def marginal_check(cl: Clouds, f, g, eps: float):
+    """FP64 (row L1, column L1, dual objective) of the coupling of (f, g) on
+    the current source iterate."""
+    _dev_f32(f, "f", (cl.n,))
+    _dev_f32(g, "g", (cl.m,))
+    out = (C.c_double * 3)()
+    _check(lib().pot_marginal_check(C.byref(cl.c), _ptr(f), _ptr(g), float(eps), out,
+                                    C.c_void_p(_stream())), "marginal_check", False)
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def timing_enable(on: bool = True) -> None:
+    """Start (and clear) or stop the library's per-launch kernel timing."""
+    _check(lib().pot_timing_enable(1 if on else 0), "timing_enable", False)
+
+
+def timing_read():
+    """(lse_ms, lse_launches, map_ms, map_launches) summed over the timed
+    launches; waits for the recorded events."""
+    a, b = C.c_double(), C.c_int64()
+    c, d = C.c_double(), C.c_int64()
+    _check(lib().pot_timing_read(C.byref(a), C.byref(b), C.byref(c), C.byref(d)), "timing_read",
+           False)
+    return a.value, b.value, c.value, d.value
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)

@@ -1,0 +1,117 @@
+"""The C ABI library without a GPU: it loads, exports every symbol the header
+declares, sizes workspaces, and rejects invalid arguments before any HIP
+call (no compute runs here)."""
+import ctypes as C
+
+import pytest
+
+import paper_2406_05061_amd as P
+from paper_2406_05061_amd import progot as B
+
+
+def test_library_exports_header_symbols():
+    syms = P.header_symbols()
+    assert {"pot_prepare_clouds", "pot_sinkhorn_solve", "pot_entropic_map", "pot_progot_solve",
+            "pot_progot_map", "pot_marginal_check", "pot_workspace_bytes"} <= set(syms)
+    lib = P.lib()
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert P.version().count(".") == 2
+
+
+def test_status_strings():
+    assert P.status_string(0) == "ok"
+    for code in (1, -1, -2, -3, -4):
+        assert P.status_string(code) not in ("ok", "unknown status")
+    assert P.status_string(99) == "unknown status"
+
+
+def test_workspace_bytes():
+    assert P.workspace_bytes(0, 10, 4) == 0
+    assert P.workspace_bytes(10, 0, 4) == 0
+    assert P.workspace_bytes(10, 10, 0) == 0
+    assert P.workspace_bytes(10, 10, 257) == 0
+    w32 = P.workspace_bytes(1000, 700, 64, "fp32")
+    w16 = P.workspace_bytes(1000, 700, 64, "bf16")
+    assert w32 > 1000 * 64 * 4 and w16 > w32
+    assert w32 % 256 == 0
+    # grows with every size
+    assert P.workspace_bytes(2000, 700, 64) > w32
+    assert P.workspace_bytes(1000, 1400, 64) > w32
+
+
+def _fake_clouds(n=8, m=8, d=4, ws_bytes=None):
+    c = B.pot_clouds()
+    c.n, c.m, c.d, c.precision = n, m, d, 0
+    c.X = c.Y = c.xk = 0x1000
+    c.ws = 0x2000
+    c.ws_bytes = P.workspace_bytes(n, m, d) if ws_bytes is None else ws_bytes
+    return c
+
+
+def test_prepare_rejects_invalid_before_launch():
+    lib = P.lib()
+    c = B.pot_clouds()
+    nb = P.workspace_bytes(8, 8, 4)
+    inv = B.POT_ERR_INVALID
+    # null inputs / workspace, bad sizes, bad precision
+    assert lib.pot_prepare_clouds(C.byref(c), None, 8, 0x1000, 8, 4, None, None, 0, 0x2000, nb, None) == inv
+    assert lib.pot_prepare_clouds(C.byref(c), 0x1000, 8, None, 8, 4, None, None, 0, 0x2000, nb, None) == inv
+    assert lib.pot_prepare_clouds(C.byref(c), 0x1000, 8, 0x1000, 8, 4, None, None, 0, None, nb, None) == inv
+    assert lib.pot_prepare_clouds(C.byref(c), 0x1000, 0, 0x1000, 8, 4, None, None, 0, 0x2000, nb, None) == inv
+    assert lib.pot_prepare_clouds(C.byref(c), 0x1000, 8, 0x1000, 8, 300, None, None, 0, 0x2000, nb, None) == inv
+    assert lib.pot_prepare_clouds(C.byref(c), 0x1000, 8, 0x1000, 8, 4, None, None, 7, 0x2000, nb, None) == inv
+    assert lib.pot_prepare_clouds(None, 0x1000, 8, 0x1000, 8, 4, None, None, 0, 0x2000, nb, None) == inv
+    # workspace too small
+    assert lib.pot_prepare_clouds(C.byref(c), 0x1000, 8, 0x1000, 8, 4, None, None, 0, 0x2000, nb - 1,
+                                  None) == B.POT_ERR_NOMEM
+
+
+def test_solvers_reject_invalid_before_launch():
+    lib = P.lib()
+    inv = B.POT_ERR_INVALID
+    c = _fake_clouds()
+    info = B.pot_sinkhorn_info()
+    f = g = 0x3000
+    # eps <= 0, nan, tau < 0, max_iter < 1, null outputs, undersized workspace
+    assert lib.pot_sinkhorn_solve(C.byref(c), 0.0, 1e-3, 10, None, None, f, g, C.byref(info), None) == inv
+    assert lib.pot_sinkhorn_solve(C.byref(c), float("nan"), 1e-3, 10, None, None, f, g, None, None) == inv
+    assert lib.pot_sinkhorn_solve(C.byref(c), 1.0, -1.0, 10, None, None, f, g, None, None) == inv
+    assert lib.pot_sinkhorn_solve(C.byref(c), 1.0, 1e-3, 0, None, None, f, g, None, None) == inv
+    assert lib.pot_sinkhorn_solve(C.byref(c), 1.0, 1e-3, 10, None, None, None, g, None, None) == inv
+    assert lib.pot_sinkhorn_solve(None, 1.0, 1e-3, 10, None, None, f, g, None, None) == inv
+    small = _fake_clouds(ws_bytes=16)
+    assert lib.pot_sinkhorn_solve(C.byref(small), 1.0, 1e-3, 10, None, None, f, g, None, None) == inv
+    # entropic map: alpha out of [0, 1], eps <= 0, null query with nq > 0
+    assert lib.pot_entropic_map(C.byref(c), g, 1.0, f, 4, 1.5, f, None) == inv
+    assert lib.pot_entropic_map(C.byref(c), g, -1.0, f, 4, 0.5, f, None) == inv
+    assert lib.pot_entropic_map(C.byref(c), g, 1.0, None, 4, 0.5, f, None) == inv
+    assert lib.pot_entropic_map(C.byref(c), g, 1.0, None, 0, 0.5, None, None) == B.POT_OK
+    # progot: K out of range, bad schedules
+    p = B.pot_progot_params()
+    p.K, p.alpha_sched, p.eps_mode, p.theta = 0, 0, 0, 1.0
+    p.tau_first = p.tau_last = 1e-3
+    p.max_iter = 100
+    pi = B.pot_progot_info()
+    assert lib.pot_progot_solve(C.byref(c), C.byref(p), f, g, None, C.byref(pi), None) == inv
+    p.K = 65
+    assert lib.pot_progot_solve(C.byref(c), C.byref(p), f, g, None, C.byref(pi), None) == inv
+    p.K, p.theta = 4, 0.0
+    assert lib.pot_progot_solve(C.byref(c), C.byref(p), f, g, None, C.byref(pi), None) == inv
+    p.theta, p.eps_mode = 1.0, 1  # explicit schedule without values
+    assert lib.pot_progot_solve(C.byref(c), C.byref(p), f, g, None, C.byref(pi), None) == inv
+    p.eps_mode, p.alpha_sched = 0, 3
+    assert lib.pot_progot_solve(C.byref(c), C.byref(p), f, g, None, C.byref(pi), None) == inv
+    eps = (C.c_float * 2)(1.0, -1.0)
+    al = (C.c_float * 2)(0.5, 1.0)
+    assert lib.pot_progot_map(C.byref(c), 2, g, eps, al, f, 4, f, None) == inv
+    out = (C.c_double * 3)()
+    assert lib.pot_marginal_check(C.byref(c), f, g, 0.0, out, None) == inv
+    assert lib.pot_marginal_check(C.byref(c), None, g, 1.0, out, None) == inv
+
+
+def test_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    X = torch.zeros(4, 2)
+    with pytest.raises(TypeError):
+        P.prepare_clouds(X, X)

@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded FP32 inputs.  Bars: potentials 1e-4 relative (max |df| /
+max(|f|_inf, eps)), map outputs 1e-3 relative, marginal L1 1e-3 after
+convergence."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.sinkhorn import cost_matrix
+import workloads
+from tests.parity import pot_err, gauge_pot_err, map_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2406_05061_amd as P
+    P.lib()
+    return P
+
+
+def _weights(n, weighted, seed):
+    if not weighted:
+        return None, np.full(n, 1.0 / n)
+    w = workloads.weights(n, seed=seed)
+    return w, w.astype(np.float64)
+
+
+SHAPES = [
+    (256, 256, 4),      # C1-like dimension
+    (1000, 777, 16),    # ragged rows and columns
+    (2048, 1500, 64),   # several tiles, ragged tail
+    (300, 513, 100),    # d padded to 128
+    (64, 2000, 256),    # largest d, few rows (split columns)
+    (1, 5, 3),          # degenerate sizes
+    (7, 1, 3),
+]
+
+
+@pytest.mark.parametrize("n,m,d", SHAPES)
+@pytest.mark.parametrize("weighted", [False, True])
+def test_sinkhorn_fixed_iterations(P, n, m, d, weighted):
+    X, Y = workloads.gmm(seed=100 + n + d, n=n, m=m, d=d, n_comp=3)
+    wa, a = _weights(n, weighted, 1)
+    wb, b = _weights(m, weighted, 2)
+    eps = float(np.float32(0.05 * oracle.mean_cost(X, Y)))
+    print(f"case n={n} m={m} d={d} weighted={weighted} eps={eps:.4g}", flush=True)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y),
+                          None if wa is None else P.to_device(wa),
+                          None if wb is None else P.to_device(wb))
+    assert abs(cl.mean_cost / oracle.mean_cost(X, Y) - 1) < 1e-6
+    for it in (1, 13):
+        f, g, info = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=it)
+        ref = oracle.sinkhorn(a, X, b, Y, eps, 0.0, n_iter=it)
+        assert info.iters == it and info.status == 0
+        ef = pot_err(f.cpu().numpy(), ref.f, eps)
+        eg = pot_err(g.cpu().numpy(), ref.g, eps)
+        assert ef < 1e-4 and eg < 1e-4, (it, ef, eg)
+        assert abs(info.err - ref.err) <= 1e-5 + 2e-3 * ref.err, (info.err, ref.err)
+
+
+@pytest.mark.parametrize("n,m,d,gen", [(1024, 1024, 4, "c1"), (2000, 1800, 16, "gmm"),
+                                       (1500, 1200, 64, "sphere")])
+def test_sinkhorn_converged(P, n, m, d, gen):
+    if gen == "c1":
+        X, Y = workloads.c1(seed=1, n=n, m=m, d=d)
+    elif gen == "gmm":
+        X, Y = workloads.gmm(seed=5, n=n, m=m, d=d)
+    else:
+        X, Y = workloads.sphere(seed=6, n=n, m=m, d=d, n_clusters=8)
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    eps = float(np.float32(oracle.mean_cost(X, Y) / 20.0))   # the value the GPU receives
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y))
+    f, g, info = P.sinkhorn_solve(cl, eps, tau=1e-3)
+    print(f"case {gen} n={n} m={m} d={d}: gpu iters {info.iters} err {info.err:.3e}", flush=True)
+    assert info.converged and info.err <= 1e-3
+    ref = oracle.sinkhorn(a, X, b, Y, eps, 1e-3)
+    assert abs(info.iters - ref.iters) <= 1, (info.iters, ref.iters)
+    same = oracle.sinkhorn(a, X, b, Y, eps, 0.0, n_iter=info.iters)
+    fg, gg = f.cpu().numpy(), g.cpu().numpy()
+    assert pot_err(fg, same.f, eps) < 1e-4 and pot_err(gg, same.g, eps) < 1e-4
+    C = cost_matrix(X, Y)
+    row, col = oracle.marginal_errors(fg, gg, C, eps, a, b)
+    assert row <= 1e-3 * 1.01 and col <= 1e-4
+    chk = P.marginal_check(cl, f, g, eps)
+    assert abs(chk[0] - row) <= 1e-9 + 1e-6 * row
+    assert abs(chk[1] - col) <= 1e-9 + 1e-6 * max(col, 1e-6)
+    dual = oracle.dual_objective(fg, gg, C, eps, a, b)
+    assert abs(chk[2] - dual) <= 1e-9 * max(1.0, abs(dual)) + 1e-7 * abs(dual)
+
+
+@pytest.mark.parametrize("nq,m,d,alpha", [(700, 900, 4, 1.0), (513, 1000, 64, 0.3),
+                                          (100, 3000, 128, 0.7), (64, 257, 256, 1.0),
+                                          (1, 33, 5, 1.0)])
+def test_entropic_map(P, nq, m, d, alpha):
+    X, Y = workloads.gmm(seed=40 + d, n=nq, m=m, d=d, n_comp=4)
+    Q = workloads.gmm(seed=41 + d, n=nq, m=4, d=d, n_comp=4)[0]
+    b = np.full(m, 1.0 / m)
+    a = np.full(nq, 1.0 / nq)
+    eps = float(np.float32(0.05 * oracle.mean_cost(X, Y)))
+    ref_s = oracle.sinkhorn(a, X, b, Y, eps, 1e-6)
+    g32 = ref_s.g.astype(np.float32)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y))
+    out = P.entropic_map(cl, P.to_device(g32), eps, P.to_device(Q), alpha=alpha)
+    ref = oracle.entropic_map(Q, Y, g32, eps, alpha=alpha)
+    e = map_err(out.cpu().numpy(), ref, Y)
+    print(f"case nq={nq} m={m} d={d} alpha={alpha}: map err {e:.2e}", flush=True)
+    assert e < 1e-4
+    # in place (Xout aliases Xq)
+    Qd = P.to_device(Q)
+    P.entropic_map(cl, P.to_device(g32), eps, Qd, alpha=alpha, out=Qd)
+    assert map_err(Qd.cpu().numpy(), ref, Y) < 1e-4
+
+
+@pytest.mark.parametrize("eps_mode", ["mean_cost", "alg4"])
+def test_progot_c1(P, eps_mode):
+    """The small ProgOT workload: n = m = 1024, d = 4, K = 4, constant speed,
+    tau 1e-3; the eps schedule per step (mean cost / 20) or from Alg. 4
+    computed by the oracle and passed as an explicit array."""
+    X, Y = workloads.c1(seed=1)
+    n, m = X.shape[0], Y.shape[0]
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    K, tau = 4, 1e-3
+    if eps_mode == "alg4":
+        Yt = workloads.c1(seed=101)[1]
+        eps_sched, _ = oracle.schedules.eps_scheduler(
+            a, X, b, Y, oracle.schedules.alpha_schedule(K), Yt, beta0=5.0, tau=tau)
+        eps_arg = eps_sched.astype(np.float32).astype(np.float64)
+    else:
+        eps_arg = None
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y))
+    f, G, TX, info = P.progot_solve(cl, K, eps=eps_arg, tau_first=tau, tau_last=tau)
+    ref = oracle.progot(a, X, b, Y, K, eps=eps_arg, tau=tau)
+    print(f"case {eps_mode}: gpu iters {info.iters} oracle {ref.iters}", flush=True)
+    assert info.converged
+    np.testing.assert_allclose(info.eps, ref.eps, rtol=1e-4)
+    np.testing.assert_allclose(info.alpha, ref.alpha, rtol=1e-6)
+    assert all(abs(p - q) <= 2 for p, q in zip(info.iters, ref.iters))
+    # the map trajectory: tau-stopped iterates differ by O(eps tau) at most
+    assert map_err(TX.cpu().numpy(), ref.TX, Y) < 1e-3
+    # final coupling: marginals on the GPU's X^(K-1) in FP64
+    chk = P.marginal_check(cl, f, G[-1], info.eps[-1])
+    assert chk[0] <= tau * 1.01 and chk[1] <= 1e-4
+    # T_Prog at fresh queries with the GPU-fitted map state vs the oracle's Alg. 3
+    Q = workloads.c1(seed=77, n=500, m=4)[0]
+    out = P.progot_map(cl, G, info.eps, info.alpha, P.to_device(Q))
+    refq = oracle.progot_map(Q, Y, G.cpu().numpy().astype(np.float64), info.eps, info.alpha)
+    assert map_err(out.cpu().numpy(), refq, Y) < 1e-4
+    # Alg. 3 at the training points reproduces Alg. 2's endpoint
+    tx2 = P.progot_map(cl, G, info.eps, info.alpha, P.to_device(X))
+    assert map_err(tx2.cpu().numpy(), TX.cpu().numpy(), Y) < 1e-5
+
+
+def test_not_converged_warning(P):
+    X, Y = workloads.gmm(seed=9, n=300, m=300, d=8)
+    eps = 0.01 * oracle.mean_cost(X, Y)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y))
+    f, g, info = P.sinkhorn_solve(cl, eps, tau=1e-9, max_iter=3)
+    assert info.status == 1 and not info.converged and info.iters == 3
+    ref = oracle.sinkhorn(np.full(300, 1 / 300), X, np.full(300, 1 / 300), Y, eps, 0.0, n_iter=3)
+    assert pot_err(f.cpu().numpy(), ref.f, eps) < 1e-4
+
+
+def test_deterministic(P):
+    X, Y = workloads.gmm(seed=10, n=3000, m=2500, d=64)
+    eps = 0.05 * oracle.mean_cost(X, Y)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y))
+    f1, g1, _ = P.sinkhorn_solve(cl, eps, tau=1e-3)
+    f2, g2, _ = P.sinkhorn_solve(cl, eps, tau=1e-3)
+    assert torch.equal(f1, f2) and torch.equal(g1, g2)
+
+
+def test_translation_invariance_gpu(P):
+    """Shifting both clouds by the same vector leaves the potentials unchanged
+    and shifts the map (up to the FP32 rounding of the expanded cost)."""
+    X, Y = workloads.gmm(seed=11, n=800, m=600, d=16)
+    v = np.linspace(-0.5, 0.5, 16).astype(np.float32)
+    eps = 0.05 * oracle.mean_cost(X, Y)
+    outs = []
+    for sh in (0.0, 1.0):
+        cl = P.prepare_clouds(P.to_device(X + sh * v), P.to_device(Y + sh * v))
+        f, g, _ = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=20)
+        T = P.entropic_map(cl, g, eps, P.to_device(X + sh * v))
+        outs.append((f.cpu().numpy(), g.cpu().numpy(), T.cpu().numpy() - sh * v))
+    assert pot_err(outs[1][0], outs[0][0], eps) < 1e-4
+    assert pot_err(outs[1][1], outs[0][1], eps) < 1e-4
+    assert map_err(outs[1][2], outs[0][2], Y) < 1e-4

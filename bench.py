@@ -31,6 +31,8 @@ import workloads  # noqa: E402
 
 METRIC = "ProgOT solve time @ marginal err 1e-3; n·m·iters/s; serve p50/p99 latency"
 PEAK = {"fp32": 157.3, "bf16": 2500.0}   # TFLOP/s, dense MFMA, MI355X
+PAD = {16: 16, 64: 64, 128: 128, 256: 256}  # template dimension of the kernel per d
+QB = {16: 2, 64: 2, 128: 2, 256: 1}
 
 WORKLOADS = {
     # name: (generator kwargs, K, precision)
@@ -50,6 +52,21 @@ def make_clouds(spec):
     if kind == "sphere":
         return workloads.sphere(**kw)
     raise ValueError(kind)
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc record, or None
+    when there is none or the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2406_05061_amd", "csrc", "progot_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("kernel_sha256_16") != sha or rec.get("workload") != workload:
+        return None
+    return float(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
 
 
 def cpu_baseline(X, Y, n_sample: int, max_iter: int):
@@ -84,6 +101,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times), to scale "
+                         "hardware byte counters, and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -96,6 +116,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {nbytes} bytes 3 times")
+        return
     spec, K, prec = WORKLOADS[args.workload]
     X, Y = make_clouds(spec)
     n, d = X.shape
@@ -154,7 +183,9 @@ def main():
         "sinkhorn_iters_per_solve": infos[-1].iters,
         "final_marginal_l1_fp64": {"row": row, "col": col},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec],
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[prec], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[prec],
+                     "traffic": recorded_traffic(f"lse_partial_{prec}<{PAD[d]},{QB[d]}>",
+                                                 args.workload),
                      "kernel": "lse_partial (fused cost + log-sum-exp)",
                      "avg_launch_us": avg_lse_s * 1e6, "launches": lse_n,
                      "flops_per_launch": flops},

@@ -30,13 +30,20 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 METRIC = "ProgOT solve time @ marginal err 1e-3; n·m·iters/s; serve p50/p99 latency"
-PEAK = {"fp32": 157.3, "bf16": 2500.0}   # TFLOP/s, dense MFMA, MI355X
+# TFLOP/s of the cross term, dense MFMA, MI355X: FP32; BF16; BF16X3 runs three
+# BF16 products per algorithmic product, so its ceiling is the BF16 peak / 3.
+PEAK = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3}
 PAD = {16: 16, 64: 64, 128: 128, 256: 256}  # template dimension of the kernel per d
 QB = {16: 2, 64: 2, 128: 2, 256: 1}
 
+_SPHERE64K = dict(kind="sphere", seed=3, n=65536, m=65536, d=256, n_clusters=32)
 WORKLOADS = {
     # name: (generator kwargs, K, precision)
     "gmm16k_d64_fp32": (dict(kind="gmm", seed=2, n=16384, m=16384, d=64), 8, "fp32"),
+    # precision workload: 32 unit-norm clusters + N(0, 0.01 I), d = 256
+    "sphere64k_d256_fp32": (_SPHERE64K, 4, "fp32"),
+    "sphere64k_d256_bf16": (_SPHERE64K, 4, "bf16"),
+    "sphere64k_d256_bf16x3": (_SPHERE64K, 4, "bf16x3"),
 }
 
 
@@ -91,12 +98,120 @@ def cpu_baseline(X, Y, n_sample: int, max_iter: int):
                       f"(max {max_iter}), cost matrix build included, {dt:.1f} s"}
 
 
+def serve_bench(args):
+    """Serving workload: a Poisson stream of ProgOT solves (K = 4) with n, m
+    log-uniform in [256, 32768] and d in {16, 64, 128}.  (1) closed loop:
+    every request submitted at once -> saturation solves/s; (2) open loop at
+    0.7 x saturation, latency = finish - scheduled arrival; (3) the same
+    arrivals served first-in first-out by single pot_progot_solve calls."""
+    import torch
+    import paper_2406_05061_amd as P
+
+    K, tau = 4, args.tau
+    reqs = workloads.request_stream(n_req=args.requests, qps=1.0, seed=4)
+    log(f"bench: serve: {len(reqs)} requests, K={K}, generating clouds")
+    data = []
+    for r in reqs:
+        X, Y = workloads.request_clouds(r)
+        data.append((P.to_device(X), P.to_device(Y)))
+    torch.cuda.synchronize()
+    pair_flops = [2.0 * r.n * r.m * r.d for r in reqs]
+    arena = args.arena_gib << 30
+
+    def run_server(arrivals):
+        srv = P.Server(arena, max_active=args.max_active)
+        t0 = time.perf_counter()
+        order = sorted(range(len(reqs)), key=lambda i: arrivals[i])
+        pending, rid_of, done = 0, {}, {}
+        infos = {}
+        while len(done) < len(reqs):
+            now = time.perf_counter() - t0
+            while pending < len(order) and arrivals[order[pending]] <= now:
+                i = order[pending]
+                rid = srv.submit(data[i][0], data[i][1], K, tau_first=tau, tau_last=tau,
+                                 want_TX=True)
+                if rid is None:
+                    break
+                rid_of[rid] = i
+                pending += 1
+            if rid_of:
+                srv.step()
+                now = time.perf_counter() - t0
+                for rid, i in list(rid_of.items()):
+                    res = srv.poll(rid)
+                    if res is not None:
+                        done[i] = now
+                        infos[i] = res[3]
+                        del rid_of[rid]
+            elif pending < len(order):
+                time.sleep(max(0.0, min(0.01, arrivals[order[pending]] - now)))
+        wall = time.perf_counter() - t0
+        srv.close()
+        return wall, done, infos
+
+    def lat_stats(done, arrivals):
+        lat = np.array([done[i] - arrivals[i] for i in range(len(reqs))])
+        return float(np.percentile(lat, 50) * 1e3), float(np.percentile(lat, 99) * 1e3)
+
+    # (1) saturation
+    zero = [0.0] * len(reqs)
+    P.timing_enable(True)
+    wall_sat, done_sat, infos_sat = run_server(zero)
+    lse_ms, lse_n, _, _ = P.timing_read()
+    P.timing_enable(False)
+    sat = len(reqs) / wall_sat
+    flops = sum(pair_flops[i] * 2 * sum(it + 1 for it in infos_sat[i].iters)
+                for i in range(len(reqs)))
+    log(f"bench: serve saturation {sat:.2f} solves/s ({wall_sat:.1f} s)")
+    # (2) open loop at 0.7 x saturation
+    qps = 0.7 * sat
+    rng = np.random.default_rng(4)
+    gaps = rng.exponential(1.0 / qps, size=len(reqs))
+    arrivals = list(np.cumsum(gaps) - gaps[0])
+    wall_srv, done_srv, infos_srv = run_server(arrivals)
+    p50, p99 = lat_stats(done_srv, arrivals)
+    log(f"bench: serve open loop qps {qps:.2f}: p50 {p50:.1f} ms p99 {p99:.1f} ms")
+    # (3) FIFO baseline with single solves
+    t0 = time.perf_counter()
+    done_seq = {}
+    for i in sorted(range(len(reqs)), key=lambda i: arrivals[i]):
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        cl = P.prepare_clouds(data[i][0], data[i][1])
+        P.progot_solve(cl, K, tau_first=tau, tau_last=tau)
+        done_seq[i] = time.perf_counter() - t0
+    wall_seq = time.perf_counter() - t0
+    b50, b99 = lat_stats(done_seq, arrivals)
+    log(f"bench: FIFO single solves: p50 {b50:.1f} ms p99 {b99:.1f} ms ({wall_seq:.1f} s)")
+    achieved = flops / (lse_ms * 1e-3) / 1e12 if lse_ms > 0 else 0.0
+    out = {
+        "metric": METRIC, "value": len(reqs) / wall_srv, "unit": "solves/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": wall_srv / len(reqs) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serve", "requests": len(reqs), "K": K, "tau": tau,
+                   "n_m": "log-uniform [256, 32768]", "d": [16, 64, 128],
+                   "qps": qps, "max_active": args.max_active, "arena_gib": args.arena_gib},
+        "latency_ms": {"p50": p50, "p99": p99},
+        "saturation_solves_per_s": sat,
+        "fifo_single_solve": {"solves_per_s": len(reqs) / wall_seq, "p50_ms": b50, "p99_ms": b99},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["fp32"], "traffic": None,
+                     "kernel": "lse_partial grouped (saturation run)", "launches": lse_n},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gmm16k_d64_fp32", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="gmm16k_d64_fp32", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--requests", type=int, default=128, help="serve: number of requests")
+    ap.add_argument("--max-active", type=int, default=128, help="serve: server slots")
+    ap.add_argument("--arena-gib", type=int, default=16, help="serve: HBM budget of the server")
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192)
@@ -116,6 +231,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "serve":
+        serve_bench(args)
+        return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -174,7 +292,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "bf16",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x3": "bf16x3"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "K": K,
                    "precision": prec, "tau": args.tau, "eps": "mean cost/20 per step",

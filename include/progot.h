@@ -55,6 +55,7 @@ extern "C" {
 typedef enum {
     POT_OK = 0,
     POT_WARN_NOT_CONVERGED = 1, /* stopped at max_iter with err > tau; outputs valid   */
+    POT_BUSY = 2,               /* serving: not admitted now / still in flight; retry  */
     POT_ERR_INVALID = -1,       /* bad sizes, null pointers, eps <= 0, K out of range  */
     POT_ERR_NOMEM = -2,         /* workspace smaller than pot_workspace_bytes()        */
     POT_ERR_NUMERIC = -3,       /* a non-finite marginal error or mean cost was seen    */
@@ -62,10 +63,13 @@ typedef enum {
 } pot_status;
 
 /* Arithmetic of the cross term <x_i, y_j> of the cost.  FP32: FP32 MFMA with
- * FP32 accumulation.  BF16: BF16 MFMA (inputs rounded to nearest even) with
- * FP32 accumulation; norms, log-sum-exp, potentials and marginal errors stay
- * FP32 in both. */
-typedef enum { POT_PREC_FP32 = 0, POT_PREC_BF16 = 1 } pot_precision;
+ * FP32 accumulation.  BF16: BF16 MFMA on copies rounded to nearest even,
+ * FP32 accumulation.  BF16X3: each value split as hi + lo (hi = bf16(x),
+ * lo = bf16(x - hi)) and the cross term formed as hi*hi + hi*lo + lo*hi on
+ * BF16 MFMA (~2^-16 relative).  In the BF16 forms the projection product of
+ * the entropic map uses BF16 weights times (Y_hi + Y_lo).  Norms, the
+ * log-sum-exp, potentials and marginal errors stay FP32 in every form. */
+typedef enum { POT_PREC_FP32 = 0, POT_PREC_BF16 = 1, POT_PREC_BF16X3 = 2 } pot_precision;
 
 #define POT_MAX_D 256      /* largest supported dimension d                    */
 #define POT_MAX_K 64       /* largest number of ProgOT steps K                  */
@@ -81,7 +85,8 @@ typedef struct pot_clouds {
     float *xk;             /* current source iterate X^(k) (device, n*d)        */
     float *x_sqn, *y_sqn;  /* |x_i|^2, |y_j|^2 (device, FP32, from FP64 sums)   */
     float *log_a, *log_b;  /* log weights (device)                              */
-    void *x_lp, *y_lp;     /* BF16 copies of xk and Y (device; BF16 form only)  */
+    void *x_lp, *y_lp;     /* BF16 [hi | lo] copies of xk and Y (BF16 forms)   */
+    void *yt_lp;           /* transposed BF16 [hi | lo] copy of Y (BF16 forms)  */
     double mean_cost;      /* (1/nm) sum_ij |x_i - y_j|^2 for the current xk    */
     void *ws;              /* workspace base (device)                           */
     size_t ws_bytes;
@@ -179,6 +184,59 @@ POT_API int pot_progot_map(const pot_clouds *c, int32_t K, const float *G, const
  * f (device, n), g (device, m); out (host, 3 doubles).  Blocks. */
 POT_API int pot_marginal_check(const pot_clouds *c, const float *f, const float *g, float eps,
                        double *out, void *stream);
+
+/* ---- Serving form: continuous batching of ProgOT solves ------------------
+ *
+ * A server advances many independent ProgOT solves (Alg. 2) of uneven sizes
+ * together.  The caller gives it one device arena; each admitted request
+ * takes a workspace of pot_server_request_bytes() from it (first fit), so
+ * admission is by HBM footprint, bounded also by max_active slots.  Each
+ * pot_server_step is one tick: one Sinkhorn iteration of every active
+ * request, with all f-updates in one grouped kernel launch per padded
+ * dimension and likewise all g-updates, then one read-back of all their
+ * row-marginal errors; a request whose solve met its tau takes its McCann
+ * step and starts the next ProgOT step at the following tick, and a request
+ * submitted between ticks joins at the next one.  A request computes exactly
+ * what pot_progot_solve computes for it alone (bit for bit): same kernels,
+ * same column splits, same host arithmetic.  FP32 cross term, uniform
+ * weights.  Calls on one server are not thread-safe. */
+typedef struct pot_server pot_server;
+
+#define POT_SERVER_MAX_ACTIVE 1024
+
+/* Device bytes the server keeps for itself at the start of the arena. */
+POT_API size_t pot_server_arena_overhead(int32_t max_active);
+/* Device bytes one request of these sizes occupies in the arena (0 if invalid). */
+POT_API size_t pot_server_request_bytes(int64_t n, int64_t m, int32_t d);
+
+/* arena (device, arena_bytes) is owned by the caller and must outlive the
+ * server; stream is the hipStream_t every launch goes to (as void*).
+ * 1 <= max_active <= POT_SERVER_MAX_ACTIVE. */
+POT_API int pot_server_create(pot_server **out, void *arena, size_t arena_bytes,
+                              int32_t max_active, void *stream);
+
+/* Admit one solve: X (device, n*d), Y (device, m*d), parameters as for
+ * pot_progot_solve; outputs f (device, n), G (device, K*m), TX (device, n*d,
+ * or NULL) are written when the request finishes.  Inputs and outputs must
+ * stay valid until then.  Returns POT_BUSY when no slot or no arena space is
+ * free now (retry after a step), POT_ERR_NOMEM when the request can never fit
+ * the arena.  The prepare kernels are enqueued at once. */
+POT_API int pot_server_submit(pot_server *srv, const float *X, int64_t n, const float *Y,
+                              int64_t m, int32_t d, const pot_progot_params *p, float *f,
+                              float *G, float *TX, int64_t *rid);
+
+/* One tick (blocks on the stream).  n_active: requests still in flight;
+ * n_finished: requests that finished in this tick (their outputs are in
+ * place).  A request that fails (non-finite error) finishes with its status. */
+POT_API int pot_server_step(pot_server *srv, int32_t *n_active, int32_t *n_finished);
+
+/* POT_BUSY while request rid is in flight; once finished, fills info (may be
+ * NULL), forgets the request and returns its status (POT_OK,
+ * POT_WARN_NOT_CONVERGED or an error).  POT_ERR_INVALID for an unknown rid. */
+POT_API int pot_server_poll(pot_server *srv, int64_t rid, pot_progot_info *info);
+
+/* Waits for the stream and frees the server's host state (not the arena). */
+POT_API int pot_server_destroy(pot_server *srv);
 
 /* Kernel timing, a tracing aid.  While enabled (process-wide), every launch
  * of the fused cost + log-sum-exp kernel (the f- and g-update) and of the

@@ -13,7 +13,8 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libprogot.so"
-SOURCES = ["progot_kernels.hip", "progot_api.hip", "progot_timing.hip"]
+SOURCES = ["progot_kernels.hip", "progot_kernels_bf16.hip", "progot_api.hip", "progot_server.hip",
+           "progot_timing.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

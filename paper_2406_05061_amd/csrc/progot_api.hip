@@ -4,8 +4,8 @@
 // workspace, laid out by plan() from (n, m, d, precision).  Host-side state is
 // limited to a small per-thread pinned buffer for scalar read-backs.
 
-#include "../../include/progot.h"
-#include "progot_internal.h"
+#include "progot.h"
+#include "progot_host.h"
 
 #include <algorithm>
 #include <chrono>
@@ -13,15 +13,8 @@
 #include <cstring>
 #include <vector>
 
-namespace {
-
-using pot::LseArgs;
-using pot::MapArgs;
-
-struct Layout {
-    size_t xk, xsq, ysq, la, lb, xlp, ylp, f0, f1, g0, g1, pm, ps, errp, errd, xst, yst, chr, chc;
-    size_t total;
-};
+namespace pot {
+namespace host {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -35,10 +28,13 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision) {
     L.ysq = take((size_t)m * 4);
     L.la = take((size_t)n * 4);
     L.lb = take((size_t)m * 4);
-    const size_t lpx = precision == POT_PREC_BF16 ? (size_t)n * d * 2 : 0;
-    const size_t lpy = precision == POT_PREC_BF16 ? (size_t)m * d * 2 : 0;
-    L.xlp = take(lpx);
-    L.ylp = take(lpy);
+    // BF16 forms: [hi | lo] row copies padded to bf16_dim(d), and the
+    // transposed target copy used by the projection product.
+    const bool lp = precision != POT_PREC_FP32;
+    const size_t Dp = (size_t)pot::bf16_dim(d);
+    L.xlp = take(lp ? 2 * (size_t)n * Dp * 2 : 0);
+    L.ylp = take(lp ? 2 * (size_t)m * Dp * 2 : 0);
+    L.ytl = take(lp ? 2 * Dp * (size_t)pot::bf16_mpad(m) * 2 : 0);
     L.f0 = take((size_t)n * 4);
     L.f1 = take((size_t)n * 4);
     L.g0 = take((size_t)m * 4);
@@ -55,29 +51,151 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision) {
     return L;
 }
 
-template <typename T> T *at(const pot_clouds *c, size_t off) {
-    return reinterpret_cast<T *>(static_cast<char *>(c->ws) + off);
-}
-
 bool valid_sizes(int64_t n, int64_t m, int32_t d, int32_t precision) {
     return n >= 1 && m >= 1 && d >= 1 && d <= POT_MAX_D &&
-           (precision == POT_PREC_FP32 || precision == POT_PREC_BF16) &&
+           (precision == POT_PREC_FP32 || precision == POT_PREC_BF16 ||
+            precision == POT_PREC_BF16X3) &&
            n <= (int64_t(1) << 31) && m <= (int64_t(1) << 31);
 }
 
 bool valid_clouds(const pot_clouds *c) {
     if (!c || !c->ws || !c->X || !c->Y || !c->xk) return false;
     if (!valid_sizes(c->n, c->m, c->d, c->precision)) return false;
+    if (c->precision != POT_PREC_FP32 && (!c->x_lp || !c->y_lp || !c->yt_lp)) return false;
     return c->ws_bytes >= plan(c->n, c->m, c->d, c->precision).total;
 }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
 
-#define POT_TRY(expr)                                         \
-    do {                                                      \
-        hipError_t _e = (expr);                               \
-        if (_e != hipSuccess) return POT_ERR_DEVICE;          \
-    } while (0)
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void bind_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
+                 const float *a, const float *b, int32_t precision, void *ws, size_t ws_bytes,
+                 const Layout &L) {
+    std::memset(c, 0, sizeof(*c));
+    c->n = n; c->m = m; c->d = d; c->precision = precision;
+    c->X = X; c->Y = Y; c->a = a; c->b = b; c->ws = ws; c->ws_bytes = ws_bytes;
+    c->xk = at<float>(c, L.xk);
+    c->x_sqn = at<float>(c, L.xsq);
+    c->y_sqn = at<float>(c, L.ysq);
+    c->log_a = at<float>(c, L.la);
+    c->log_b = at<float>(c, L.lb);
+    c->x_lp = precision != POT_PREC_FP32 ? at<void>(c, L.xlp) : nullptr;
+    c->y_lp = precision != POT_PREC_FP32 ? at<void>(c, L.ylp) : nullptr;
+    c->yt_lp = precision != POT_PREC_FP32 ? at<void>(c, L.ytl) : nullptr;
+}
+
+int enqueue_moments(pot_clouds *c, const Layout &L, double *host, hipStream_t s) {
+    const int d = c->d;
+    POT_TRY(pot::launch_cloud_prep(c->xk, c->n, d, c->x_sqn, c->x_lp, at<double>(c, L.xst),
+                                   pot::cloud_stat_blocks(c->n), s));
+    POT_TRY(hipMemcpyAsync(host, at<double>(c, L.xst), (d + 1) * 8, hipMemcpyDeviceToHost, s));
+    POT_TRY(hipMemcpyAsync(host + d + 1, at<double>(c, L.yst), (d + 1) * 8, hipMemcpyDeviceToHost, s));
+    return POT_OK;
+}
+
+int enqueue_prepare(pot_clouds *c, const Layout &L, double *host, hipStream_t s) {
+    POT_TRY(hipMemcpyAsync(c->xk, c->X, (size_t)c->n * c->d * sizeof(float), hipMemcpyDeviceToDevice, s));
+    POT_TRY(pot::launch_log_weights(c->a, c->n, c->log_a, s));
+    POT_TRY(pot::launch_log_weights(c->b, c->m, c->log_b, s));
+    POT_TRY(pot::launch_cloud_prep(c->Y, c->m, c->d, c->y_sqn, c->y_lp, at<double>(c, L.yst),
+                                   pot::cloud_stat_blocks(c->m), s));
+    if (c->yt_lp) POT_TRY(pot::launch_bf16_transpose(c->y_lp, c->m, c->d, c->yt_lp, s));
+    return enqueue_moments(c, L, host, s);
+}
+
+int finish_moments(pot_clouds *c, const double *host) {
+    const int d = c->d;
+    const double *sx = host, *sy = host + d + 1;
+    const double n = (double)c->n, m = (double)c->m;
+    double dot = 0.0;
+    for (int k = 0; k < d; ++k) dot += (sx[k] / n) * (sy[k] / m);
+    c->mean_cost = sx[d] / n + sy[d] / m - 2.0 * dot;
+    return std::isfinite(c->mean_cost) ? POT_OK : POT_ERR_NUMERIC;
+}
+
+LseJob f_job(const pot_clouds *c, const Layout &L, float eps) {
+    LseJob a{};
+    a.U = c->xk; a.U_lp = c->x_lp; a.nu = c->n; a.usq = c->x_sqn; a.logw = c->log_a;
+    a.V = c->Y; a.V_lp = c->y_lp; a.nv = c->m; a.vsq = c->y_sqn;
+    a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
+    a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = at<float>(c, L.errp);
+    return a;
+}
+
+LseJob g_job(const pot_clouds *c, const Layout &L, float eps) {
+    LseJob a{};
+    a.U = c->Y; a.U_lp = c->y_lp; a.nu = c->m; a.usq = c->y_sqn; a.logw = c->log_b;
+    a.V = c->xk; a.V_lp = c->x_lp; a.nv = c->n; a.vsq = c->x_sqn;
+    a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
+    a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = nullptr;
+    return a;
+}
+
+void alpha_schedule(int K, int kind, float *alpha) {
+    for (int k = 0; k < K; ++k) {
+        double a;
+        if (kind == 1) {
+            a = 1.0 / std::exp(1.0);
+        } else {
+            const double tk = kind == 2 ? std::pow((double)k / K, 2.0) : (double)k / K;
+            const double t1 = kind == 2 ? std::pow((double)(k + 1) / K, 2.0) : (double)(k + 1) / K;
+            a = (t1 - tk) / (1.0 - tk);
+        }
+        alpha[k] = (float)a;
+    }
+    alpha[K - 1] = 1.f;
+}
+
+bool valid_params(const pot_progot_params *p) {
+    if (!p || p->K < 1 || p->K > POT_MAX_K || p->max_iter < 1 || p->alpha_sched < 0 ||
+        p->alpha_sched > 2)
+        return false;
+    if (p->eps_mode == 0) {
+        if (!finite_pos(p->theta)) return false;
+    } else if (p->eps_mode == 1) {
+        if (!p->eps_explicit) return false;
+        for (int k = 0; k < p->K; ++k)
+            if (!(p->eps_explicit[k] > 0.0) || !std::isfinite(p->eps_explicit[k])) return false;
+    } else {
+        return false;
+    }
+    return p->tau_first >= 0.f && p->tau_last >= 0.f && std::isfinite(p->tau_first) &&
+           std::isfinite(p->tau_last);
+}
+
+int step_values(const pot_progot_params *p, const float *alpha, int k, double mean_cost,
+                float *eps, float *tau, float *gamma) {
+    const int K = p->K;
+    *eps = p->eps_mode == 0 ? (float)(p->theta * mean_cost / 20.0) : (float)p->eps_explicit[k];
+    if (!finite_pos(*eps)) return POT_ERR_NUMERIC;
+    *tau = K == 1 ? p->tau_last
+                  : p->tau_first + (p->tau_last - p->tau_first) * (float)k / (float)(K - 1);
+    const float w = (p->warm_start == 0 || k == 0) ? alpha[k] : alpha[k - 1];
+    *gamma = 1.f - w;
+    return POT_OK;
+}
+
+int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
+            float alpha, float *Xout, hipStream_t s) {
+    MapArgs a{};
+    a.Xq = Xq; a.nq = nq; a.Y = c->Y; a.Y_lp = c->y_lp; a.m = c->m; a.ysq = c->y_sqn; a.g = g;
+    a.eps = eps; a.alpha = alpha; a.d = c->d; a.precision = c->precision;
+    a.YT_lp = c->yt_lp; a.mp = pot::bf16_mpad(c->m);
+    a.Xout = Xout; a.out_sqn = nullptr;
+    POT_TRY(pot::launch_entropic_map(a, s));
+    return POT_OK;
+}
+
+}  // namespace host
+}  // namespace pot
+
+namespace {
+
+using namespace pot::host;
+using pot::LseJob;
 
 // Per-thread pinned landing zone for scalar read-backs.
 struct Pinned {
@@ -96,48 +214,13 @@ float *pinned_slot() {
     return g_pinned.buf;
 }
 
-double now_s() {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-// mean_ij |x_i - y_j|^2 from the FP64 first and second moments:
-// (1/n) sum |x|^2 + (1/m) sum |y|^2 - 2 xbar . ybar.
-int refresh_mean_cost(pot_clouds *c, const Layout &L, bool with_y, hipStream_t s) {
-    const int d = c->d;
-    const int nbx = pot::cloud_stat_blocks(c->n);
-    POT_TRY(pot::launch_cloud_prep(c->xk, c->n, d, c->x_sqn, c->x_lp, at<double>(c, L.xst), nbx, s));
-    if (with_y) {
-        const int nby = pot::cloud_stat_blocks(c->m);
-        POT_TRY(pot::launch_cloud_prep(c->Y, c->m, d, c->y_sqn, c->y_lp, at<double>(c, L.yst), nby, s));
-    }
-    std::vector<double> sx(d + 1), sy(d + 1);
-    POT_TRY(hipMemcpyAsync(sx.data(), at<double>(c, L.xst), (d + 1) * 8, hipMemcpyDeviceToHost, s));
-    POT_TRY(hipMemcpyAsync(sy.data(), at<double>(c, L.yst), (d + 1) * 8, hipMemcpyDeviceToHost, s));
+// Synchronous mean-cost refresh of the source iterate (single-problem path).
+int refresh_mean_cost(pot_clouds *c, const Layout &L, hipStream_t s) {
+    std::vector<double> host(moments_len(c->d));
+    int st = enqueue_moments(c, L, host.data(), s);
+    if (st != POT_OK) return st;
     POT_TRY(hipStreamSynchronize(s));
-    const double n = (double)c->n, m = (double)c->m;
-    double dot = 0.0;
-    for (int k = 0; k < d; ++k) dot += (sx[k] / n) * (sy[k] / m);
-    c->mean_cost = sx[d] / n + sy[d] / m - 2.0 * dot;
-    if (!std::isfinite(c->mean_cost)) return POT_ERR_NUMERIC;
-    return POT_OK;
-}
-
-LseArgs f_update_args(const pot_clouds *c, const Layout &L, float eps) {
-    LseArgs a{};
-    a.U = c->xk; a.U_lp = c->x_lp; a.nu = c->n; a.usq = c->x_sqn; a.logw = c->log_a;
-    a.V = c->Y; a.V_lp = c->y_lp; a.nv = c->m; a.vsq = c->y_sqn;
-    a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
-    a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = at<float>(c, L.errp);
-    return a;
-}
-
-LseArgs g_update_args(const pot_clouds *c, const Layout &L, float eps) {
-    LseArgs a{};
-    a.U = c->Y; a.U_lp = c->y_lp; a.nu = c->m; a.usq = c->y_sqn; a.logw = c->log_b;
-    a.V = c->xk; a.V_lp = c->x_lp; a.nv = c->n; a.vsq = c->x_sqn;
-    a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
-    a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = nullptr;
-    return a;
+    return finish_moments(c, host.data());
 }
 
 struct SinkResult {
@@ -170,8 +253,8 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
     hipEvent_t ev;
     POT_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     int status = POT_OK;
-    LseArgs fa = f_update_args(c, L, eps);
-    LseArgs ga = g_update_args(c, L, eps);
+    LseJob fa = f_job(c, L, eps);
+    LseJob ga = g_job(c, L, eps);
     for (int t = 1;; ++t) {
         fa.vpot = t == 1 ? g_init : gb[(t - 1) & 1];
         fa.gamma = t == 1 ? gamma : 1.f;
@@ -212,31 +295,6 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
     return status;
 }
 
-void alpha_schedule(int K, int kind, float *alpha) {
-    for (int k = 0; k < K; ++k) {
-        double a;
-        if (kind == 1) {
-            a = 1.0 / std::exp(1.0);
-        } else {
-            const double tk = kind == 2 ? std::pow((double)k / K, 2.0) : (double)k / K;
-            const double t1 = kind == 2 ? std::pow((double)(k + 1) / K, 2.0) : (double)(k + 1) / K;
-            a = (t1 - tk) / (1.0 - tk);
-        }
-        alpha[k] = (float)a;
-    }
-    alpha[K - 1] = 1.f;
-}
-
-int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
-            float alpha, float *Xout, float *out_sqn, void *out_lp, hipStream_t s) {
-    MapArgs a{};
-    a.Xq = Xq; a.nq = nq; a.Y = c->Y; a.Y_lp = c->y_lp; a.m = c->m; a.ysq = c->y_sqn; a.g = g;
-    a.eps = eps; a.alpha = alpha; a.d = c->d; a.precision = c->precision;
-    a.Xout = Xout; a.out_sqn = out_sqn; a.out_lp = out_lp;
-    POT_TRY(pot::launch_entropic_map(a, s));
-    return POT_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -245,6 +303,7 @@ const char *pot_status_string(int code) {
     switch (code) {
         case POT_OK: return "ok";
         case POT_WARN_NOT_CONVERGED: return "not converged: max_iter reached with err > tau";
+        case POT_BUSY: return "busy: not admitted now or still in flight";
         case POT_ERR_INVALID: return "invalid argument";
         case POT_ERR_NOMEM: return "workspace too small";
         case POT_ERR_NUMERIC: return "non-finite marginal error or mean cost";
@@ -282,20 +341,12 @@ int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y,
         }
         if (std::fabs(tot - 1.0) > 1e-5) return POT_ERR_INVALID;
     }
-    std::memset(c, 0, sizeof(*c));
-    c->n = n; c->m = m; c->d = d; c->precision = precision;
-    c->X = X; c->Y = Y; c->a = a; c->b = b; c->ws = ws; c->ws_bytes = ws_bytes;
-    c->xk = at<float>(c, L.xk);
-    c->x_sqn = at<float>(c, L.xsq);
-    c->y_sqn = at<float>(c, L.ysq);
-    c->log_a = at<float>(c, L.la);
-    c->log_b = at<float>(c, L.lb);
-    c->x_lp = precision == POT_PREC_BF16 ? at<void>(c, L.xlp) : nullptr;
-    c->y_lp = precision == POT_PREC_BF16 ? at<void>(c, L.ylp) : nullptr;
-    POT_TRY(hipMemcpyAsync(c->xk, X, (size_t)n * d * sizeof(float), hipMemcpyDeviceToDevice, s));
-    POT_TRY(pot::launch_log_weights(a, n, c->log_a, s));
-    POT_TRY(pot::launch_log_weights(b, m, c->log_b, s));
-    return refresh_mean_cost(c, L, true, s);
+    bind_clouds(c, X, n, Y, m, d, a, b, precision, ws, ws_bytes, L);
+    std::vector<double> host(moments_len(d));
+    const int st = enqueue_prepare(c, L, host.data(), s);
+    if (st != POT_OK) return st;
+    POT_TRY(hipStreamSynchronize(s));
+    return finish_moments(c, host.data());
 }
 
 int pot_sinkhorn_solve(pot_clouds *c, float eps, float tau, int32_t max_iter, const float *f_init,
@@ -327,26 +378,12 @@ int pot_entropic_map(const pot_clouds *c, const float *g, float eps, const float
         return POT_ERR_INVALID;
     if (nq == 0) return POT_OK;
     if (!Xq || !Xout || nq > (int64_t(1) << 31)) return POT_ERR_INVALID;
-    return run_map(c, g, eps, Xq, nq, alpha, Xout, nullptr, nullptr, static_cast<hipStream_t>(stream));
+    return run_map(c, g, eps, Xq, nq, alpha, Xout, static_cast<hipStream_t>(stream));
 }
 
 int pot_progot_solve(pot_clouds *c, const pot_progot_params *p, float *f, float *G, float *TX,
                      pot_progot_info *info, void *stream) {
-    if (!valid_clouds(c) || !p || !f || !G) return POT_ERR_INVALID;
-    if (p->K < 1 || p->K > POT_MAX_K || p->max_iter < 1 || p->alpha_sched < 0 || p->alpha_sched > 2)
-        return POT_ERR_INVALID;
-    if (p->eps_mode == 0) {
-        if (!finite_pos(p->theta)) return POT_ERR_INVALID;
-    } else if (p->eps_mode == 1) {
-        if (!p->eps_explicit) return POT_ERR_INVALID;
-        for (int k = 0; k < p->K; ++k)
-            if (!(p->eps_explicit[k] > 0.0) || !std::isfinite(p->eps_explicit[k])) return POT_ERR_INVALID;
-    } else {
-        return POT_ERR_INVALID;
-    }
-    if (!(p->tau_first >= 0.f) || !(p->tau_last >= 0.f) || !std::isfinite(p->tau_first) ||
-        !std::isfinite(p->tau_last))
-        return POT_ERR_INVALID;
+    if (!valid_clouds(c) || !valid_params(p) || !f || !G) return POT_ERR_INVALID;
     const double t0 = now_s();
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout L = plan(c->n, c->m, c->d, c->precision);
@@ -356,35 +393,32 @@ int pot_progot_solve(pot_clouds *c, const pot_progot_params *p, float *f, float 
     alpha_schedule(K, p->alpha_sched, alpha);
 
     POT_TRY(hipMemcpyAsync(c->xk, c->X, (size_t)n * c->d * sizeof(float), hipMemcpyDeviceToDevice, s));
-    int st = refresh_mean_cost(c, L, false, s);
+    int st = refresh_mean_cost(c, L, s);
     if (st != POT_OK) return st;
 
     pot_progot_info loc{};
     loc.K = K;
     loc.converged = 1;
     for (int k = 0; k < K; ++k) {
-        const float eps = p->eps_mode == 0 ? (float)(p->theta * c->mean_cost / 20.0)
-                                           : (float)p->eps_explicit[k];
-        if (!finite_pos(eps)) return POT_ERR_NUMERIC;
-        const float tau = K == 1 ? p->tau_last
-                                 : p->tau_first + (p->tau_last - p->tau_first) * (float)k / (float)(K - 1);
-        const float w = (p->warm_start == 0 || k == 0) ? alpha[k] : alpha[k - 1];
+        float eps, tau, gamma;
+        st = step_values(p, alpha, k, c->mean_cost, &eps, &tau, &gamma);
+        if (st != POT_OK) return st;
         const float *g_init = k == 0 ? nullptr : G + (size_t)(k - 1) * m;
         SinkResult r;
-        st = sinkhorn_core(c, L, eps, tau, p->max_iter, g_init, 1.f - w, &r, s);
+        st = sinkhorn_core(c, L, eps, tau, p->max_iter, g_init, gamma, &r, s);
         if (st != POT_OK) return st;
         POT_TRY(hipMemcpyAsync(G + (size_t)k * m, r.g, m * sizeof(float), hipMemcpyDeviceToDevice, s));
         loc.iters[k] = r.iters; loc.err[k] = r.err; loc.eps[k] = eps; loc.alpha[k] = alpha[k];
         if (!r.converged) loc.converged = 0;
         if (k + 1 < K) {
-            st = run_map(c, G + (size_t)k * m, eps, c->xk, n, alpha[k], c->xk, nullptr, nullptr, s);
+            st = run_map(c, G + (size_t)k * m, eps, c->xk, n, alpha[k], c->xk, s);
             if (st != POT_OK) return st;
-            st = refresh_mean_cost(c, L, false, s);  // norms, BF16 copy and mean cost of X^(k+1)
+            st = refresh_mean_cost(c, L, s);  // norms, BF16 copy and mean cost of X^(k+1)
             if (st != POT_OK) return st;
         } else {
             POT_TRY(hipMemcpyAsync(f, r.f, n * sizeof(float), hipMemcpyDeviceToDevice, s));
             if (TX) {
-                st = run_map(c, G + (size_t)k * m, eps, c->xk, n, 1.f, TX, nullptr, nullptr, s);
+                st = run_map(c, G + (size_t)k * m, eps, c->xk, n, 1.f, TX, s);
                 if (st != POT_OK) return st;
             }
         }
@@ -408,8 +442,7 @@ int pot_progot_map(const pot_clouds *c, int32_t K, const float *G, const float *
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int k = 0; k < K; ++k) {
         const float a = k + 1 == K ? 1.f : alpha[k];
-        const int st = run_map(c, G + (size_t)k * c->m, eps[k], k == 0 ? Xq : Yout, nq, a, Yout,
-                               nullptr, nullptr, s);
+        const int st = run_map(c, G + (size_t)k * c->m, eps[k], k == 0 ? Xq : Yout, nq, a, Yout, s);
         if (st != POT_OK) return st;
     }
     return POT_OK;

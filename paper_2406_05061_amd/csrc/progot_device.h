@@ -1,0 +1,43 @@
+// Device helpers shared by the FP32 and BF16 kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace pot {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr float kNegBig = -1.0e30f;  // finite "minus infinity" of running maxima
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// The lane's D/4 features of row `row` of U (zero beyond nu and d).
+template <int D>
+__device__ __forceinline__ void row_fetch(const float *__restrict__ U, int64_t nu, int d,
+                                          int64_t row, int lq, float (&u)[D / 4]) {
+    constexpr int KD = D / 4;
+    const int c0 = lq * KD;
+    if (row < nu && d == D) {
+        const f4 *p = reinterpret_cast<const f4 *>(U + row * D + c0);
+#pragma unroll
+        for (int k = 0; k < KD / 4; ++k) {
+            f4 v = p[k];
+            u[4 * k + 0] = v.x; u[4 * k + 1] = v.y; u[4 * k + 2] = v.z; u[4 * k + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < KD; ++k)
+            u[k] = (row < nu && c0 + k < d) ? U[row * d + c0 + k] : 0.f;
+    }
+}
+
+}  // namespace
+}  // namespace pot

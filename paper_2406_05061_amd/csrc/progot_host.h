@@ -1,0 +1,70 @@
+// Host-side building blocks shared by the single-problem entry points and the
+// serving scheduler, so both take exactly the same steps (same kernels, same
+// splits, same host arithmetic) and a problem gets the same bits either way.
+#pragma once
+
+#include "progot.h"
+#include "progot_internal.h"
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pot {
+namespace host {
+
+// Workspace regions of one pair of clouds (byte offsets, 256-byte aligned).
+struct Layout {
+    size_t xk, xsq, ysq, la, lb, xlp, ylp, ytl, f0, f1, g0, g1, pm, ps, errp, errd, xst, yst, chr, chc;
+    size_t total;
+};
+
+Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision);
+
+template <typename T> T *at(const pot_clouds *c, size_t off) {
+    return reinterpret_cast<T *>(static_cast<char *>(c->ws) + off);
+}
+
+bool valid_sizes(int64_t n, int64_t m, int32_t d, int32_t precision);
+bool valid_clouds(const pot_clouds *c);
+bool finite_pos(float v);
+double now_s();
+
+// Fill the views of c over the workspace (no device work).
+void bind_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
+                 const float *a, const float *b, int32_t precision, void *ws, size_t ws_bytes,
+                 const Layout &L);
+
+// Number of doubles of a moments read-back: (sum_i x_i, sum |x|^2) for the
+// source iterate and for the targets.
+inline int moments_len(int d) { return 2 * (d + 1); }
+
+// Enqueue xk = X, log weights, the targets' norms/copies/moments and the
+// source's, then the moments' copy into `host` (2 (d+1) doubles, pinned or
+// not: the caller synchronises before finish_moments).
+int enqueue_prepare(pot_clouds *c, const Layout &L, double *host, hipStream_t s);
+// Enqueue the source iterate's norms, BF16 copies and moments, and the copy.
+int enqueue_moments(pot_clouds *c, const Layout &L, double *host, hipStream_t s);
+// mean_ij |x_i - y_j|^2 = (1/n) sum |x|^2 + (1/m) sum |y|^2 - 2 xbar . ybar.
+int finish_moments(pot_clouds *c, const double *host);
+
+LseJob f_job(const pot_clouds *c, const Layout &L, float eps);
+LseJob g_job(const pot_clouds *c, const Layout &L, float eps);
+
+// alpha_k for k = 0..K-1 (0 constant speed, 1 decelerated, 2 accelerated).
+void alpha_schedule(int K, int kind, float *alpha);
+// eps_k, tau_k and the warm-start factor of step k of a ProgOT solve.
+int step_values(const pot_progot_params *p, const float *alpha, int k, double mean_cost,
+                float *eps, float *tau, float *gamma);
+bool valid_params(const pot_progot_params *p);
+
+int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
+            float alpha, float *Xout, hipStream_t s);
+
+}  // namespace host
+}  // namespace pot
+
+#define POT_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return POT_ERR_DEVICE;          \
+    } while (0)

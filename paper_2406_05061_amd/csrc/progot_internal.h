@@ -13,12 +13,16 @@ int map_rows_per_block(int d);
 constexpr int kMaxSplit = 32;       // column splits of the log-sum-exp kernel
 constexpr int kReduceBlock = 256;   // threads of the per-row kernels
 
-// Arguments of one potential update (the f-update or the g-update of Alg. 1):
+// One potential update (the f-update or the g-update of Alg. 1) of one
+// problem, as the kernels see it:
 //   out_i = eps*logw_i + usq_i - eps*ln2*log2 sum_j 2^(scale2*<u_i,v_j> + beta_j)
 //   beta_j = (gamma*vpot_j - vsq_j) * log2(e)/eps,  scale2 = 2*log2(e)/eps.
-struct LseArgs {
+// The columns are split S ways (cps columns each); the partial kernel writes
+// per-split (max, sum) partials, the merge kernel the potential and, when
+// pot_old is set, the per-block row-marginal error partials.
+struct LseJob {
     const float *U;        // rows (nu x d)
-    const void *U_lp;      // BF16 copy of U (BF16 form)
+    const void *U_lp;      // BF16 [hi | lo] copy of U (BF16 forms)
     int64_t nu;
     const float *usq;      // |u_i|^2
     const float *logw;     // log weights of the rows
@@ -35,17 +39,51 @@ struct LseArgs {
     float *pot_out;        // new potential (nu)
     float *part_m, *part_s;  // split partials (kMaxSplit x nu each)
     float *err_part;       // per-block error partials (ceil(nu/256))
+    // filled by plan_lse_job
+    int S;                 // column splits
+    int64_t cps;           // columns per split
+    float scale2, bscale;
+    int64_t blocks;        // workgroups of the partial kernel
+    int64_t mblocks;       // workgroups of the merge kernel
+    // grouped launches: first workgroup of this job in the flattened grid
+    int64_t blk_begin, mblk_begin;
+    // serving: device control word of the problem's current Sinkhorn loop.
+    // ctl[0] = 0 while running; the error sum of the f-update that carries
+    // err(iter) sets ctl[0] = iter (and ctl[1] = err bits) once err <= tau or
+    // iter == max_iter, and every later update of the job is skipped, so the
+    // loop stops on the device at the same iterate as the host-checked loop.
+    int *ctl;
+    int iter;
+    int max_iter;
+    float tau;
 };
+typedef LseJob LseArgs;
+
+// Choose S, the scales and the workgroup counts of a job.  Depends only on
+// the job's own sizes, so a problem computes the same bits alone, in a
+// single-problem launch, or inside a grouped launch.
+void plan_lse_job(LseJob &j);
 
 // Enqueue one potential update (partials + merge).  Returns the number of
 // error partials written to err_part (0 if pot_old is NULL).
 hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part);
 
+// Grouped form: every job of `jobs` (host array, planned, FP32, all of one
+// padded dimension) in one partial launch and one merge launch; jobs_dev is
+// device memory holding a copy of the planned jobs with blk_begin/mblk_begin
+// filled (done here, via an async copy from the host array, which must stay
+// alive until the stream reaches the copy).  err sums of jobs with pot_old go
+// to err_out[k] for the k-th such job.
+hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, float *err_out,
+                                   hipStream_t s);
+int padded_dim_f32(int d);
+
 // Deterministic sum of n float partials into *out (device).
 hipError_t launch_sum_f32(const float *part, int n, float *out, hipStream_t s);
 
-// Per-point squared norms in FP64 (rounded to FP32), optional BF16 copy, and
-// FP64 partial sums of (sum_i x_i, sum_i |x_i|^2) into stats (nblk x (d+1)).
+// Per-point squared norms in FP64 (rounded to FP32), optional BF16 hi/lo
+// copies (lp != NULL), and FP64 partial sums of (sum_i x_i, sum_i |x_i|^2)
+// into stats (nblk x (d+1)).
 hipError_t launch_cloud_prep(const float *X, int64_t n, int d, float *sqn, void *lp,
                              double *stats_part, int nblk, hipStream_t s);
 int cloud_stat_blocks(int64_t n);
@@ -66,11 +104,23 @@ struct MapArgs {
     const float *g;        // target potential
     float eps, alpha;
     int d, precision;
+    const void *YT_lp;     // transposed BF16 copy of Y (BF16 forms)
+    int64_t mp;            // row stride of YT_lp
     float *Xout;           // may alias Xq
     float *out_sqn;        // |Xout_i|^2 (nullable)
-    void *out_lp;          // BF16 copy of Xout (nullable)
 };
 hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s);
+
+// BF16 forms (precision 1: one BF16 product; 2: hi/lo split, three products).
+int bf16_dim(int d);                 // padded dimension of the BF16 copies
+int64_t bf16_mpad(int64_t m);        // padded column count of the transposed copy
+int lse_bf16_rows_per_block(int d, int precision);
+hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s);  // planned job
+hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s);
+// [hi | lo] BF16 copies of the rows of X (each n x bf16_dim(d), zero padded).
+hipError_t launch_bf16_rows(const float *X, int64_t n, int d, void *lp, hipStream_t s);
+// [hi^T | lo^T], each bf16_dim(d) x bf16_mpad(m), from the row copies of Y.
+hipError_t launch_bf16_transpose(const void *lp, int64_t m, int d, void *yt, hipStream_t s);
 
 // FP64 check: row sums and column sums of P in FP64, reduced to
 // part[0..3*nb) per-block partials of (|r_i - a_i|, r_i, f_i a_i) and

@@ -21,23 +21,12 @@
 // j = 16 sub + 4q + r), so the projection needs no register shuffle.
 
 #include "progot_internal.h"
+#include "progot_device.h"
 
 #include <cmath>
 
 namespace pot {
 namespace {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.6931471805599453f;
-constexpr float kNegBig = -1.0e30f;  // finite "minus infinity" of running maxima
-
-__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
-
-__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
 
 template <int D> struct Tile {
     static constexpr int BN = D >= 256 ? 32 : 64;   // columns per LDS tile
@@ -92,44 +81,29 @@ __device__ __forceinline__ void tile_store(float *__restrict__ lds, const f4 (&p
     }
 }
 
-// The lane's D/4 features of row `row` of U (zero beyond nu and d).
-template <int D>
-__device__ __forceinline__ void row_fetch(const float *__restrict__ U, int64_t nu, int d,
-                                          int64_t row, int lq, float (&u)[D / 4]) {
-    constexpr int KD = D / 4;
-    const int c0 = lq * KD;
-    if (row < nu && d == D) {
-        const f4 *p = reinterpret_cast<const f4 *>(U + row * D + c0);
-#pragma unroll
-        for (int k = 0; k < KD / 4; ++k) {
-            f4 v = p[k];
-            u[4 * k + 0] = v.x; u[4 * k + 1] = v.y; u[4 * k + 2] = v.z; u[4 * k + 3] = v.w;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < KD; ++k)
-            u[k] = (row < nu && c0 + k < d) ? U[row * d + c0 + k] : 0.f;
-    }
-}
-
-// Partial log-sum-exp of t_ij over one column split, for ROWS = 64*QB rows.
+// Partial log-sum-exp of t_ij over one column split, for ROWS = 64*QB rows
+// (row tile `tile`, column split `split` of job J).
 // Output: part_m/part_s[split*nu + i] = (max, sum 2^{t - max}) in log2 units.
 template <int D, int QB>
-__global__ __launch_bounds__(256) void lse_partial_f32(
-    const float *__restrict__ U, int64_t nu, const float *__restrict__ V,
-    const float *__restrict__ vsq, const float *__restrict__ vpot, int64_t nv, int d,
-    float gamma, float scale2, float bscale, int S, int64_t cols_per_split,
-    float *__restrict__ part_m, float *__restrict__ part_s) {
+__device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, int split,
+                                                 float (&vt)[2][Tile<D>::BN * Tile<D>::STRIDE],
+                                                 float (&bt)[2][Tile<D>::BN]) {
     using T = Tile<D>;
     constexpr int ROWS = 64 * QB;
-    __shared__ float vt[2][T::BN * T::STRIDE];
-    __shared__ float bt[2][T::BN];
+    const float *__restrict__ U = J.U;
+    const float *__restrict__ V = J.V;
+    const float *__restrict__ vsq = J.vsq;
+    const float *__restrict__ vpot = J.vpot;
+    const int64_t nu = J.nu, nv = J.nv;
+    const int d = J.d;
+    const float gamma = J.gamma, scale2 = J.scale2, bscale = J.bscale;
+    const int64_t cols_per_split = J.cps;
+    float *__restrict__ part_m = J.part_m;
+    float *__restrict__ part_s = J.part_s;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lq = lane >> 4;
-    const int split = blockIdx.x % S;   // consecutive blocks -> different XCDs -> one split each
-    const int64_t tile = blockIdx.x / S;
     const int64_t row0 = tile * ROWS + wave * (QB * 16);
 
     float ub[QB][T::KD];
@@ -236,6 +210,52 @@ __global__ __launch_bounds__(256) void lse_partial_f32(
     }
 }
 
+// One job; consecutive blocks take consecutive splits (block b runs on XCD
+// b mod 8, so with S = 8 each XCD streams one eighth of the columns).
+template <int D, int QB>
+__global__ __launch_bounds__(256) void lse_partial_f32(LseJob J) {
+    __shared__ float vt[2][Tile<D>::BN * Tile<D>::STRIDE];
+    __shared__ float bt[2][Tile<D>::BN];
+    lse_partial_body<D, QB>(J, blockIdx.x / J.S, blockIdx.x % J.S, vt, bt);
+}
+
+// d <= 64: the register budget of 3 waves per SIMD holds without spills and
+// the extra wave hides the log-sum-exp epilogue behind other waves' MFMAs.
+template <int D, int QB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+void lse_partial_f32_o3(LseJob J) {
+    __shared__ float vt[2][Tile<D>::BN * Tile<D>::STRIDE];
+    __shared__ float bt[2][Tile<D>::BN];
+    lse_partial_body<D, QB>(J, blockIdx.x / J.S, blockIdx.x % J.S, vt, bt);
+}
+
+// Index of the job owning flattened block `item` (jobs sorted by `begin`).
+template <bool MERGE>
+__device__ __forceinline__ int find_job(const LseJob *__restrict__ jobs, int njobs, int64_t item) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t b = MERGE ? jobs[mid].mblk_begin : jobs[mid].blk_begin;
+        if (b <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Grouped: one launch covers the flattened work list of many jobs (problems
+// of different sizes); block b finds its job by binary search over the jobs'
+// first-block offsets and runs the same body as the single-job kernel, so
+// every problem gets the same bits as when it runs alone.
+template <int D, int QB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 64 ? 3 : 1, 8)))
+void lse_partial_f32_group(const LseJob *__restrict__ jobs, int njobs) {
+    __shared__ float vt[2][Tile<D>::BN * Tile<D>::STRIDE];
+    __shared__ float bt[2][Tile<D>::BN];
+    const LseJob &J = jobs[find_job<false>(jobs, njobs, blockIdx.x)];
+    if (J.ctl && *(volatile const int *)J.ctl != 0) return;   // loop already stopped
+    const int64_t local = (int64_t)blockIdx.x - J.blk_begin;
+    lse_partial_body<D, QB>(J, local / J.S, (int)(local % J.S), vt, bt);
+}
+
 __device__ __forceinline__ float block_sum_256(float v, float *red) {
     const int tid = threadIdx.x;
     red[tid] = v;
@@ -251,12 +271,13 @@ __device__ __forceinline__ float block_sum_256(float v, float *red) {
 // Merge the split partials into the potential and the error partial
 // w_i |exp((pot_old_i - pot_i)/eps) - 1|, which is |(P 1)_i - w_i| for the
 // coupling of (pot_old, vpot): row sums of the previous iterate.
-__global__ __launch_bounds__(256) void lse_merge(
-    const float *__restrict__ part_m, const float *__restrict__ part_s, int S, int64_t nu,
-    const float *__restrict__ usq, const float *__restrict__ logw, float eps,
-    const float *__restrict__ pot_old, float *__restrict__ pot_out, float *__restrict__ err_part) {
-    __shared__ float red[256];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void lse_merge_body(const LseJob &J, int64_t blk, float *red) {
+    const float *__restrict__ part_m = J.part_m;
+    const float *__restrict__ part_s = J.part_s;
+    const int S = J.S;
+    const int64_t nu = J.nu;
+    const float eps = J.eps;
+    const int64_t i = blk * 256 + threadIdx.x;
     float e = 0.f;
     if (i < nu) {
         float M = kNegBig;
@@ -264,28 +285,72 @@ __global__ __launch_bounds__(256) void lse_merge(
         float sum = 0.f;
         for (int s = 0; s < S; ++s) sum += part_s[s * nu + i] * exp2f(part_m[s * nu + i] - M);
         const float L = M + log2f(sum);
-        const float lw = logw[i];
-        const float pot = fmaf(eps, lw, usq[i]) - eps * kLn2 * L;
-        if (pot_old) e = expf(lw) * fabsf(expm1f((pot_old[i] - pot) / eps));
-        pot_out[i] = pot;
+        const float lw = J.logw[i];
+        const float pot = fmaf(eps, lw, J.usq[i]) - eps * kLn2 * L;
+        if (J.pot_old) e = expf(lw) * fabsf(expm1f((J.pot_old[i] - pot) / eps));
+        J.pot_out[i] = pot;
     }
-    if (pot_old) {
+    if (J.pot_old) {
         const float tot = block_sum_256(e, red);
-        if (threadIdx.x == 0) err_part[blockIdx.x] = tot;
+        if (threadIdx.x == 0) J.err_part[blk] = tot;
     }
 }
 
-__global__ __launch_bounds__(256) void sum_f32(const float *__restrict__ part, int n, float *__restrict__ out) {
+__global__ __launch_bounds__(256) void lse_merge(LseJob J) {
     __shared__ float red[256];
+    lse_merge_body(J, blockIdx.x, red);
+}
+
+__global__ __launch_bounds__(256) void lse_merge_group(const LseJob *__restrict__ jobs, int njobs) {
+    __shared__ float red[256];
+    const LseJob J = jobs[find_job<true>(jobs, njobs, blockIdx.x)];
+    if (J.ctl && *(volatile const int *)J.ctl != 0) return;   // loop already stopped
+    lse_merge_body(J, blockIdx.x - J.mblk_begin, red);
+}
+
+__device__ __forceinline__ void sum_body(const float *__restrict__ part, int n, float *out,
+                                         float *red) {
     float v = 0.f;
     for (int i = threadIdx.x; i < n; i += 256) v += part[i];
     const float tot = block_sum_256(v, red);
     if (threadIdx.x == 0) out[0] = tot;
 }
 
+// Error sums of the jobs that carry pot_old, one block each, in job order;
+// with a control word, also the device-side stop rule of the Sinkhorn loop.
+__global__ __launch_bounds__(256) void sum_group(const LseJob *__restrict__ jobs, int njobs,
+                                                 float *__restrict__ out) {
+    __shared__ float red[256];
+    __shared__ float tot;
+    int k = 0, b = blockIdx.x;
+    for (int j = 0; j < njobs; ++j) {
+        const LseJob &J = jobs[j];
+        if (!J.pot_old) continue;
+        if (k == b) {
+            if (J.ctl && *(volatile const int *)J.ctl != 0) return;
+            sum_body(J.err_part, (int)J.mblocks, &tot, red);
+            if (threadIdx.x == 0) {
+                const float err = tot;
+                if (out) out[k] = err;
+                if (J.ctl && ((J.tau > 0.f && err <= J.tau) || J.iter >= J.max_iter || !(err == err))) {
+                    J.ctl[1] = __float_as_int(err);
+                    J.ctl[0] = J.iter;
+                }
+            }
+            return;
+        }
+        ++k;
+    }
+}
+
+__global__ __launch_bounds__(256) void sum_f32(const float *__restrict__ part, int n, float *__restrict__ out) {
+    __shared__ float red[256];
+    sum_body(part, n, out, red);
+}
+
 // Squared norms (FP64 accumulation), optional BF16 copy.
 __global__ __launch_bounds__(256) void cloud_norms(const float *__restrict__ X, int64_t n, int d,
-                                                   float *__restrict__ sqn, __bf16 *__restrict__ lp) {
+                                                   float *__restrict__ sqn) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const float *x = X + i * d;
@@ -293,7 +358,6 @@ __global__ __launch_bounds__(256) void cloud_norms(const float *__restrict__ X, 
     for (int k = 0; k < d; ++k) {
         const double v = x[k];
         s += v * v;
-        if (lp) lp[i * d + k] = (__bf16)x[k];
     }
     sqn[i] = (float)s;
 }
@@ -346,7 +410,7 @@ template <int D, int QB>
 __global__ __launch_bounds__(256) void entropic_map_f32(
     const float *Xq, int64_t nq, int d, const float *__restrict__ Y,
     const float *__restrict__ ysq, const float *__restrict__ g, int64_t m, float scale2,
-    float bscale, float alpha, float *Xout, float *__restrict__ out_sqn, __bf16 *__restrict__ out_lp) {
+    float bscale, float alpha, float *Xout, float *__restrict__ out_sqn) {
     using T = Tile<D>;
     constexpr int ROWS = 64 * QB;
     constexpr int NDB = D / 16;   // 16-feature blocks of the output
@@ -398,23 +462,26 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
             fetch_beta(jn);
         }
         const float *vb = vt[buf];
+        // k outer, (column subtile, row block) inner: NSUB x QB independent
+        // accumulation chains.
         f4 acc[QB][T::NSUB];
 #pragma unroll
-        for (int sub = 0; sub < T::NSUB; ++sub) {
-            float a[T::KD];
-            const f4 *ap = reinterpret_cast<const f4 *>(vb + (sub * 16 + li) * T::STRIDE + lq * T::KD);
+        for (int sub = 0; sub < T::NSUB; ++sub)
 #pragma unroll
-            for (int k = 0; k < T::KD / 4; ++k) {
-                f4 v = ap[k];
-                a[4 * k + 0] = v.x; a[4 * k + 1] = v.y; a[4 * k + 2] = v.z; a[4 * k + 3] = v.w;
-            }
+            for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) {
-                f4 c = {0.f, 0.f, 0.f, 0.f};
+        for (int k4 = 0; k4 < T::KD / 4; ++k4) {
+            f4 a[T::NSUB];
 #pragma unroll
-                for (int k = 0; k < T::KD; ++k) c = mfma4(a[k], ub[qb][k], c);
-                acc[qb][sub] = c;
-            }
+            for (int sub = 0; sub < T::NSUB; ++sub)
+                a[sub] = *reinterpret_cast<const f4 *>(vb + (sub * 16 + li) * T::STRIDE + lq * T::KD + 4 * k4);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb)
+                        acc[qb][sub] = mfma4(a[sub][kk], ub[qb][4 * k4 + kk], acc[qb][sub]);
         }
         f4 beta[T::NSUB];
 #pragma unroll
@@ -496,11 +563,6 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
                     for (int r = 0; r < 4; ++r)
                         if (f0 + r < d) Xout[row * d + f0 + r] = xn[r];
                 }
-                if (out_lp) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (f0 + r < d) out_lp[row * d + f0 + r] = (__bf16)xn[r];
-                }
             }
         }
         sq += __shfl_xor(sq, 16);
@@ -564,11 +626,20 @@ __global__ __launch_bounds__(256) void fp64_rowsums(
 }
 
 template <int D, int QB>
-hipError_t lse_launch_t(const LseArgs &a, int S, int64_t cps, float scale2, float bscale, hipStream_t s) {
-    const int64_t tiles = (a.nu + 64 * QB - 1) / (64 * QB);
-    const dim3 grid((unsigned)(tiles * S));
-    hipLaunchKernelGGL((lse_partial_f32<D, QB>), grid, dim3(256), 0, s, a.U, a.nu, a.V, a.vsq,
-                       a.vpot, a.nv, a.d, a.gamma, scale2, bscale, S, cps, a.part_m, a.part_s);
+hipError_t lse_launch_t(const LseJob &j, hipStream_t s) {
+    // the plan must cover every row tile of this kernel variant
+    if (j.blocks != (j.nu + 64 * QB - 1) / (64 * QB) * j.S) return hipErrorInvalidValue;
+    if constexpr (D <= 64)
+        hipLaunchKernelGGL((lse_partial_f32_o3<D, QB>), dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+    else
+        hipLaunchKernelGGL((lse_partial_f32<D, QB>), dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+    return hipGetLastError();
+}
+
+template <int D, int QB>
+hipError_t lse_group_launch_t(const LseJob *jobs_dev, int njobs, int64_t total, hipStream_t s) {
+    hipLaunchKernelGGL((lse_partial_f32_group<D, QB>), dim3((unsigned)total), dim3(256), 0, s,
+                       jobs_dev, njobs);
     return hipGetLastError();
 }
 
@@ -577,7 +648,7 @@ hipError_t map_launch_t(const MapArgs &a, float scale2, float bscale, hipStream_
     const int64_t tiles = (a.nq + 64 * QB - 1) / (64 * QB);
     hipLaunchKernelGGL((entropic_map_f32<D, QB>), dim3((unsigned)tiles), dim3(256), 0, s, a.Xq,
                        a.nq, a.d, a.Y, a.ysq, a.g, a.m, scale2, bscale, a.alpha, a.Xout,
-                       a.out_sqn, (__bf16 *)a.out_lp);
+                       a.out_sqn);
     return hipGetLastError();
 }
 
@@ -596,35 +667,77 @@ int qb_for(int D) { return D >= 256 ? 1 : 2; }
 int lse_rows_per_block(int d) { return 64 * qb_for(padded_dim(d)); }
 int map_rows_per_block(int d) { return 64 * qb_for(padded_dim(d)); }
 
-hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
-    const int D = padded_dim(a.d);
-    const int rows = lse_rows_per_block(a.d);
-    const int64_t tiles = (a.nu + rows - 1) / rows;
+int padded_dim_f32(int d) { return padded_dim(d); }
+
+void plan_lse_job(LseJob &j) {
+    const int rows = j.precision == 0 ? lse_rows_per_block(j.d) : lse_bf16_rows_per_block(j.d, j.precision);
+    const int64_t tiles = (j.nu + rows - 1) / rows;
     // Split the columns so that the grid holds >= ~1024 workgroups (4 per CU),
     // keeping >= 256 columns per split.
     int64_t S = tiles >= 1024 ? 1 : (1024 + tiles - 1) / tiles;
-    const int64_t max_by_cols = (a.nv + 255) / 256;
+    const int64_t max_by_cols = (j.nv + 255) / 256;
     if (S > max_by_cols) S = max_by_cols;
     if (S > kMaxSplit) S = kMaxSplit;
     if (S < 1) S = 1;
-    const int64_t cps = (a.nv + S - 1) / S;
-    const float scale2 = 2.f * kLog2e / a.eps;
-    const float bscale = kLog2e / a.eps;
+    j.S = (int)S;
+    j.cps = (j.nv + S - 1) / S;
+    j.scale2 = 2.f * kLog2e / j.eps;
+    j.bscale = kLog2e / j.eps;
+    j.blocks = tiles * S;
+    j.mblocks = (j.nu + 255) / 256;
+}
+
+hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
+    LseJob j = a;
+    plan_lse_job(j);
     hipError_t e;
     const int64_t slot = timing_begin(0, s);
-    switch (D) {
-        case 16: e = lse_launch_t<16, 2>(a, (int)S, cps, scale2, bscale, s); break;
-        case 32: e = lse_launch_t<32, 2>(a, (int)S, cps, scale2, bscale, s); break;
-        case 64: e = lse_launch_t<64, 2>(a, (int)S, cps, scale2, bscale, s); break;
-        case 128: e = lse_launch_t<128, 2>(a, (int)S, cps, scale2, bscale, s); break;
-        default: e = lse_launch_t<256, 1>(a, (int)S, cps, scale2, bscale, s); break;
+    if (j.precision != 0) {
+        e = launch_lse_partial_bf16(j, s);
+    } else switch (padded_dim(j.d)) {
+        case 16: e = lse_launch_t<16, 2>(j, s); break;
+        case 32: e = lse_launch_t<32, 2>(j, s); break;
+        case 64: e = lse_launch_t<64, 2>(j, s); break;
+        case 128: e = lse_launch_t<128, 2>(j, s); break;
+        default: e = lse_launch_t<256, 1>(j, s); break;
     }
     timing_end(slot, s);
     if (e != hipSuccess) return e;
-    const int nb = (int)((a.nu + 255) / 256);
-    hipLaunchKernelGGL(lse_merge, dim3(nb), dim3(256), 0, s, a.part_m, a.part_s, (int)S, a.nu,
-                       a.usq, a.logw, a.eps, a.pot_old, a.pot_out, a.err_part);
-    if (n_err_part) *n_err_part = a.pot_old ? nb : 0;
+    hipLaunchKernelGGL(lse_merge, dim3((unsigned)j.mblocks), dim3(256), 0, s, j);
+    if (n_err_part) *n_err_part = j.pot_old ? (int)j.mblocks : 0;
+    return hipGetLastError();
+}
+
+hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, float *err_out,
+                                   hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    int64_t blk = 0, mblk = 0;
+    int nerr = 0;
+    const int D = padded_dim(jobs[0].d);
+    for (int k = 0; k < njobs; ++k) {
+        plan_lse_job(jobs[k]);
+        if (jobs[k].precision != 0 || padded_dim(jobs[k].d) != D) return hipErrorInvalidValue;
+        jobs[k].blk_begin = blk;
+        jobs[k].mblk_begin = mblk;
+        blk += jobs[k].blocks;
+        mblk += jobs[k].mblocks;
+        if (jobs[k].pot_old) ++nerr;
+    }
+    hipError_t e = hipMemcpyAsync(jobs_dev, jobs, sizeof(LseJob) * njobs, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    const int64_t slot = timing_begin(0, s);
+    switch (D) {
+        case 16: e = lse_group_launch_t<16, 2>(jobs_dev, njobs, blk, s); break;
+        case 32: e = lse_group_launch_t<32, 2>(jobs_dev, njobs, blk, s); break;
+        case 64: e = lse_group_launch_t<64, 2>(jobs_dev, njobs, blk, s); break;
+        case 128: e = lse_group_launch_t<128, 2>(jobs_dev, njobs, blk, s); break;
+        default: e = lse_group_launch_t<256, 1>(jobs_dev, njobs, blk, s); break;
+    }
+    timing_end(slot, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lse_merge_group, dim3((unsigned)mblk), dim3(256), 0, s, jobs_dev, njobs);
+    if (nerr > 0)
+        hipLaunchKernelGGL(sum_group, dim3(nerr), dim3(256), 0, s, jobs_dev, njobs, err_out);
     return hipGetLastError();
 }
 
@@ -640,9 +753,9 @@ int cloud_stat_blocks(int64_t n) {
 
 hipError_t launch_cloud_prep(const float *X, int64_t n, int d, float *sqn, void *lp,
                              double *stats_part, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(cloud_norms, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d,
-                       sqn, (__bf16 *)lp);
+    hipLaunchKernelGGL(cloud_norms, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, sqn);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess && lp) e = launch_bf16_rows(X, n, d, lp, s);
     if (e != hipSuccess || !stats_part) return e;
     const int64_t rpb = (n + nblk - 1) / nblk;
     hipLaunchKernelGGL(cloud_stats, dim3(nblk), dim3(256), 0, s, X, n, d, sqn, rpb, stats_part);
@@ -666,7 +779,9 @@ hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s) {
     const float bscale = kLog2e / a.eps;
     const int64_t slot = timing_begin(1, s);
     hipError_t e;
-    switch (padded_dim(a.d)) {
+    if (a.precision != 0) {
+        e = launch_map_bf16(a, scale2, bscale, s);
+    } else switch (padded_dim(a.d)) {
         case 16: e = map_launch_t<16, 2>(a, scale2, bscale, s); break;
         case 32: e = map_launch_t<32, 2>(a, scale2, bscale, s); break;
         case 64: e = map_launch_t<64, 2>(a, scale2, bscale, s); break;

@@ -2,7 +2,7 @@
 // pot_timing_read): HIP timing events around kernel launches, resolved
 // lazily when read.
 
-#include "../../include/progot.h"
+#include "progot.h"
 #include "progot_internal.h"
 
 #include <mutex>

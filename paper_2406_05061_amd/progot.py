@@ -9,6 +9,7 @@ built library every call raises.
 from __future__ import annotations
 
 import ctypes as C
+import os
 import re
 from dataclasses import dataclass
 from pathlib import Path
@@ -16,16 +17,18 @@ from pathlib import Path
 import numpy as np
 
 _PKG = Path(__file__).resolve().parent
-LIB_PATH = _PKG / "libprogot.so"
+# PROGOT_LIB selects another build of the same library (A/B timing of variants).
+LIB_PATH = Path(os.environ.get("PROGOT_LIB", str(_PKG / "libprogot.so")))
 HEADER = _PKG.parent / "include" / "progot.h"
 
 POT_OK = 0
 POT_WARN_NOT_CONVERGED = 1
+POT_BUSY = 2
 POT_ERR_INVALID = -1
 POT_ERR_NOMEM = -2
 POT_ERR_NUMERIC = -3
 POT_ERR_DEVICE = -4
-PREC = {"fp32": 0, "bf16": 1}
+PREC = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 ALPHA_SCHED = {"constant": 0, "decelerated": 1, "accelerated": 2}
 MAX_K = 64
 
@@ -43,7 +46,7 @@ class pot_clouds(C.Structure):
         ("xk", C.c_void_p),
         ("x_sqn", C.c_void_p), ("y_sqn", C.c_void_p),
         ("log_a", C.c_void_p), ("log_b", C.c_void_p),
-        ("x_lp", C.c_void_p), ("y_lp", C.c_void_p),
+        ("x_lp", C.c_void_p), ("y_lp", C.c_void_p), ("yt_lp", C.c_void_p),
         ("mean_cost", C.c_double), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
     ]
 
@@ -85,6 +88,14 @@ _SIGS = {
                                  C.POINTER(C.c_float), _vp, _i64, _vp, _vp]),
     "pot_marginal_check": (C.c_int, [C.POINTER(pot_clouds), _vp, _vp, _f32, C.POINTER(C.c_double),
                                      _vp]),
+    "pot_server_arena_overhead": (C.c_size_t, [_i32]),
+    "pot_server_request_bytes": (C.c_size_t, [_i64, _i64, _i32]),
+    "pot_server_create": (C.c_int, [C.POINTER(C.c_void_p), _vp, C.c_size_t, _i32, _vp]),
+    "pot_server_submit": (C.c_int, [_vp, _vp, _i64, _vp, _i64, _i32, C.POINTER(pot_progot_params),
+                                    _vp, _vp, _vp, C.POINTER(C.c_int64)]),
+    "pot_server_step": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "pot_server_poll": (C.c_int, [_vp, C.c_int64, C.POINTER(pot_progot_info)]),
+    "pot_server_destroy": (C.c_int, [_vp]),
     "pot_timing_enable": (C.c_int, [C.c_int]),
     "pot_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                   C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -254,13 +265,9 @@ class ProgOTInfo:
     status: int
 
 
-def progot_solve(cl: Clouds, K: int, *, alpha_sched: str = "constant", theta: float = 1.0,
-                 eps=None, tau_first: float = 1e-3, tau_last: float = 1e-3,
-                 max_iter: int = 10_000, warm_start: str = "alpha_k", want_TX: bool = True):
-    """Alg. 2; returns (f, G, TX or None, ProgOTInfo).  eps=None uses the
-    per-step mean-cost rule with theta; an array gives an explicit schedule."""
-    torch = _torch()
-    dev = cl.X.device
+def _params(K, alpha_sched="constant", theta=1.0, eps=None, tau_first=1e-3, tau_last=1e-3,
+            max_iter=10_000, warm_start="alpha_k"):
+    """pot_progot_params plus the buffer its eps pointer refers to (keep both alive)."""
     p = pot_progot_params()
     p.K = int(K)
     p.alpha_sched = ALPHA_SCHED[alpha_sched]
@@ -273,6 +280,23 @@ def progot_solve(cl: Clouds, K: int, *, alpha_sched: str = "constant", theta: fl
     p.tau_first, p.tau_last = float(tau_first), float(tau_last)
     p.max_iter = int(max_iter)
     p.warm_start = 0 if warm_start == "alpha_k" else 1
+    return p, keep
+
+
+def _info(info, st):
+    k = info.K
+    return ProgOTInfo(k, list(info.iters[:k]), bool(info.converged), list(info.eps[:k]),
+                      list(info.alpha[:k]), list(info.err[:k]), info.seconds, st)
+
+
+def progot_solve(cl: Clouds, K: int, *, alpha_sched: str = "constant", theta: float = 1.0,
+                 eps=None, tau_first: float = 1e-3, tau_last: float = 1e-3,
+                 max_iter: int = 10_000, warm_start: str = "alpha_k", want_TX: bool = True):
+    """Alg. 2; returns (f, G, TX or None, ProgOTInfo).  eps=None uses the
+    per-step mean-cost rule with theta; an array gives an explicit schedule."""
+    torch = _torch()
+    dev = cl.X.device
+    p, keep = _params(K, alpha_sched, theta, eps, tau_first, tau_last, max_iter, warm_start)
     f = torch.empty(cl.n, dtype=torch.float32, device=dev)
     G = torch.empty((K, cl.m), dtype=torch.float32, device=dev)
     TX = torch.empty((cl.n, cl.d), dtype=torch.float32, device=dev) if want_TX else None
@@ -280,9 +304,7 @@ def progot_solve(cl: Clouds, K: int, *, alpha_sched: str = "constant", theta: fl
     st = _check(lib().pot_progot_solve(C.byref(cl.c), C.byref(p), _ptr(f), _ptr(G), _ptr(TX),
                                        C.byref(info), C.c_void_p(_stream())), "progot_solve")
     del keep
-    k = info.K
-    return f, G, TX, ProgOTInfo(k, list(info.iters[:k]), bool(info.converged), list(info.eps[:k]),
-                                list(info.alpha[:k]), list(info.err[:k]), info.seconds, st)
+    return f, G, TX, _info(info, st)
 
 
 def progot_map(cl: Clouds, G, eps, alpha, Xq, out=None):
@@ -308,6 +330,79 @@ def marginal_check(cl: Clouds, f, g, eps: float):
     _check(lib().pot_marginal_check(C.byref(cl.c), _ptr(f), _ptr(g), float(eps), out,
                                     C.c_void_p(_stream())), "marginal_check", False)
     return float(out[0]), float(out[1]), float(out[2])
+
+
+class Server:
+    """Serving form (continuous batching of ProgOT solves; see include/progot.h).
+
+    The arena (a uint8 device tensor) is the HBM budget requests are admitted
+    against.  Every call must run with the same current stream as creation."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 64, device="cuda"):
+        torch = _torch()
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.stream = _stream()
+        h = C.c_void_p()
+        _check(lib().pot_server_create(C.byref(h), _ptr(self.arena), int(arena_bytes),
+                                       int(max_active), C.c_void_p(self.stream)),
+               "server_create", False)
+        self.h = h
+        self.live = {}   # rid -> tensors the library points into
+
+    @staticmethod
+    def request_bytes(n: int, m: int, d: int) -> int:
+        return int(lib().pot_server_request_bytes(n, m, d))
+
+    @staticmethod
+    def arena_overhead(max_active: int) -> int:
+        return int(lib().pot_server_arena_overhead(max_active))
+
+    def submit(self, X, Y, K: int, *, want_TX: bool = True, **kw):
+        """Returns a request id, or None when it cannot be admitted now."""
+        torch = _torch()
+        _dev_f32(X, "X")
+        _dev_f32(Y, "Y")
+        n, d = X.shape
+        m = Y.shape[0]
+        p, keep = _params(K, **kw)
+        f = torch.empty(n, dtype=torch.float32, device=X.device)
+        G = torch.empty((K, m), dtype=torch.float32, device=X.device)
+        TX = torch.empty((n, d), dtype=torch.float32, device=X.device) if want_TX else None
+        rid = C.c_int64()
+        st = lib().pot_server_submit(self.h, _ptr(X), n, _ptr(Y), m, d, C.byref(p), _ptr(f),
+                                     _ptr(G), _ptr(TX), C.byref(rid))
+        if st == POT_BUSY:
+            return None
+        _check(st, "server_submit", False)
+        self.live[rid.value] = (X, Y, f, G, TX, keep)
+        return rid.value
+
+    def step(self):
+        """One tick; returns (n_active, n_finished_in_this_tick)."""
+        a, fin = C.c_int32(), C.c_int32()
+        _check(lib().pot_server_step(self.h, C.byref(a), C.byref(fin)), "server_step", False)
+        return a.value, fin.value
+
+    def poll(self, rid: int):
+        """None while in flight, else (f, G, TX, ProgOTInfo)."""
+        info = pot_progot_info()
+        st = lib().pot_server_poll(self.h, int(rid), C.byref(info))
+        if st == POT_BUSY:
+            return None
+        _check(st, "server_poll")
+        _, _, f, G, TX, _ = self.live.pop(rid)
+        return f, G, TX, _info(info, st)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pot_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def timing_enable(on: bool = True) -> None:

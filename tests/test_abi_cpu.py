@@ -115,3 +115,25 @@ def test_binding_refuses_cpu_tensors():
     X = torch.zeros(4, 2)
     with pytest.raises(TypeError):
         P.prepare_clouds(X, X)
+
+
+def test_server_rejects_invalid_before_device_work():
+    lib = P.lib()
+    inv = B.POT_ERR_INVALID
+    h = C.c_void_p()
+    assert P.Server.request_bytes(0, 10, 4) == 0
+    assert P.Server.request_bytes(100, 100, 64) >= P.workspace_bytes(100, 100, 64)
+    assert lib.pot_server_arena_overhead(0) == 0
+    assert lib.pot_server_arena_overhead(4) > 0
+    assert lib.pot_server_create(None, 0x1000, 1 << 30, 4, None) == inv
+    assert lib.pot_server_create(C.byref(h), None, 1 << 30, 4, None) == inv
+    assert lib.pot_server_create(C.byref(h), 0x1000, 1 << 30, 0, None) == inv
+    assert lib.pot_server_create(C.byref(h), 0x1000, 1 << 30, 100000, None) == inv
+    assert lib.pot_server_create(C.byref(h), 0x1000, 16, 4, None) == B.POT_ERR_NOMEM
+    assert lib.pot_server_step(None, None, None) == inv
+    assert lib.pot_server_poll(None, 1, None) == inv
+    assert lib.pot_server_destroy(None) == inv
+    rid = C.c_int64()
+    p = B.pot_progot_params()
+    assert lib.pot_server_submit(None, 0x1000, 8, 0x1000, 8, 4, C.byref(p), 0x1, 0x1, None,
+                                 C.byref(rid)) == inv

@@ -1,0 +1,89 @@
+"""The BF16 forms against the FP64 oracle.
+
+BF16X3 (hi/lo split, three BF16 products) must meet the same bars as FP32
+(potentials 1e-4, maps 1e-3).  Plain BF16 (one product, inputs rounded to 8
+mantissa bits) is measured and reported per result on the precision
+workload's 4096 x 4096 subsample, with a sanity bound only: its cross-term
+error ~2^-9 |x| |y| / sqrt(d) is what the form trades for speed."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.parity import pot_err, map_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available()
+    import paper_2406_05061_amd as P
+    return P
+
+
+@pytest.mark.parametrize("n,m,d", [(256, 256, 4), (1000, 777, 64), (300, 513, 100), (200, 700, 256),
+                                   (1, 9, 7)])
+def test_bf16x3_fixed_iterations(P, n, m, d):
+    X, Y = workloads.sphere(seed=200 + d, n=n, m=m, d=d, n_clusters=6)
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    eps = float(np.float32(oracle.mean_cost(X, Y) / 20.0))
+    print(f"case bf16x3 n={n} m={m} d={d}", flush=True)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision="bf16x3")
+    for it in (1, 11):
+        f, g, info = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=it)
+        ref = oracle.sinkhorn(a, X, b, Y, eps, 0.0, n_iter=it)
+        ef, eg = pot_err(f.cpu().numpy(), ref.f, eps), pot_err(g.cpu().numpy(), ref.g, eps)
+        assert ef < 1e-4 and eg < 1e-4, (it, ef, eg)
+    Q = workloads.sphere(seed=300 + d, n=min(n, 64), m=2, d=d, n_clusters=6)[0]
+    g32 = g.cpu().numpy()
+    for alpha in (1.0, 0.4):
+        out = P.entropic_map(cl, g, eps, P.to_device(Q), alpha=alpha)
+        ref_t = oracle.entropic_map(Q, Y, g32.astype(np.float64), eps, alpha=alpha)
+        assert map_err(out.cpu().numpy(), ref_t, Y) < 1e-3
+
+
+def test_precision_table(P):
+    """The precision workload's protocol on its seeded 4096 x 4096 subsample
+    (d = 256, 32 unit-norm clusters + N(0, 0.01 I)): Sinkhorn at mean cost/20
+    for a fixed 30 iterations, then the entropic map of the sources; errors
+    of FP32, BF16X3 and BF16 against FP64."""
+    X, Y = workloads.sphere(seed=3, n=65536, m=65536, d=256, n_clusters=32)
+    idx = workloads.subsample_index(65536, 4096, seed=33)
+    Xs, Ys = X[idx], Y[idx]
+    n = 4096
+    a = np.full(n, 1.0 / n)
+    eps = float(np.float32(oracle.mean_cost(Xs, Ys) / 20.0))
+    ref = oracle.sinkhorn(a, Xs, a, Ys, eps, 0.0, n_iter=30)
+    ref_t = oracle.entropic_map(Xs, Ys, ref.g, eps)
+    rows = {}
+    for prec in ("fp32", "bf16x3", "bf16"):
+        cl = P.prepare_clouds(P.to_device(Xs), P.to_device(Ys), precision=prec)
+        f, g, _ = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=30)
+        T = P.entropic_map(cl, g, eps, P.to_device(Xs))
+        # map of the oracle's potential isolates the map kernel's own error
+        T_ref_g = P.entropic_map(cl, P.to_device(ref.g.astype(np.float32)), eps, P.to_device(Xs))
+        rows[prec] = (pot_err(f.cpu().numpy(), ref.f, eps), pot_err(g.cpu().numpy(), ref.g, eps),
+                      map_err(T.cpu().numpy(), ref_t, Ys), map_err(T_ref_g.cpu().numpy(), ref_t, Ys))
+    print("precision table (4096 subsample, d=256): form  f_err  g_err  map_err  map_err(oracle g)")
+    for k, v in rows.items():
+        print(f"  {k:7s} " + "  ".join(f"{x:.2e}" for x in v), flush=True)
+    for k in ("fp32", "bf16x3"):
+        assert rows[k][0] < 1e-4 and rows[k][1] < 1e-4 and rows[k][2] < 1e-3 and rows[k][3] < 1e-3
+    assert max(rows["bf16"]) < 5e-2
+
+
+def test_progot_bf16x3_c1(P):
+    X, Y = workloads.c1(seed=1)
+    n = X.shape[0]
+    a = np.full(n, 1.0 / n)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision="bf16x3")
+    f, G, TX, info = P.progot_solve(cl, 4, tau_first=1e-3, tau_last=1e-3)
+    ref = oracle.progot(a, X, a, Y, 4, tau=1e-3)
+    assert info.converged
+    assert all(abs(p - q) <= 2 for p, q in zip(info.iters, ref.iters))
+    assert map_err(TX.cpu().numpy(), ref.TX, Y) < 1e-3
+    row, col, _ = P.marginal_check(cl, f, G[-1], info.eps[-1])
+    assert row <= 1e-3 * 1.01 and col <= 1e-4

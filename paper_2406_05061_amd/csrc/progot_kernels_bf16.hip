@@ -492,9 +492,9 @@ int bf16_dim(int d) {
 int64_t bf16_mpad(int64_t m) { return (m + 63) / 64 * 64; }
 
 // Rows per workgroup: 4 waves x QB x 16.  Each column fragment read from LDS
-// feeds QB (x3 for the split form) MFMAs, which keeps LDS traffic below its
-// bandwidth: one product per read would need ~2x the LDS bandwidth of a CU.
-constexpr int lse_qb(int npart) { return npart == 2 ? 2 : 4; }
+// feeds QB (x3 for the split form) MFMAs; QB = 2 keeps two waves per SIMD
+// (measured faster than QB = 4 at one wave per SIMD on d = 256).
+constexpr int lse_qb(int npart) { (void)npart; return 2; }
 int lse_bf16_rows_per_block(int d, int precision) {
     (void)d;
     return 64 * lse_qb(precision == 2 ? 2 : 1);

@@ -44,6 +44,10 @@ WORKLOADS = {
     "sphere64k_d256_fp32": (_SPHERE64K, 4, "fp32"),
     "sphere64k_d256_bf16": (_SPHERE64K, 4, "bf16"),
     "sphere64k_d256_bf16x3": (_SPHERE64K, 4, "bf16x3"),
+    # large map estimation: fit on 64 unit-norm clusters, then T_Prog on 2^20
+    # queries drawn from the source distribution
+    "sphere256k_d128_bf16": (dict(kind="sphere", seed=5, n=262144, m=262144, d=128,
+                                  n_clusters=64, n_query=1 << 20, query_seed=55), 8, "bf16"),
 }
 
 
@@ -244,7 +248,11 @@ def main():
         log(f"bench: copied {nbytes} bytes 3 times")
         return
     spec, K, prec = WORKLOADS[args.workload]
-    X, Y = make_clouds(spec)
+    Q = None
+    if spec.get("n_query"):
+        X, Y, Q = make_clouds(spec)
+    else:
+        X, Y = make_clouds(spec)
     n, d = X.shape
     m = Y.shape[0]
     log(f"bench: {args.workload}: n={n} m={m} d={d} K={K} {prec} tau={args.tau}")
@@ -309,6 +317,25 @@ def main():
                      "flops_per_launch": flops},
         "map_kernel": {"avg_launch_us": map_ms * 1e3 / max(map_n, 1), "launches": map_n},
     }
+    if Q is not None:
+        # out-of-sample progressive map (Alg. 3) of the fitted state
+        Qd = P.to_device(Q)
+        P.progot_map(cl, G, infos[-1].eps, infos[-1].alpha, Qd[:4096])   # warm-up
+        torch.cuda.synchronize()
+        P.timing_enable(True)
+        t0 = time.perf_counter()
+        Yq = P.progot_map(cl, G, infos[-1].eps, infos[-1].alpha, Qd)
+        torch.cuda.synchronize()
+        t_eval = time.perf_counter() - t0
+        _, _, mms, mn = P.timing_read()
+        P.timing_enable(False)
+        nq = Q.shape[0]
+        mflops = 4.0 * nq * m * d            # cross term + projection per step
+        out["eval"] = {"queries": nq, "seconds": t_eval, "queries_per_s": nq / t_eval,
+                       "map_avg_launch_us": mms * 1e3 / max(mn, 1), "launches": mn,
+                       "map_tflops": mflops / (mms * 1e-3 / max(mn, 1)) / 1e12}
+        log(f"bench: T_Prog on {nq} queries: {t_eval:.2f} s")
+        del Yq
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline (oracle, {args.cpu_sample}^2 sample) ...")
         out["cpu_baseline"] = cpu_baseline(X, Y, args.cpu_sample, args.cpu_iters)

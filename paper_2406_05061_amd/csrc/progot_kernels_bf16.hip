@@ -517,9 +517,9 @@ hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s) {
 hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     const bool x3 = a.precision == 2;
     switch (bf16_dim(a.d)) {
-        case 32: return x3 ? map_bf16_t<32, 2, 2>(a, scale2, bscale, s) : map_bf16_t<32, 2, 1>(a, scale2, bscale, s);
-        case 64: return x3 ? map_bf16_t<64, 2, 2>(a, scale2, bscale, s) : map_bf16_t<64, 2, 1>(a, scale2, bscale, s);
-        case 128: return x3 ? map_bf16_t<128, 2, 2>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1>(a, scale2, bscale, s);
+        case 32: return x3 ? map_bf16_t<32, 4, 2>(a, scale2, bscale, s) : map_bf16_t<32, 4, 1>(a, scale2, bscale, s);
+        case 64: return x3 ? map_bf16_t<64, 4, 2>(a, scale2, bscale, s) : map_bf16_t<64, 4, 1>(a, scale2, bscale, s);
+        case 128: return x3 ? map_bf16_t<128, 2, 2>(a, scale2, bscale, s) : map_bf16_t<128, 4, 1>(a, scale2, bscale, s);
         default: return x3 ? map_bf16_t<256, 1, 2>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1>(a, scale2, bscale, s);
     }
 }

@@ -48,6 +48,8 @@ WORKLOADS = {
     # queries drawn from the source distribution
     "sphere256k_d128_bf16": (dict(kind="sphere", seed=5, n=262144, m=262144, d=128,
                                   n_clusters=64, n_query=1 << 20, query_seed=55), 8, "bf16"),
+    "sphere256k_d128_bf16x3": (dict(kind="sphere", seed=5, n=262144, m=262144, d=128,
+                                    n_clusters=64, n_query=1 << 20, query_seed=55), 8, "bf16x3"),
 }
 
 
@@ -282,8 +284,10 @@ def main():
     elapsed = t1 - t0
     log(f"bench: {args.steps} solves in {elapsed:.3f} s; iters per solve {infos[-1].iters}")
 
+    tc = time.perf_counter()
     row, col, dual = P.marginal_check(cl, f, G[-1], infos[-1].eps[-1])
-    log(f"bench: final FP64 marginal L1 row {row:.3e} col {col:.3e}")
+    t_check = time.perf_counter() - tc
+    log(f"bench: final FP64 marginal L1 row {row:.3e} col {col:.3e} ({t_check * 1e3:.1f} ms)")
 
     value = n * m * iters_total / elapsed
     avg_lse_s = lse_ms * 1e-3 / max(lse_n, 1)
@@ -307,7 +311,7 @@ def main():
                    "alpha": "constant speed"},
         "solve_time_s": elapsed / args.steps,
         "sinkhorn_iters_per_solve": infos[-1].iters,
-        "final_marginal_l1_fp64": {"row": row, "col": col},
+        "final_marginal_l1_fp64": {"row": row, "col": col, "check_seconds": t_check},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec],
                      "unit": "TFLOP/s", "frac": achieved / PEAK[prec],
                      "traffic": recorded_traffic(f"lse_partial_{prec}<{PAD[d]},{QB[d]}>",

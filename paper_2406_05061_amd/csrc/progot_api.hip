@@ -47,6 +47,7 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision) {
     L.yst = take((size_t)pot::cloud_stat_blocks(m) * (d + 1) * 8);
     L.chr = take((size_t)pot::fp64_check_blocks(n) * 3 * 8);
     L.chc = take((size_t)pot::fp64_check_blocks(m) * 3 * 8);
+    L.n64 = take(((size_t)n + (size_t)m) * 8);
     L.total = off;
     return L;
 }
@@ -455,6 +456,7 @@ int pot_marginal_check(const pot_clouds *c, const float *f, const float *g, floa
     const Layout L = plan(c->n, c->m, c->d, c->precision);
     const int nbr = pot::fp64_check_blocks(c->n), nbc = pot::fp64_check_blocks(c->m);
     POT_TRY(pot::launch_fp64_check(c->xk, c->n, c->Y, c->m, c->d, f, g, c->a, c->b, eps,
+                                   at<double>(c, L.n64), at<double>(c, L.n64) + c->n,
                                    at<double>(c, L.chr), at<double>(c, L.chc), s));
     std::vector<double> hr(3 * (size_t)nbr), hc(3 * (size_t)nbc);
     POT_TRY(hipMemcpyAsync(hr.data(), at<double>(c, L.chr), hr.size() * 8, hipMemcpyDeviceToHost, s));

@@ -1,0 +1,143 @@
+// FP64 check of a coupling's marginals and dual objective (gfx950).
+//
+// For the coupling P_ij = exp((f_i + g_j - C_ij)/eps) of the entropic dual
+// (eq. entdual), one pass over rows gives r_i = sum_j P_ij, the row-marginal
+// L1 sum_i |r_i - a_i|, the mass sum_ij P_ij and <f, a>; the same kernel over
+// columns gives the column-marginal L1 and <g, b>.  Everything is FP64:
+// C_ij = |x_i|^2 + |y_j|^2 - 2 <x_i, y_j> with FP64 norms of the FP32 inputs
+// and the cross term on v_mfma_f64_16x16x4_f64 (FP64 products of the exact
+// FP32 values, FP64 accumulation), FP64 exp, FP64 sums.
+//
+// Tiling as in the FP32 potential kernel: a workgroup holds 64 rows in
+// registers (lane l of a wave owns row l%16, lane group l/16 holds features
+// [q D/4, (q+1) D/4)), streams 16-column tiles through LDS, and each lane
+// accumulates its row's sum over the columns of its accumulator slots.  The
+// FP64 accumulator layout differs from the FP32/BF16 16x16 ones: register r
+// of lane l holds tile row 4 r + l/16 (checked on the device with a probe
+// of the instruction's lane layout).
+
+#include "progot_internal.h"
+
+#include <cmath>
+
+namespace pot {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void sqnorm_f64(const float *__restrict__ X, int64_t n, int d,
+                                                  double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+        const double v = X[i * d + k];
+        s = fma(v, v, s);
+    }
+    out[i] = s;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void fp64_rowsums(
+    const float *__restrict__ U, int64_t nu, const float *__restrict__ V, int64_t nv, int d,
+    const double *__restrict__ usq, const double *__restrict__ vsq, const float *__restrict__ pu,
+    const float *__restrict__ pv, const float *__restrict__ w_in, double eps,
+    double *__restrict__ part) {
+    constexpr int KD = D / 4;
+    constexpr int BN = 16;
+    constexpr int STRIDE = D + 2;
+    __shared__ double vt[BN * STRIDE];
+    __shared__ double vb[BN];
+    __shared__ double red[256];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lq = lane >> 4;
+    const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + li;
+    const bool live = row < nu;
+
+    double ub[KD];
+#pragma unroll
+    for (int k = 0; k < KD; ++k) {
+        const int f = lq * KD + k;
+        ub[k] = (live && f < d) ? (double)U[row * d + f] : 0.0;
+    }
+    const double base = live ? (double)pu[row] - usq[row] : 0.0;   // f_i - |x_i|^2
+    const double inv_eps = 1.0 / eps;
+    double rsum = 0.0;
+
+    for (int64_t j0 = 0; j0 < nv; j0 += BN) {
+        for (int e = tid; e < BN * D; e += 256) {
+            const int r = e / D, c = e % D;
+            const int64_t j = j0 + r;
+            vt[r * STRIDE + c] = (j < nv && c < d) ? (double)V[j * d + c] : 0.0;
+        }
+        if (tid < BN) {
+            const int64_t j = j0 + tid;
+            vb[tid] = j < nv ? (double)pv[j] - vsq[j] : -INFINITY;   // g_j - |y_j|^2
+        }
+        __syncthreads();
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KD; ++s) acc = mfma_f64(vt[li * STRIDE + lq * KD + s], ub[s], acc);
+        // The FP64 16x16 accumulator interleaves its rows: register r of lane
+        // l holds row 4 r + l/16 (measured), so acc[r] = <y_{j0 + 4 r + lq}, x_row>.
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rsum += exp((base + vb[4 * r + lq] + 2.0 * acc[r]) * inv_eps);
+        __syncthreads();
+    }
+    rsum += __shfl_xor(rsum, 16);
+    rsum += __shfl_xor(rsum, 32);
+    const bool own = live && lq == 0;
+    const double w = own ? (w_in ? (double)w_in[row] : 1.0 / (double)nu) : 0.0;
+    const double vals[3] = {own ? fabs(rsum - w) : 0.0, own ? rsum : 0.0, own ? (double)pu[row] * w : 0.0};
+    for (int q = 0; q < 3; ++q) {
+        __syncthreads();
+        red[tid] = vals[q];
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) part[(int64_t)blockIdx.x * 3 + q] = red[0];
+    }
+}
+
+template <int D>
+void rowsums_t(const float *U, int64_t nu, const float *V, int64_t nv, int d, const double *usq,
+               const double *vsq, const float *pu, const float *pv, const float *w, double eps,
+               double *part, hipStream_t s) {
+    hipLaunchKernelGGL((fp64_rowsums<D>), dim3((unsigned)fp64_check_blocks(nu)), dim3(256), 0, s, U,
+                       nu, V, nv, d, usq, vsq, pu, pv, w, eps, part);
+}
+
+void rowsums(const float *U, int64_t nu, const float *V, int64_t nv, int d, const double *usq,
+             const double *vsq, const float *pu, const float *pv, const float *w, double eps,
+             double *part, hipStream_t s) {
+    if (d <= 16) rowsums_t<16>(U, nu, V, nv, d, usq, vsq, pu, pv, w, eps, part, s);
+    else if (d <= 32) rowsums_t<32>(U, nu, V, nv, d, usq, vsq, pu, pv, w, eps, part, s);
+    else if (d <= 64) rowsums_t<64>(U, nu, V, nv, d, usq, vsq, pu, pv, w, eps, part, s);
+    else if (d <= 128) rowsums_t<128>(U, nu, V, nv, d, usq, vsq, pu, pv, w, eps, part, s);
+    else rowsums_t<256>(U, nu, V, nv, d, usq, vsq, pu, pv, w, eps, part, s);
+}
+
+}  // namespace
+
+int fp64_check_blocks(int64_t n) { return (int)((n + 63) / 64); }
+
+hipError_t launch_fp64_check(const float *X, int64_t n, const float *Y, int64_t m, int d,
+                             const float *f, const float *g, const float *a, const float *b,
+                             float eps, double *xsq64, double *ysq64, double *part_rows,
+                             double *part_cols, hipStream_t s) {
+    hipLaunchKernelGGL(sqnorm_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, xsq64);
+    hipLaunchKernelGGL(sqnorm_f64, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, Y, m, d, ysq64);
+    rowsums(X, n, Y, m, d, xsq64, ysq64, f, g, a, (double)eps, part_rows, s);
+    rowsums(Y, m, X, n, d, ysq64, xsq64, g, f, b, (double)eps, part_cols, s);
+    return hipGetLastError();
+}
+
+}  // namespace pot

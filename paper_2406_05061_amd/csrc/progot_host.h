@@ -14,7 +14,8 @@ namespace host {
 
 // Workspace regions of one pair of clouds (byte offsets, 256-byte aligned).
 struct Layout {
-    size_t xk, xsq, ysq, la, lb, xlp, ylp, ytl, f0, f1, g0, g1, pm, ps, errp, errd, xst, yst, chr, chc;
+    size_t xk, xsq, ysq, la, lb, xlp, ylp, ytl, f0, f1, g0, g1, pm, ps, errp, errd, xst, yst, chr, chc,
+        n64;
     size_t total;
 };
 

@@ -122,14 +122,15 @@ hipError_t launch_bf16_rows(const float *X, int64_t n, int d, void *lp, hipStrea
 // [hi^T | lo^T], each bf16_dim(d) x bf16_mpad(m), from the row copies of Y.
 hipError_t launch_bf16_transpose(const void *lp, int64_t m, int d, void *yt, hipStream_t s);
 
-// FP64 check: row sums and column sums of P in FP64, reduced to
-// part[0..3*nb) per-block partials of (|r_i - a_i|, r_i, f_i a_i) and
-// (|c_j - b_j|, c_j, g_j b_j).  Weights a, b: caller arrays or NULL (uniform,
-// 1/n in FP64).
+// FP64 check: FP64 norms of X and Y into xsq64/ysq64 (n and m doubles),
+// then row sums and column sums of P in FP64 reduced to per-block partials
+// part[0..3*nb) of (sum |r_i - a_i|, sum r_i, sum f_i a_i) and
+// (sum |c_j - b_j|, sum c_j, sum g_j b_j).  Weights a, b: caller arrays or
+// NULL (uniform, 1/n in FP64).
 hipError_t launch_fp64_check(const float *X, int64_t n, const float *Y, int64_t m, int d,
                              const float *f, const float *g, const float *a,
-                             const float *b, float eps, double *part_rows,
-                             double *part_cols, hipStream_t s);
+                             const float *b, float eps, double *xsq64, double *ysq64,
+                             double *part_rows, double *part_cols, hipStream_t s);
 int fp64_check_blocks(int64_t n);
 
 // Launch timing (see pot_timing_enable): kind 0 = cost + log-sum-exp

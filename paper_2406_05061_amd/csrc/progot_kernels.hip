@@ -571,60 +571,6 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
     }
 }
 
-// FP64 check, one thread per "row" u: r_u = sum_v exp((pu_u + pv_v - |u - v|^2)/eps)
-// with the distance by direct differences in FP64.  Per-block partials of
-// (sum |r_u - w_u|, sum r_u, sum pu_u w_u).
-constexpr int kChkTile = 32;
-__global__ __launch_bounds__(256) void fp64_rowsums(
-    const float *__restrict__ U, int64_t nu, const float *__restrict__ V, int64_t nv, int d,
-    const float *__restrict__ pu, const float *__restrict__ pv, const float *__restrict__ w_in,
-    double eps, double *__restrict__ part) {
-    __shared__ float vt[kChkTile * 256];
-    __shared__ double vp[kChkTile];
-    __shared__ double red[256];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool live = i < nu;
-    const double fi = live ? (double)pu[i] : 0.0;
-    double rsum = 0.0;
-    for (int64_t j0 = 0; j0 < nv; j0 += kChkTile) {
-        const int nt = (int)(nv - j0 < kChkTile ? nv - j0 : kChkTile);
-        __syncthreads();
-        for (int e = threadIdx.x; e < nt * d; e += 256) vt[e] = V[j0 * d + e];
-        if ((int)threadIdx.x < nt) vp[threadIdx.x] = pv[j0 + threadIdx.x];
-        __syncthreads();
-        double dist[kChkTile];
-#pragma unroll
-        for (int jj = 0; jj < kChkTile; ++jj) dist[jj] = 0.0;
-        if (live) {
-            for (int k = 0; k < d; ++k) {
-                const double x = U[i * d + k];
-#pragma unroll
-                for (int jj = 0; jj < kChkTile; ++jj) {
-                    if (jj < nt) {
-                        const double df = x - (double)vt[jj * d + k];
-                        dist[jj] = fma(df, df, dist[jj]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int jj = 0; jj < kChkTile; ++jj)
-                if (jj < nt) rsum += exp((fi + vp[jj] - dist[jj]) / eps);
-        }
-    }
-    const double w = live ? (w_in ? (double)w_in[i] : 1.0 / (double)nu) : 0.0;
-    const double vals[3] = {live ? fabs(rsum - w) : 0.0, rsum, fi * w};
-    for (int q = 0; q < 3; ++q) {
-        __syncthreads();
-        red[threadIdx.x] = vals[q];
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 3 + q] = red[0];
-    }
-}
-
 template <int D, int QB>
 hipError_t lse_launch_t(const LseJob &j, hipStream_t s) {
     // the plan must cover every row tile of this kernel variant
@@ -790,19 +736,6 @@ hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s) {
     }
     timing_end(slot, s);
     return e;
-}
-
-int fp64_check_blocks(int64_t n) { return (int)((n + 255) / 256); }
-
-hipError_t launch_fp64_check(const float *X, int64_t n, const float *Y, int64_t m, int d,
-                             const float *f, const float *g, const float *a,
-                             const float *b, float eps, double *part_rows,
-                             double *part_cols, hipStream_t s) {
-    hipLaunchKernelGGL(fp64_rowsums, dim3(fp64_check_blocks(n)), dim3(256), 0, s, X, n, Y, m, d, f,
-                       g, a, (double)eps, part_rows);
-    hipLaunchKernelGGL(fp64_rowsums, dim3(fp64_check_blocks(m)), dim3(256), 0, s, Y, m, X, n, d, g,
-                       f, b, (double)eps, part_cols);
-    return hipGetLastError();
 }
 
 }  // namespace pot

@@ -22,6 +22,9 @@ FLAGS = [
     "-Wall", "-Wno-unused-result", "-fvisibility=hidden",
     # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in VGPRs: the epilogues read every accumulator element, and
+    # the AGPR form costs one v_accvgpr_read per element
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", str(ROOT / "include"),
 ]
 

@@ -32,8 +32,8 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision) {
     // transposed target copy used by the projection product.
     const bool lp = precision != POT_PREC_FP32;
     const size_t Dp = (size_t)pot::bf16_dim(d);
-    L.xlp = take(lp ? 2 * (size_t)n * Dp * 2 : 0);
-    L.ylp = take(lp ? 2 * (size_t)m * Dp * 2 : 0);
+    L.xlp = take(lp ? 2 * (size_t)pot::bf16_mpad(n) * Dp * 2 : 0);
+    L.ylp = take(lp ? 2 * (size_t)pot::bf16_mpad(m) * Dp * 2 : 0);
     L.ytl = take(lp ? 2 * Dp * (size_t)pot::bf16_mpad(m) * 2 : 0);
     L.f0 = take((size_t)n * 4);
     L.f1 = take((size_t)n * 4);
@@ -103,7 +103,7 @@ int enqueue_prepare(pot_clouds *c, const Layout &L, double *host, hipStream_t s)
     POT_TRY(pot::launch_log_weights(c->b, c->m, c->log_b, s));
     POT_TRY(pot::launch_cloud_prep(c->Y, c->m, c->d, c->y_sqn, c->y_lp, at<double>(c, L.yst),
                                    pot::cloud_stat_blocks(c->m), s));
-    if (c->yt_lp) POT_TRY(pot::launch_bf16_transpose(c->y_lp, c->m, c->d, c->yt_lp, s));
+    if (c->yt_lp) POT_TRY(pot::launch_bf16_transpose(c->Y, c->m, c->d, c->yt_lp, s));
     return enqueue_moments(c, L, host, s);
 }
 

@@ -22,12 +22,13 @@ constexpr int kReduceBlock = 256;   // threads of the per-row kernels
 // pot_old is set, the per-block row-marginal error partials.
 struct LseJob {
     const float *U;        // rows (nu x d)
-    const void *U_lp;      // BF16 [hi | lo] copy of U (BF16 forms)
+    const void *U_lp;      // BF16 [hi | lo] copy of U (BF16 forms; unused by the kernels,
+                           // which split the scaled FP32 rows themselves)
     int64_t nu;
     const float *usq;      // |u_i|^2
     const float *logw;     // log weights of the rows
     const float *V;        // columns (nv x d)
-    const void *V_lp;
+    const void *V_lp;      // BF16 [hi | lo] copy of V, bf16_mpad(nv) rows per part
     int64_t nv;
     const float *vsq;      // |v_j|^2
     const float *vpot;     // potential of the columns (NULL = 0)
@@ -105,7 +106,7 @@ struct MapArgs {
     float eps, alpha;
     int d, precision;
     const void *YT_lp;     // transposed BF16 copy of Y (BF16 forms)
-    int64_t mp;            // row stride of YT_lp
+    int64_t mp;            // bf16_mpad(m): rows of Y_lp per part, row stride of YT_lp
     float *Xout;           // may alias Xq
     float *out_sqn;        // |Xout_i|^2 (nullable)
 };
@@ -113,14 +114,16 @@ hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s);
 
 // BF16 forms (precision 1: one BF16 product; 2: hi/lo split, three products).
 int bf16_dim(int d);                 // padded dimension of the BF16 copies
-int64_t bf16_mpad(int64_t m);        // padded column count of the transposed copy
+int64_t bf16_mpad(int64_t m);        // padded row count of the BF16 copies (multiple of 64)
 int lse_bf16_rows_per_block(int d, int precision);
 hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s);  // planned job
 hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s);
-// [hi | lo] BF16 copies of the rows of X (each n x bf16_dim(d), zero padded).
+// [hi | lo] BF16 copies of the rows of X (each bf16_mpad(n) x bf16_dim(d),
+// zero padded, in the tile layout of the BF16 kernels).
 hipError_t launch_bf16_rows(const float *X, int64_t n, int d, void *lp, hipStream_t s);
-// [hi^T | lo^T], each bf16_dim(d) x bf16_mpad(m), from the row copies of Y.
-hipError_t launch_bf16_transpose(const void *lp, int64_t m, int d, void *yt, hipStream_t s);
+// [hi^T | lo^T] of Y, each bf16_dim(d) x bf16_mpad(m) in blocks of 32
+// columns (permuted into the projection product's order, tile layout).
+hipError_t launch_bf16_transpose(const float *Y, int64_t m, int d, void *yt, hipStream_t s);
 
 // FP64 check: FP64 norms of X and Y into xsq64/ysq64 (n and m doubles),
 // then row sums and column sums of P in FP64 reduced to per-block partials

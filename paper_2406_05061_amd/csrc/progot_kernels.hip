@@ -627,6 +627,8 @@ void plan_lse_job(LseJob &j) {
     if (S < 1) S = 1;
     j.S = (int)S;
     j.cps = (j.nv + S - 1) / S;
+    // BF16 splits start on the 64-row boundaries of the padded column copy
+    if (j.precision != 0) j.cps = (j.cps + 63) / 64 * 64;
     j.scale2 = 2.f * kLog2e / j.eps;
     j.bscale = kLog2e / j.eps;
     j.blocks = tiles * S;

@@ -2,23 +2,40 @@
 // kernel (gfx950, v_mfma_f32_16x16x32_bf16).
 //
 // Only the cross term <u_i, v_j> changes arithmetic: its operands are BF16
-// copies (round to nearest even) of the FP32 clouds, accumulated in FP32.
-// With NPART = 2 each value is split as hi + lo (hi = bf16(x), lo =
-// bf16(x - hi)) and the cross term is hi*hi + hi*lo + lo*hi: three products
-// whose error is ~2^-16 relative instead of 2^-8.  Norms, the log-sum-exp,
-// potentials and marginal errors stay FP32, as in the FP32 form.
+// (round to nearest even), accumulated in FP32.  With NPART = 2 each value is
+// split as hi + lo (hi = bf16(x), lo = bf16(x - hi)) and the cross term is
+// hi*hi + hi*lo + lo*hi: three products whose error is ~2^-16 relative
+// instead of 2^-8.  Norms, the log-sum-exp, potentials and marginal errors
+// stay FP32, as in the FP32 form.
 //
-// Shadow layouts (device, written by cloud_norms / bf16_transpose):
-//   rows:        [hi | lo], each n x D bf16, D = padded dimension, zero padded
-//   transposed:  [hi | lo], each D x mp bf16 (mp = m rounded up to 64), used
-//                as the A operand of the projection product.
+// On gfx950 the MFMA, the VALU and the transcendental unit of a SIMD do not
+// overlap in practice (measured: their issue times add), so these kernels
+// are written to issue as few VALU instructions per (row, column) pair as
+// possible:
+//   * the row operand is held in registers already multiplied by
+//     scale2 = 2 log2(e)/eps (converted from the FP32 rows in the kernel),
+//   * the column bias beta_j enters as the accumulator's initial value, so
+//     the MFMA output is the log2-domain exponent itself,
+//   * the column copies are padded to whole tiles, so tile loads carry no
+//     bounds checks,
+//   * MFMA results live in VGPRs (the library is built with the VGPR form).
+// What remains per pair is a max (half a v_max3), a subtraction, an exp2
+// and an add for the log-sum-exp.
+//
+// Shadow layouts (device, written by bf16_split_rows / bf16_transpose, both
+// in the tile layout described below):
+//   rows:        [hi | lo], each np x D bf16, np = rows rounded up to 64,
+//                D = padded dimension, zero padded
+//   transposed:  [hi | lo], each D x np bf16 in blocks of 32 columns: within
+//                a block, position k holds column perm32(k), the order in
+//                which the projection product consumes them (below).
 //
 // MFMA 16x16x32 bf16: lane l holds A[l%16][8(l/16)..+7] and
-// B[8(l/16)..+7][l%16]; the accumulator holds D[4(l/16)+r][l%16].  As in the
-// FP32 kernels the column tile is the A operand, so lane l owns row i = l%16.
-// Lane group q holds the features [q D/4, (q+1) D/4); MFMA step s uses its
-// features q D/4 + 8s .. + 7 (the k index 8q + e maps to feature
-// q D/4 + 8s + e on both operands).
+// B[8(l/16)..+7][l%16]; the accumulator holds D[4(l/16)+r][l%16].  The
+// column tile is the A operand, so lane l owns row i = l%16.  Lane group q
+// holds the features [q D/4, (q+1) D/4); MFMA step s uses its features
+// q D/4 + 8s .. + 7 (the k index 8q + e maps to feature q D/4 + 8s + e on
+// both operands).
 
 #include "progot_internal.h"
 #include "progot_device.h"
@@ -28,7 +45,6 @@ namespace {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -36,26 +52,79 @@ __device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
 
 __device__ __forceinline__ bf8 bf8_zero() { return __builtin_bit_cast(bf8, u4{0u, 0u, 0u, 0u}); }
 
+// Keeps an operand computed before the tile loop in its registers: without
+// this the compiler re-derives the BF16 row operands from the FP32 rows in
+// every iteration (a v_mul and a v_cvt_pk per element).
+__device__ __forceinline__ void pin(bf8 &x) {
+    u4 t = __builtin_bit_cast(u4, x);
+    asm volatile("" : "+v"(t));
+    x = __builtin_bit_cast(bf8, t);
+}
+
+// The lane's D/4 features of row `row` of U times `scale`, as hi (and lo)
+// BF16 B operands of the KS = D/32 MFMA steps (zero beyond nu and d).
+template <int D, int NPART>
+__device__ __forceinline__ void scaled_row_operand(const float *__restrict__ U, int64_t nu, int d,
+                                                   int64_t row, int lq, float scale,
+                                                   bf8 (&ub)[NPART][D / 32]) {
+    float u[D / 4];
+    row_fetch<D>(U, nu, d, row, lq, u);
+#pragma unroll
+    for (int s = 0; s < D / 32; ++s) {
+        bf8 h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float v = u[8 * s + e] * scale;
+            const __bf16 hv = (__bf16)v;
+            h[e] = hv;
+            l[e] = (__bf16)(v - (float)hv);
+        }
+        ub[0][s] = h;
+        pin(ub[0][s]);
+        if constexpr (NPART == 2) {
+            ub[1][s] = l;
+            pin(ub[1][s]);
+        }
+    }
+}
+
+// Tile layout, in global memory and in LDS alike.  On gfx950 a ds_read_b128
+// is conflict-free when each group of 16 consecutive lanes reads 16
+// consecutive 16-byte chunks (one 256-byte block); padded row strides, which
+// suffice on other parts, measured 2-way conflicted.  Rows are therefore
+// stored "16 rows per chunk column": chunk c (8 bf16) of row j, with C
+// chunks per row, sits at chunk index ((j / 16) * C + c) * 16 + j % 16.  The
+// MFMA operand read of lane (li, lq) -- row 16 b + li, chunk c(lq) -- is one
+// 256-byte block per lane group.  The BF16 copies are written in this
+// layout, so a tile of whole 16-row blocks is one contiguous range: thread i
+// loads chunk i (1 KiB contiguous per wave instruction) and stores it to
+// LDS chunk i.
+__device__ __forceinline__ int tile_chunk(int blk16, int C, int c, int li) {
+    return ((blk16 * C) + c) * 16 + li;
+}
+
 template <int D, int NPART> struct TileH {
     static constexpr int BN = (D * NPART >= 512) ? 32 : 64;  // columns per LDS tile
     static constexpr int NSUB = BN / 16;
     static constexpr int KS = D / 32;        // MFMA k-steps over the features
-    static constexpr int KL = D / 4;         // features per lane group
-    static constexpr int STRIDE = D + 8;     // bf16 per LDS row (16-byte pad)
-    static constexpr int NCH = BN * D / 8;   // 16-byte chunks per part
-    static constexpr int PER_T = (NCH + 255) / 256;
+    static constexpr int C = D / 8;          // 16-byte chunks per column
+    static constexpr int NCH = BN * C;       // 16-byte chunks per part
+    static constexpr int PER_T = NCH / 256;
+    static_assert(NCH % 256 == 0, "tile chunks must cover the workgroup");
 };
 
-// Partial log-sum-exp over one column split (BF16 cross term).
+// Partial log-sum-exp over one column split (BF16 cross term).  Splits start
+// on multiples of 64 columns and the column copy is padded to 64 rows, so
+// every tile load is in bounds; columns past the split get beta = kNegBig.
 template <int D, int QB, int NPART>
 __global__ __launch_bounds__(256) void lse_partial_bf16(
-    const __bf16 *__restrict__ Ulp, int64_t nu, const __bf16 *__restrict__ Vlp, int64_t nv,
-    const float *__restrict__ vsq, const float *__restrict__ vpot, float gamma, float scale2,
-    float bscale, int S, int64_t cols_per_split, float *__restrict__ part_m,
+    const float *__restrict__ U, int64_t nu, int d, const __bf16 *__restrict__ Vlp, int64_t nv,
+    int64_t vstride, const float *__restrict__ vsq, const float *__restrict__ vpot, float gamma,
+    float scale2, float bscale, int S, int64_t cols_per_split, float *__restrict__ part_m,
     float *__restrict__ part_s) {
     using T = TileH<D, NPART>;
     constexpr int ROWS = 64 * QB;
-    __shared__ __bf16 vt[2][NPART][T::BN * T::STRIDE];
+    __shared__ __bf16 vt[2][NPART][T::BN * D];
     __shared__ float bt[2][T::BN];
 
     const int tid = threadIdx.x;
@@ -67,16 +136,8 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
 
     bf8 ub[QB][NPART][T::KS];
 #pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-        const int64_t row = row0 + qb * 16 + li;
-#pragma unroll
-        for (int p = 0; p < NPART; ++p)
-#pragma unroll
-            for (int s = 0; s < T::KS; ++s)
-                ub[qb][p][s] = row < nu ? *reinterpret_cast<const bf8 *>(
-                                              Ulp + (int64_t)p * nu * D + row * D + lq * T::KL + 8 * s)
-                                        : bf8_zero();
-    }
+    for (int qb = 0; qb < QB; ++qb)
+        scaled_row_operand<D, NPART>(U, nu, d, row0 + qb * 16 + li, lq, scale2, ub[qb]);
 
     float run_m[QB], run_s[QB];
 #pragma unroll
@@ -85,46 +146,33 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
     const int64_t c0 = (int64_t)split * cols_per_split;
     const int64_t c1 = c0 + cols_per_split < nv ? c0 + cols_per_split : nv;
     const int ntiles = c0 < c1 ? (int)((c1 - c0 + T::BN - 1) / T::BN) : 0;
-
     u4 pre[NPART][T::PER_T];
     float bpre = 0.f;
-    auto fetch = [&](int64_t j0) {
+    auto fetch = [&](int t) {
+        // uniform tile base, 32-bit per-lane offsets
 #pragma unroll
-        for (int p = 0; p < NPART; ++p)
+        for (int p = 0; p < NPART; ++p) {
+            const __bf16 *src = Vlp + p * vstride + (c0 + (int64_t)t * T::BN) * D;
 #pragma unroll
-            for (int r = 0; r < T::PER_T; ++r) {
-                const int c = tid + 256 * r;
-                u4 v = {0u, 0u, 0u, 0u};
-                if (c < T::NCH) {
-                    const int row = c / (D / 8);
-                    const int col = (c % (D / 8)) * 8;
-                    const int64_t j = j0 + row;
-                    if (j < c1) v = *reinterpret_cast<const u4 *>(Vlp + (int64_t)p * nv * D + j * D + col);
-                }
-                pre[p][r] = v;
-            }
+            for (int r = 0; r < T::PER_T; ++r)
+                pre[p][r] = *reinterpret_cast<const u4 *>(src + (tid + 256 * r) * 8);
+        }
         if (tid < T::BN) {
-            const int64_t j = j0 + tid;
-            bpre = j < c1 ? ((vpot ? gamma * vpot[j] : 0.f) - vsq[j]) * bscale : -INFINITY;
+            const int64_t j = c0 + (int64_t)t * T::BN + tid;
+            bpre = j < c1 ? ((vpot ? gamma * vpot[j] : 0.f) - vsq[j]) * bscale : kNegBig;
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
         for (int p = 0; p < NPART; ++p)
 #pragma unroll
-            for (int r = 0; r < T::PER_T; ++r) {
-                const int c = tid + 256 * r;
-                if (c < T::NCH) {
-                    const int row = c / (D / 8);
-                    const int col = (c % (D / 8)) * 8;
-                    *reinterpret_cast<u4 *>(&vt[buf][p][row * T::STRIDE + col]) = pre[p][r];
-                }
-            }
+            for (int r = 0; r < T::PER_T; ++r)
+                *reinterpret_cast<u4 *>(&vt[buf][p][(tid + 256 * r) * 8]) = pre[p][r];
         if (tid < T::BN) bt[buf][tid] = bpre;
     };
 
     if (ntiles > 0) {
-        fetch(c0);
+        fetch(0);
         store(0);
     }
     __syncthreads();
@@ -132,14 +180,17 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
     for (int t = 0; t < ntiles; ++t) {
         const int buf = t & 1;
         const bool more = t + 1 < ntiles;
-        if (more) fetch(c0 + (int64_t)(t + 1) * T::BN);
-        // k outer, (column subtile, row block) inner: NSUB x QB independent
-        // accumulation chains keep the MFMA pipe busy.
+        if (more) fetch(t + 1);
+        // accumulators start at beta_j: the MFMA output is the exponent
         f4 acc[QB][T::NSUB];
 #pragma unroll
-        for (int sub = 0; sub < T::NSUB; ++sub)
+        for (int sub = 0; sub < T::NSUB; ++sub) {
+            const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = beta;
+        }
+        // k outer, (column subtile, row block) inner: NSUB x QB independent
+        // accumulation chains keep the MFMA pipe busy.
 #pragma unroll
         for (int s = 0; s < T::KS; ++s) {
             bf8 a[NPART][T::NSUB];
@@ -148,7 +199,7 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
 #pragma unroll
                 for (int sub = 0; sub < T::NSUB; ++sub)
                     a[p][sub] = *reinterpret_cast<const bf8 *>(
-                        &vt[buf][p][(sub * 16 + li) * T::STRIDE + lq * T::KL + 8 * s]);
+                        &vt[buf][p][tile_chunk(sub, T::C, lq * T::KS + s, li) * 8]);
 #pragma unroll
             for (int sub = 0; sub < T::NSUB; ++sub)
 #pragma unroll
@@ -160,27 +211,20 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
                     }
                 }
         }
-        f4 beta[T::NSUB];
-#pragma unroll
-        for (int sub = 0; sub < T::NSUB; ++sub)
-            beta[sub] = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
-            float tv[T::NSUB * 4];
             float mx = kNegBig;
 #pragma unroll
             for (int sub = 0; sub < T::NSUB; ++sub)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float x = fmaf(acc[qb][sub][r], scale2, beta[sub][r]);
-                    tv[sub * 4 + r] = x;
-                    mx = fmaxf(mx, x);
-                }
+                for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
             const float mn = fmaxf(run_m[qb], mx);
-            float s = 0.f;
+            float s4[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int e = 0; e < T::NSUB * 4; ++e) s += ex2(tv[e] - mn);
-            run_s[qb] = fmaf(run_s[qb], ex2(run_m[qb] - mn), s);
+            for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) s4[r] += ex2(acc[qb][sub][r] - mn);
+            run_s[qb] = fmaf(run_s[qb], ex2(run_m[qb] - mn), (s4[0] + s4[1]) + (s4[2] + s4[3]));
             run_m[qb] = mn;
         }
         if (more) store(buf ^ 1);
@@ -206,10 +250,29 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
     }
 }
 
-// Entropic map + McCann-type step, BF16 cross term and a BF16 projection
-// product P (rounded) x (Y_hi + Y_lo); the normaliser sums the rounded P, so
-// T is an exact convex combination of the targets with perturbed weights.
+// Position k of a 32-column group of the transposed copy holds column
+// perm32(k): the B operand of the projection product takes, in lane group q,
+// the columns 4q..4q+3 of the first score subtile and then the same four of
+// the second (the accumulator layout of the score tile), so k = 8q + e is
+// column 4q + e (e < 4) or 16 + 4q + e - 4 (e >= 4).
+__host__ __device__ constexpr int perm32(int k) {
+    return (k & 7) < 4 ? 4 * (k >> 3) + (k & 7) : 16 + 4 * (k >> 3) + (k & 7) - 4;
+}
+
+// Entropic map + McCann-type step.  The projection product is P x (Y_hi +
+// Y_lo) with P rounded to BF16 (NPART = 1) or split as P_hi + P_lo with the
+// three products P_hi Y_hi + P_hi Y_lo + P_lo Y_hi (NPART = 2, so both
+// products of the split form carry ~16 bits).  The normaliser is the same
+// product against a row of ones, so it sums exactly the weights applied to
+// the targets: T is a convex combination of the targets.
+// P = 2^(t - m_used) with m_used the running maximum.  The output
+// accumulator is rescaled only in tiles where some row of the wave sets a new
+// maximum (a row does so about log(tiles) times for columns in random
+// order), not in every tile.  The threshold stays 0: with m_used exactly the
+// maximum, the largest weight of each row is 1.0, exact in BF16 (a stale
+// maximum rounds it too and measurably doubles the map's rounding error).
 constexpr int kMapBN = 32;
+constexpr float kLazy = 0.f;
 
 template <int D, int QB, int NPART>
 __global__ __launch_bounds__(256) void entropic_map_bf16(
@@ -218,16 +281,14 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout,
     float *__restrict__ out_sqn) {
     constexpr int BN = kMapBN;
-    constexpr int KS = D / 32, KL = D / 4, STRIDE = D + 8;
-    constexpr int TSTRIDE = BN + 8;
+    constexpr int KS = D / 32, C = D / 8;
     constexpr int NDB = D / 16;
     constexpr int ROWS = 64 * QB;
-    constexpr int NCH = BN * D / 8;            // row-major chunks per part
+    constexpr int NCH = BN * D / 8;            // 16-byte chunks per part (both copies)
     constexpr int PER_T = (NCH + 255) / 256;
-    constexpr int NCHT = D * BN / 8;           // transposed chunks per part
-    constexpr int PER_TT = (NCHT + 255) / 256;
-    __shared__ __bf16 yr[2][NPART][BN * STRIDE];
-    __shared__ __bf16 ytr[2][2][D * TSTRIDE];
+    // row tile: BN columns x C chunks; transposed tile: D dims x 4 chunks
+    __shared__ __bf16 yr[2][NPART][BN * D];
+    __shared__ __bf16 ytr[2][2][D * BN];
     __shared__ float bt[2][BN];
 
     const int tid = threadIdx.x;
@@ -235,97 +296,62 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     const int li = lane & 15, lq = lane >> 4;
     const int64_t row0 = (int64_t)blockIdx.x * ROWS + wave * (QB * 16);
 
-    // queries: FP32 rows -> hi (+ lo) BF16 B operands
     bf8 ub[QB][NPART][KS];
 #pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-        float u[KL];
-        row_fetch<D>(Xq, nq, d, row0 + qb * 16 + li, lq, u);
+    for (int qb = 0; qb < QB; ++qb)
+        scaled_row_operand<D, NPART>(Xq, nq, d, row0 + qb * 16 + li, lq, scale2, ub[qb]);
+
+    // A operand of the normaliser: a row of ones (output row 0)
+    bf8 ones = bf8_zero();
+    if (li == 0) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            bf8 h, l;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const __bf16 hv = (__bf16)u[8 * s + e];
-                h[e] = hv;
-                l[e] = (__bf16)(u[8 * s + e] - (float)hv);
-            }
-            ub[qb][0][s] = h;
-            if constexpr (NPART == 2) ub[qb][1][s] = l;
-        }
+        for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
     }
 
-    float run_m[QB], run_l[QB];
-    f4 o[QB][NDB];
+    float m_used[QB];
+    f4 o[QB][NDB], on[QB];
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-        run_m[qb] = kNegBig;
-        run_l[qb] = 0.f;
+        m_used[qb] = kNegBig;
+        on[qb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int db = 0; db < NDB; ++db) o[qb][db] = f4{0.f, 0.f, 0.f, 0.f};
     }
 
     const int ntiles = (int)((m + BN - 1) / BN);
     u4 pre[NPART][PER_T];
-    u4 pret[2][PER_TT];
+    u4 pret[2][PER_T];
     float bpre = 0.f;
-    auto fetch = [&](int64_t j0) {
+    auto fetch = [&](int t) {
+        const int64_t j0 = (int64_t)t * BN;
 #pragma unroll
-        for (int p = 0; p < NPART; ++p)
+        for (int r = 0; r < PER_T; ++r) {
+            const int c = tid + 256 * r;
+            if (NCH % 256 == 0 || c < NCH) {
 #pragma unroll
-            for (int r = 0; r < PER_T; ++r) {
-                const int c = tid + 256 * r;
-                u4 v = {0u, 0u, 0u, 0u};
-                if (c < NCH) {
-                    const int row = c / (D / 8);
-                    const int col = (c % (D / 8)) * 8;
-                    const int64_t j = j0 + row;
-                    if (j < m) v = *reinterpret_cast<const u4 *>(Ylp + (int64_t)p * m * D + j * D + col);
-                }
-                pre[p][r] = v;
+                for (int p = 0; p < NPART; ++p)
+                    pre[p][r] = *reinterpret_cast<const u4 *>(Ylp + (p * mp + j0) * D + c * 8);
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+                    pret[p][r] = *reinterpret_cast<const u4 *>(YTlp + (p * mp + j0) * D + c * 8);
             }
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int r = 0; r < PER_TT; ++r) {
-                const int c = tid + 256 * r;
-                u4 v = {0u, 0u, 0u, 0u};
-                if (c < NCHT) {
-                    const int dd = c / (BN / 8);
-                    const int jc = (c % (BN / 8)) * 8;
-                    // mp is a multiple of 64 >= every tile end, padding is zero
-                    v = *reinterpret_cast<const u4 *>(YTlp + (int64_t)p * D * mp + (int64_t)dd * mp + j0 + jc);
-                }
-                pret[p][r] = v;
-            }
+        }
         if (tid < BN) {
             const int64_t j = j0 + tid;
-            bpre = j < m ? (g[j] - ysq[j]) * bscale : -INFINITY;
+            bpre = j < m ? (g[j] - ysq[j]) * bscale : kNegBig;
         }
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int p = 0; p < NPART; ++p)
+        for (int r = 0; r < PER_T; ++r) {
+            const int c = tid + 256 * r;
+            if (NCH % 256 == 0 || c < NCH) {
 #pragma unroll
-            for (int r = 0; r < PER_T; ++r) {
-                const int c = tid + 256 * r;
-                if (c < NCH) {
-                    const int row = c / (D / 8);
-                    const int col = (c % (D / 8)) * 8;
-                    *reinterpret_cast<u4 *>(&yr[buf][p][row * STRIDE + col]) = pre[p][r];
-                }
+                for (int p = 0; p < NPART; ++p) *reinterpret_cast<u4 *>(&yr[buf][p][c * 8]) = pre[p][r];
+#pragma unroll
+                for (int p = 0; p < 2; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
             }
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int r = 0; r < PER_TT; ++r) {
-                const int c = tid + 256 * r;
-                if (c < NCHT) {
-                    const int dd = c / (BN / 8);
-                    const int jc = (c % (BN / 8)) * 8;
-                    *reinterpret_cast<u4 *>(&ytr[buf][p][dd * TSTRIDE + jc]) = pret[p][r];
-                }
-            }
+        }
         if (tid < BN) bt[buf][tid] = bpre;
     };
 
@@ -338,20 +364,21 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     for (int t = 0; t < ntiles; ++t) {
         const int buf = t & 1;
         const bool more = t + 1 < ntiles;
-        if (more) fetch((int64_t)(t + 1) * BN);
+        if (more) fetch(t + 1);
         f4 acc[QB][2];
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
+            const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
             bf8 a[NPART][KS];
 #pragma unroll
             for (int p = 0; p < NPART; ++p)
 #pragma unroll
                 for (int s = 0; s < KS; ++s)
                     a[p][s] = *reinterpret_cast<const bf8 *>(
-                        &yr[buf][p][(sub * 16 + li) * STRIDE + lq * KL + 8 * s]);
+                        &yr[buf][p][tile_chunk(sub, C, lq * KS + s, li) * 8]);
 #pragma unroll
             for (int qb = 0; qb < QB; ++qb) {
-                f4 c = {0.f, 0.f, 0.f, 0.f};
+                f4 c = beta;
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
                     c = mfma_bf(a[0][s], ub[qb][0][s], c);
@@ -363,45 +390,52 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
                 acc[qb][sub] = c;
             }
         }
-        const f4 beta0 = *reinterpret_cast<const f4 *>(&bt[buf][lq * 4]);
-        const f4 beta1 = *reinterpret_cast<const f4 *>(&bt[buf][16 + lq * 4]);
+        bf8 pb[QB], pl[NPART == 2 ? QB : 1];
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
-            float p[8];
             float mx = kNegBig;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                p[r] = fmaf(acc[qb][0][r], scale2, beta0[r]);
-                p[4 + r] = fmaf(acc[qb][1][r], scale2, beta1[r]);
-                mx = fmaxf(mx, fmaxf(p[r], p[4 + r]));
-            }
+            for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
             mx = fmaxf(mx, __shfl_xor(mx, 16));
             mx = fmaxf(mx, __shfl_xor(mx, 32));
-            const float mn = fmaxf(run_m[qb], mx);
-            const float cs = ex2(run_m[qb] - mn);
-            run_m[qb] = mn;
-            bf8 pb;
-            float s = 0.f;
+            const bool up = mx > m_used[qb] + kLazy;
+            if (__builtin_amdgcn_ballot_w64(up)) {
+                const float mn = up ? mx : m_used[qb];
+                const float cs = ex2(m_used[qb] - mn);
+                m_used[qb] = mn;
+                on[qb] *= cs;
+#pragma unroll
+                for (int db = 0; db < NDB; ++db) o[qb][db] *= cs;
+            }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const __bf16 v = (__bf16)ex2(p[e] - mn);
-                pb[e] = v;
-                s += (float)v;
+                const float v = ex2(acc[qb][e >> 2][e & 3] - m_used[qb]);
+                const __bf16 h = (__bf16)v;
+                pb[qb][e] = h;
+                if constexpr (NPART == 2) pl[qb][e] = (__bf16)(v - (float)h);
             }
-            run_l[qb] = fmaf(run_l[qb], cs, s);
+        }
+        // O^T += Y^T P^T: each Y^T fragment (16 dims x 32 columns) is read
+        // once and feeds the QB row blocks
 #pragma unroll
-            for (int db = 0; db < NDB; ++db) {
-                f4 acc_o = o[qb][db] * cs;
+        for (int db = 0; db < NDB; ++db)
 #pragma unroll
-                for (int p2 = 0; p2 < 2; ++p2) {
-                    const __bf16 *row = &ytr[buf][p2][(db * 16 + li) * TSTRIDE + 4 * lq];
-                    const u2 lo4 = *reinterpret_cast<const u2 *>(row);
-                    const u2 hi4 = *reinterpret_cast<const u2 *>(row + 16);
-                    const bf8 av = __builtin_bit_cast(bf8, u4{lo4.x, lo4.y, hi4.x, hi4.y});
-                    acc_o = mfma_bf(av, pb, acc_o);
+            for (int p2 = 0; p2 < 2; ++p2) {
+                const bf8 av =
+                    *reinterpret_cast<const bf8 *>(&ytr[buf][p2][tile_chunk(db, 4, lq, li) * 8]);
+#pragma unroll
+                for (int qb = 0; qb < QB; ++qb) {
+                    o[qb][db] = mfma_bf(av, pb[qb], o[qb][db]);
+                    if constexpr (NPART == 2)
+                        if (p2 == 0) o[qb][db] = mfma_bf(av, pl[qb], o[qb][db]);
                 }
-                o[qb][db] = acc_o;
             }
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+            on[qb] = mfma_bf(ones, pb[qb], on[qb]);
+            if constexpr (NPART == 2) on[qb] = mfma_bf(ones, pl[qb], on[qb]);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -409,9 +443,8 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-        float l = run_l[qb];
-        l += __shfl_xor(l, 16);
-        l += __shfl_xor(l, 32);
+        // the normaliser of row li sits in output row 0: lane li, register 0
+        const float l = __shfl(on[qb][0], li);
         const float inv = 1.f / l;
         const int64_t row = row0 + qb * 16 + li;
         double sq = 0.0;
@@ -437,42 +470,62 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     }
 }
 
-// BF16 hi/lo row copies with zero padding to D: lp = [hi | lo], each n x D.
+// BF16 hi/lo copies of the rows of X in the tile layout, rows padded to
+// np = bf16_mpad(n) and features to D with zeros: element (i, k) of part p
+// at p np D + ((i / 16) (D / 8) + k / 8) 128 + (i % 16) 8 + k % 8.  One
+// thread per destination element.
 __global__ __launch_bounds__(256) void bf16_split_rows(const float *__restrict__ X, int64_t n, int d,
-                                                       int D, __bf16 *__restrict__ lp) {
+                                                       int D, int64_t np, __bf16 *__restrict__ lp) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n * D) return;
-    const int64_t i = e / D;
-    const int k = (int)(e % D);
-    const float x = k < d ? X[i * d + k] : 0.f;
+    if (e >= np * D) return;
+    const int C = D / 8;
+    const int64_t bc = e >> 7;                    // (i / 16) C + k / 8
+    const int64_t i = (bc / C) * 16 + ((e >> 3) & 15);
+    const int k = (int)(bc % C) * 8 + (int)(e & 7);
+    const float x = (i < n && k < d) ? X[i * d + k] : 0.f;
     const __bf16 h = (__bf16)x;
     lp[e] = h;
-    lp[n * D + e] = (__bf16)(x - (float)h);
+    lp[np * D + e] = (__bf16)(x - (float)h);
 }
 
-// Transposed copy of both parts: yt[p][k][j] = lp[p][j][k], zero for j >= m.
-__global__ __launch_bounds__(256) void bf16_transpose(const __bf16 *__restrict__ lp, int64_t m, int D,
-                                                      int64_t mp, __bf16 *__restrict__ yt) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= mp) return;
-    for (int p = 0; p < 2; ++p)
-        for (int k = 0; k < D; ++k)
-            yt[(int64_t)p * D * mp + (int64_t)k * mp + j] =
-                j < m ? lp[(int64_t)p * m * D + j * D + k] : (__bf16)0.f;
+// Transposed hi/lo copies of Y for the projection product, one block of
+// D x 32 per group of 32 columns (tile t), in the tile layout with the
+// dimensions as rows: element (dim, position q) of tile t of part p at
+// p mp D + t 32 D + ((dim / 16) 4 + q / 8) 128 + (dim % 16) 8 + q % 8,
+// holding column 32 t + perm32(q) (zero beyond m and d).
+__global__ __launch_bounds__(256) void bf16_transpose(const float *__restrict__ Y, int64_t m, int d,
+                                                      int D, int64_t mp, __bf16 *__restrict__ yt) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= mp * D) return;
+    const int nblk = D / 4;                       // 16-chunk blocks per tile
+    const int64_t rest = e >> 7;
+    const int blk = (int)(rest % nblk);
+    const int64_t t = rest / nblk;
+    const int dim = (blk >> 2) * 16 + (int)((e >> 3) & 15);
+    const int q = (blk & 3) * 8 + (int)(e & 7);
+    const int64_t j = 32 * t + perm32(q);
+    const float y = (j < m && dim < d) ? Y[j * d + dim] : 0.f;
+    const __bf16 h = (__bf16)y;
+    yt[e] = h;
+    yt[mp * D + e] = (__bf16)(y - (float)h);
 }
 
 template <int D, int QB, int NPART>
 hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
-    // the plan must cover every row tile of this kernel variant
-    if (a.blocks != (a.nu + 64 * QB - 1) / (64 * QB) * a.S) return hipErrorInvalidValue;
+    // the plan must cover every row tile of this kernel variant, and splits
+    // must start on the 64-column boundaries of the padded copy
+    if (a.blocks != (a.nu + 64 * QB - 1) / (64 * QB) * a.S || a.cps % 64 != 0)
+        return hipErrorInvalidValue;
+    const int64_t vstride = bf16_mpad(a.nv) * D;
     hipLaunchKernelGGL((lse_partial_bf16<D, QB, NPART>), dim3((unsigned)a.blocks), dim3(256), 0, s,
-                       (const __bf16 *)a.U_lp, a.nu, (const __bf16 *)a.V_lp, a.nv, a.vsq, a.vpot,
+                       a.U, a.nu, a.d, (const __bf16 *)a.V_lp, a.nv, vstride, a.vsq, a.vpot,
                        a.gamma, a.scale2, a.bscale, a.S, a.cps, a.part_m, a.part_s);
     return hipGetLastError();
 }
 
 template <int D, int QB, int NPART>
 hipError_t map_bf16_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
+    if (a.mp != bf16_mpad(a.m)) return hipErrorInvalidValue;
     const int64_t tiles = (a.nq + 64 * QB - 1) / (64 * QB);
     hipLaunchKernelGGL((entropic_map_bf16<D, QB, NPART>), dim3((unsigned)tiles), dim3(256), 0, s,
                        a.Xq, a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m,
@@ -519,24 +572,26 @@ hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStre
     switch (bf16_dim(a.d)) {
         case 32: return x3 ? map_bf16_t<32, 4, 2>(a, scale2, bscale, s) : map_bf16_t<32, 4, 1>(a, scale2, bscale, s);
         case 64: return x3 ? map_bf16_t<64, 4, 2>(a, scale2, bscale, s) : map_bf16_t<64, 4, 1>(a, scale2, bscale, s);
-        case 128: return x3 ? map_bf16_t<128, 2, 2>(a, scale2, bscale, s) : map_bf16_t<128, 4, 1>(a, scale2, bscale, s);
+        case 128: return x3 ? map_bf16_t<128, 2, 2>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1>(a, scale2, bscale, s);
         default: return x3 ? map_bf16_t<256, 1, 2>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1>(a, scale2, bscale, s);
     }
 }
 
 hipError_t launch_bf16_rows(const float *X, int64_t n, int d, void *lp, hipStream_t s) {
     const int D = bf16_dim(d);
-    const int64_t tot = n * D;
+    const int64_t np = bf16_mpad(n);
+    const int64_t tot = np * D;
     hipLaunchKernelGGL(bf16_split_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, n, d, D,
-                       (__bf16 *)lp);
+                       np, (__bf16 *)lp);
     return hipGetLastError();
 }
 
-hipError_t launch_bf16_transpose(const void *lp, int64_t m, int d, void *yt, hipStream_t s) {
+hipError_t launch_bf16_transpose(const float *Y, int64_t m, int d, void *yt, hipStream_t s) {
     const int D = bf16_dim(d);
     const int64_t mp = bf16_mpad(m);
-    hipLaunchKernelGGL(bf16_transpose, dim3((unsigned)((mp + 255) / 256)), dim3(256), 0, s,
-                       (const __bf16 *)lp, m, D, mp, (__bf16 *)yt);
+    const int64_t tot = mp * D;
+    hipLaunchKernelGGL(bf16_transpose, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Y, m, d, D,
+                       mp, (__bf16 *)yt);
     return hipGetLastError();
 }
 

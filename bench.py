@@ -67,6 +67,22 @@ def make_clouds(spec):
     raise ValueError(kind)
 
 
+# What the FP32 potential kernel is built from: its source, the headers it
+# includes and the build flags.
+KERNEL_SOURCES = ["paper_2406_05061_amd/csrc/progot_kernels.hip",
+                  "paper_2406_05061_amd/csrc/progot_device.h",
+                  "paper_2406_05061_amd/csrc/progot_internal.h",
+                  "paper_2406_05061_amd/build.py"]
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def recorded_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 --pmc record, or None
     when there is none or the kernel source changed since it was taken."""
@@ -75,9 +91,7 @@ def recorded_traffic(kernel: str, workload: str):
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
     except (OSError, KeyError, ValueError):
         return None
-    src = os.path.join(ROOT, "paper_2406_05061_amd", "csrc", "progot_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("kernel_sha256_16") != sha or rec.get("workload") != workload:
+    if rec.get("kernel_sha256_16") != kernel_source_sha() or rec.get("workload") != workload:
         return None
     return float(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
 

@@ -280,10 +280,16 @@ __device__ __forceinline__ void lse_merge_body(const LseJob &J, int64_t blk, flo
     const int64_t i = blk * 256 + threadIdx.x;
     float e = 0.f;
     if (i < nu) {
-        float M = kNegBig;
-        for (int s = 0; s < S; ++s) M = fmaxf(M, part_m[s * nu + i]);
-        float sum = 0.f;
-        for (int s = 0; s < S; ++s) sum += part_s[s * nu + i] * exp2f(part_m[s * nu + i] - M);
+        // one pass over the splits, running (max, sum); unrolled so the
+        // loads of several splits are in flight together
+        float M = kNegBig, sum = 0.f;
+#pragma unroll 8
+        for (int s = 0; s < S; ++s) {
+            const float m = part_m[s * nu + i], v = part_s[s * nu + i];
+            const float Mn = fmaxf(M, m);
+            sum = sum * exp2f(M - Mn) + v * exp2f(m - Mn);
+            M = Mn;
+        }
         const float L = M + log2f(sum);
         const float lw = J.logw[i];
         const float pot = fmaf(eps, lw, J.usq[i]) - eps * kLn2 * L;
@@ -615,14 +621,32 @@ int map_rows_per_block(int d) { return 64 * qb_for(padded_dim(d)); }
 
 int padded_dim_f32(int d) { return padded_dim(d); }
 
+// Workgroups per potential update.  The chip holds ~512-1024 of the BF16
+// workgroups at once; with ~8 rounds the last, partly filled round costs
+// little (measured: 1024 -> 8192 made the BF16 update 26% faster at
+// n = 65536, d = 128, and changed nothing where the grid was already
+// large).  The FP32 kernel measured the same at both, so it keeps the
+// smaller merge.
+constexpr int64_t kSplitTargetBf16 = 8192;
+constexpr int64_t kSplitTargetF32 = 1024;
+
 void plan_lse_job(LseJob &j) {
     const int rows = j.precision == 0 ? lse_rows_per_block(j.d) : lse_bf16_rows_per_block(j.d, j.precision);
     const int64_t tiles = (j.nu + rows - 1) / rows;
-    // Split the columns so that the grid holds >= ~1024 workgroups (4 per CU),
-    // keeping >= 256 columns per split.
-    int64_t S = tiles >= 1024 ? 1 : (1024 + tiles - 1) / tiles;
+    // Split the columns so that the grid holds >= target workgroups,
+    // keeping >= 256 columns per split.  S is a power of two, so with S >= 8
+    // the blocks an XCD receives (block b goes to XCD b mod 8, split b mod S)
+    // stream a fixed subset of the column splits through that XCD's L2.
+    const int64_t target = j.precision == 0 ? kSplitTargetF32 : kSplitTargetBf16;
+    int64_t S = tiles >= target ? 1 : (target + tiles - 1) / tiles;
     const int64_t max_by_cols = (j.nv + 255) / 256;
     if (S > max_by_cols) S = max_by_cols;
+    if (S > 1) {
+        int64_t q = 1;
+        while (q < S) q <<= 1;
+        S = q;
+        if (S > max_by_cols) S = max_by_cols;
+    }
     if (S > kMaxSplit) S = kMaxSplit;
     if (S < 1) S = 1;
     j.S = (int)S;

@@ -189,27 +189,40 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
 #pragma unroll
             for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = beta;
         }
-        // k outer, (column subtile, row block) inner: NSUB x QB independent
-        // accumulation chains keep the MFMA pipe busy.
-#pragma unroll
-        for (int s = 0; s < T::KS; ++s) {
-            bf8 a[NPART][T::NSUB];
+        // k outer; the column fragments of step s + 1 are read while step s
+        // runs, and each product term sweeps all NSUB x QB accumulators, so
+        // consecutive MFMAs are independent.
+        bf8 a[2][NPART][T::NSUB];
+        auto read_a = [&](int s, bf8 (&dst)[NPART][T::NSUB]) {
 #pragma unroll
             for (int p = 0; p < NPART; ++p)
 #pragma unroll
                 for (int sub = 0; sub < T::NSUB; ++sub)
-                    a[p][sub] = *reinterpret_cast<const bf8 *>(
+                    dst[p][sub] = *reinterpret_cast<const bf8 *>(
                         &vt[buf][p][tile_chunk(sub, T::C, lq * T::KS + s, li) * 8]);
+        };
+        read_a(0, a[0]);
+#pragma unroll
+        for (int s = 0; s < T::KS; ++s) {
+            if (s + 1 < T::KS) read_a(s + 1, a[(s + 1) & 1]);
+            const int cs = s & 1;
 #pragma unroll
             for (int sub = 0; sub < T::NSUB; ++sub)
 #pragma unroll
-                for (int qb = 0; qb < QB; ++qb) {
-                    acc[qb][sub] = mfma_bf(a[0][sub], ub[qb][0][s], acc[qb][sub]);
-                    if constexpr (NPART == 2) {
-                        acc[qb][sub] = mfma_bf(a[0][sub], ub[qb][1][s], acc[qb][sub]);
-                        acc[qb][sub] = mfma_bf(a[1][sub], ub[qb][0][s], acc[qb][sub]);
-                    }
-                }
+                for (int qb = 0; qb < QB; ++qb)
+                    acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][0][s], acc[qb][sub]);
+            if constexpr (NPART == 2) {
+#pragma unroll
+                for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb)
+                        acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][1][s], acc[qb][sub]);
+#pragma unroll
+                for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb)
+                        acc[qb][sub] = mfma_bf(a[cs][1][sub], ub[qb][0][s], acc[qb][sub]);
+            }
         }
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
@@ -369,25 +382,41 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
             const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
-            bf8 a[NPART][KS];
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = beta;
+        }
+        // k outer with the next step's fragments read ahead; each product
+        // term sweeps the 2 x QB accumulators (independent consecutive MFMAs)
+        bf8 a[2][NPART][2];
+        auto read_a = [&](int s, bf8 (&dst)[NPART][2]) {
 #pragma unroll
             for (int p = 0; p < NPART; ++p)
 #pragma unroll
-                for (int s = 0; s < KS; ++s)
-                    a[p][s] = *reinterpret_cast<const bf8 *>(
+                for (int sub = 0; sub < 2; ++sub)
+                    dst[p][sub] = *reinterpret_cast<const bf8 *>(
                         &yr[buf][p][tile_chunk(sub, C, lq * KS + s, li) * 8]);
+        };
+        read_a(0, a[0]);
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) {
-                f4 c = beta;
+        for (int s = 0; s < KS; ++s) {
+            if (s + 1 < KS) read_a(s + 1, a[(s + 1) & 1]);
+            const int cs = s & 1;
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    c = mfma_bf(a[0][s], ub[qb][0][s], c);
-                    if constexpr (NPART == 2) {
-                        c = mfma_bf(a[0][s], ub[qb][1][s], c);
-                        c = mfma_bf(a[1][s], ub[qb][0][s], c);
-                    }
-                }
-                acc[qb][sub] = c;
+            for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+                for (int qb = 0; qb < QB; ++qb)
+                    acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][0][s], acc[qb][sub]);
+            if constexpr (NPART == 2) {
+#pragma unroll
+                for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb)
+                        acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][1][s], acc[qb][sub]);
+#pragma unroll
+                for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb)
+                        acc[qb][sub] = mfma_bf(a[cs][1][sub], ub[qb][0][s], acc[qb][sub]);
             }
         }
         bf8 pb[QB], pl[NPART == 2 ? QB : 1];
@@ -418,19 +447,21 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
             }
         }
         // O^T += Y^T P^T: each Y^T fragment (16 dims x 32 columns) is read
-        // once and feeds the QB row blocks
+        // once and feeds the QB row blocks; the hi part of every dimension
+        // block is applied before the lo part, so an accumulator is not
+        // touched by consecutive MFMAs
 #pragma unroll
-        for (int db = 0; db < NDB; ++db)
+        for (int p2 = 0; p2 < 2; ++p2)
 #pragma unroll
-            for (int p2 = 0; p2 < 2; ++p2) {
+            for (int db = 0; db < NDB; ++db) {
                 const bf8 av =
                     *reinterpret_cast<const bf8 *>(&ytr[buf][p2][tile_chunk(db, 4, lq, li) * 8]);
 #pragma unroll
-                for (int qb = 0; qb < QB; ++qb) {
-                    o[qb][db] = mfma_bf(av, pb[qb], o[qb][db]);
-                    if constexpr (NPART == 2)
-                        if (p2 == 0) o[qb][db] = mfma_bf(av, pl[qb], o[qb][db]);
-                }
+                for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pb[qb], o[qb][db]);
+                if constexpr (NPART == 2)
+                    if (p2 == 0)
+#pragma unroll
+                        for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pl[qb], o[qb][db]);
             }
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {

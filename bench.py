@@ -37,6 +37,8 @@ PAD = {16: 16, 64: 64, 128: 128, 256: 256}  # template dimension of the kernel p
 QB = {16: 2, 64: 2, 128: 2, 256: 1}
 
 _SPHERE64K = dict(kind="sphere", seed=3, n=65536, m=65536, d=256, n_clusters=32)
+_SPHERE256K = dict(kind="sphere", seed=5, n=262144, m=262144, d=128, n_clusters=64,
+                   n_query=1 << 20, query_seed=55)
 WORKLOADS = {
     # name: (generator kwargs, K, precision)
     "gmm16k_d64_fp32": (dict(kind="gmm", seed=2, n=16384, m=16384, d=64), 8, "fp32"),
@@ -46,10 +48,10 @@ WORKLOADS = {
     "sphere64k_d256_bf16x3": (_SPHERE64K, 4, "bf16x3"),
     # large map estimation: fit on 64 unit-norm clusters, then T_Prog on 2^20
     # queries drawn from the source distribution
-    "sphere256k_d128_bf16": (dict(kind="sphere", seed=5, n=262144, m=262144, d=128,
-                                  n_clusters=64, n_query=1 << 20, query_seed=55), 8, "bf16"),
-    "sphere256k_d128_bf16x3": (dict(kind="sphere", seed=5, n=262144, m=262144, d=128,
-                                    n_clusters=64, n_query=1 << 20, query_seed=55), 8, "bf16x3"),
+    "sphere256k_d128_bf16": (_SPHERE256K, 8, "bf16"),
+    "sphere256k_d128_bf16x3": (_SPHERE256K, 8, "bf16x3"),
+    # the same in FP32, the baseline of the BF16 forms' speedup
+    "sphere256k_d128_fp32": (_SPHERE256K, 8, "fp32"),
 }
 
 

@@ -45,6 +45,28 @@ def test_bf16x3_fixed_iterations(P, n, m, d):
         assert map_err(out.cpu().numpy(), ref_t, Y) < 1e-3
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("nq,m,d", [(300, 1000, 128), (333, 999, 200), (129, 1025, 256), (1, 33, 256)])
+def test_bf16_map_ragged(P, prec, nq, m, d):
+    """Entropic map of both BF16 forms on ragged sizes (query blocks and the
+    last column tile partly filled; d = 200 pads to 256) against FP64, at a
+    converged target potential.  BF16X3 meets the 1e-3 map bar; plain BF16
+    (weights and cross term rounded once) is held to 5e-3."""
+    X, Y = workloads.sphere(seed=400 + d, n=max(nq, 64), m=m, d=d, n_clusters=5)
+    Q = X[:nq]
+    eps = float(np.float32(oracle.mean_cost(X, Y) / 20.0))
+    print(f"case map {prec} nq={nq} m={m} d={d}", flush=True)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=prec)
+    f, g, _ = P.sinkhorn_solve(cl, eps, tau=1e-3)
+    g64 = g.cpu().numpy().astype(np.float64)
+    for alpha in (1.0, 0.3):
+        out = P.entropic_map(cl, g, eps, P.to_device(Q), alpha=alpha)
+        ref = oracle.entropic_map(Q, Y, g64, eps, alpha=alpha)
+        e = map_err(out.cpu().numpy(), ref, Y)
+        print(f"  alpha {alpha}: map err {e:.2e}", flush=True)
+        assert e < (1e-3 if prec == "bf16x3" else 5e-3)
+
+
 def test_precision_table(P):
     """The precision workload's protocol on its seeded 4096 x 4096 subsample
     (d = 256, 32 unit-norm clusters + N(0, 0.01 I)): Sinkhorn at mean cost/20

@@ -106,9 +106,18 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
     const int li = lane & 15, lq = lane >> 4;
     const int64_t row0 = tile * ROWS + wave * (QB * 16);
 
+    // rows held already multiplied by scale2 (and kept in registers: the
+    // empty asm stops the compiler from re-deriving them inside the loop)
     float ub[QB][T::KD];
 #pragma unroll
-    for (int qb = 0; qb < QB; ++qb) row_fetch<D>(U, nu, d, row0 + qb * 16 + li, lq, ub[qb]);
+    for (int qb = 0; qb < QB; ++qb) {
+        row_fetch<D>(U, nu, d, row0 + qb * 16 + li, lq, ub[qb]);
+#pragma unroll
+        for (int k = 0; k < T::KD; ++k) {
+            ub[qb][k] *= scale2;
+            asm volatile("" : "+v"(ub[qb][k]));
+        }
+    }
 
     float run_m[QB], run_s[QB];
 #pragma unroll
@@ -143,9 +152,11 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
             fetch_beta(jn);
         }
         const float *vb = vt[buf];
+        // accumulators start at beta_j: the MFMA output is the exponent t_ij
         f4 acc[QB][T::NSUB];
 #pragma unroll
         for (int sub = 0; sub < T::NSUB; ++sub) {
+            const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
             float a[T::KD];
             const f4 *ap = reinterpret_cast<const f4 *>(vb + (sub * 16 + li) * T::STRIDE + lq * T::KD);
 #pragma unroll
@@ -155,33 +166,26 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
             }
 #pragma unroll
             for (int qb = 0; qb < QB; ++qb) {
-                f4 c = {0.f, 0.f, 0.f, 0.f};
+                f4 c = beta;
 #pragma unroll
                 for (int k = 0; k < T::KD; ++k) c = mfma4(a[k], ub[qb][k], c);
                 acc[qb][sub] = c;
             }
         }
-        f4 beta[T::NSUB];
-#pragma unroll
-        for (int sub = 0; sub < T::NSUB; ++sub)
-            beta[sub] = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
-            float tv[T::NSUB * 4];
             float mx = kNegBig;
 #pragma unroll
             for (int sub = 0; sub < T::NSUB; ++sub)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float x = fmaf(acc[qb][sub][r], scale2, beta[sub][r]);
-                    tv[sub * 4 + r] = x;
-                    mx = fmaxf(mx, x);
-                }
+                for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
             const float mn = fmaxf(run_m[qb], mx);
-            float s = 0.f;
+            float s4[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int e = 0; e < T::NSUB * 4; ++e) s += ex2(tv[e] - mn);
-            run_s[qb] = fmaf(run_s[qb], ex2(run_m[qb] - mn), s);
+            for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) s4[r] += ex2(acc[qb][sub][r] - mn);
+            run_s[qb] = fmaf(run_s[qb], ex2(run_m[qb] - mn), (s4[0] + s4[1]) + (s4[2] + s4[3]));
             run_m[qb] = mn;
         }
         if (more) {

@@ -185,6 +185,35 @@ POT_API int pot_progot_map(const pot_clouds *c, int32_t K, const float *G, const
 POT_API int pot_marginal_check(const pot_clouds *c, const float *f, const float *g, float eps,
                        double *out, void *stream);
 
+/* ---- Alg. 4 (eps-scheduler) ------------------------------------------------
+ *
+ * The schedule of regularisations that Alg. 2 consumes (pass the result as
+ * pot_progot_params.eps_explicit with eps_mode = 1):
+ *   eps_0 = c->mean_cost / 20 (the prepared pair: call before the source
+ *           iterate moves, i.e. after pot_prepare_clouds),
+ *   sigma = mean_lj |y_l - y_j|^2 / 20 (closed form from the targets),
+ *   for each grid scale s_p: Sink(b, Y, b, Y, s_p sigma, tau) (Alg. 1), the
+ *           one-step entropic map of the hold-out targets Y_test (alpha = 1)
+ *           and err_p = sum |y~ - T_p(y~)|^2,
+ *   p* = first argmin, eps_final = s_{p*} sigma,
+ *   eps_k = (1 - t_k) beta0 eps_0 + t_k eps_final, t_k = 1 - prod_{l=1..k}
+ *           (1 - alpha_l) of the alpha schedule (K = 1: eps_final).
+ * The grid solves run in FP32 and advance together in grouped launches; each
+ * gets the same result as pot_sinkhorn_solve on (Y, Y) at its eps.
+ *   c: prepared clouds (any precision; only Y, b, m, d, mean_cost are used).
+ *   Y_test (device, m_test*d): hold-out targets.
+ *   s_grid (host, n_grid doubles > 0), 1 <= n_grid <= POT_MAX_GRID.
+ *   eps_out (host, K doubles); err_out (host, n_grid doubles) and p_star
+ *   (host) may be NULL.  ws (device): pot_eps_schedule_bytes() bytes.
+ * Returns POT_WARN_NOT_CONVERGED (outputs valid) when a grid solve hit
+ * max_iter.  Blocks. */
+#define POT_MAX_GRID 64
+POT_API size_t pot_eps_schedule_bytes(int64_t m, int64_t m_test, int32_t d, int32_t n_grid);
+POT_API int pot_eps_schedule(const pot_clouds *c, const float *Y_test, int64_t m_test, int32_t K,
+                             int32_t alpha_sched, const double *s_grid, int32_t n_grid, float beta0,
+                             float tau, int32_t max_iter, double *eps_out, double *err_out,
+                             int32_t *p_star, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- Serving form: continuous batching of ProgOT solves ------------------
  *
  * A server advances many independent ProgOT solves (Alg. 2) of uneven sizes

@@ -1,0 +1,253 @@
+// Alg. 4 (the eps-scheduler) on the GPU.
+//
+// eps_0 is the mean cost of the caller's pair / 20 and sigma the mean cost of
+// the targets with themselves / 20 (closed form from the targets' FP64
+// moments).  For every scale s_p of the grid, Alg. 1 is run on (b, Y, b, Y)
+// at eps_p = s_p sigma to tolerance tau; all grid points advance together,
+// one grouped f-update launch and one grouped g-update launch per iteration
+// (the same kernels and bodies as a solve on its own, so each grid point
+// gets the bits pot_sinkhorn_solve would give it), with the stop rule of
+// Alg. 1 checked per grid point on the host exactly as in a single solve.
+// The hold-out targets are then mapped by the one-step entropic map
+// (alpha = 1) of each solve and scored by err_p = sum |y~ - T_p(y~)|^2 (FP64
+// sum).  With p* the first argmin, eps_final = s_{p*} sigma and the schedule
+// is eps_k = (1 - t_k) beta0 eps_0 + t_k eps_final, t_k = 1 - prod_{l=1..k}
+// (1 - alpha_l) (K = 1: eps_final).
+
+#include "progot.h"
+#include "progot_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+using namespace pot::host;
+using pot::LseJob;
+
+namespace {
+
+constexpr int kSqBlocks = 256;
+
+// Per-block FP64 partial sums of (a_i - b_i)^2 over len floats.
+__global__ __launch_bounds__(256) void sqdist_partial(const float *__restrict__ A,
+                                                      const float *__restrict__ B, int64_t len,
+                                                      double *__restrict__ part) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256) {
+        const double e = (double)A[i] - (double)B[i];
+        s = fma(e, e, s);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Workspace: the (Y, Y) pair, then one block of buffers per grid point
+// (ping-pong potentials, split partials, error partials), the job tables,
+// the error sums, the mapped hold-out targets and the FP64 partials.
+struct SchedLayout {
+    Layout cy;
+    size_t f0, f1, g0, g1, pm, ps, errp, per_p;  // within one grid point's block
+    size_t grid, jobs, errs, ty, sq, total;
+};
+
+SchedLayout sched_plan(int64_t m, int64_t mt, int32_t d, int32_t G) {
+    SchedLayout S{};
+    S.cy = plan(m, m, d, POT_PREC_FP32);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = a256(o + bytes); return r; };
+    S.f0 = take((size_t)m * 4);
+    S.f1 = take((size_t)m * 4);
+    S.g0 = take((size_t)m * 4);
+    S.g1 = take((size_t)m * 4);
+    S.pm = take((size_t)pot::kMaxSplit * m * 4);
+    S.ps = take((size_t)pot::kMaxSplit * m * 4);
+    S.errp = take((((size_t)m + 255) / 256) * 4);
+    S.per_p = o;
+    S.grid = a256(S.cy.total);
+    size_t off = S.grid + (size_t)G * S.per_p;
+    auto take2 = [&](size_t bytes) { size_t r = off; off = a256(off + bytes); return r; };
+    S.jobs = take2(sizeof(LseJob) * 2 * (size_t)G);
+    S.errs = take2(sizeof(float) * (size_t)G);
+    S.ty = take2((size_t)mt * d * 4);
+    S.sq = take2(kSqBlocks * sizeof(double));
+    S.total = off;
+    return S;
+}
+
+struct GridPoint {
+    float eps;
+    float *fb[2], *gb[2];
+    float *pm, *ps, *errp;
+    bool done = false, converged = false;
+    int iters = 0;
+    float err = 0.f;
+    const float *g = nullptr;
+};
+
+LseJob point_job(const LseJob &base, const GridPoint &q) {
+    LseJob j = base;
+    j.eps = q.eps;
+    j.part_m = q.pm;
+    j.part_s = q.ps;
+    return j;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pot_eps_schedule_bytes(int64_t m, int64_t m_test, int32_t d, int32_t n_grid) {
+    if (!valid_sizes(m, m, d, POT_PREC_FP32) || m_test < 1 || n_grid < 1 || n_grid > POT_MAX_GRID)
+        return 0;
+    return sched_plan(m, m_test, d, n_grid).total;
+}
+
+int pot_eps_schedule(const pot_clouds *c, const float *Y_test, int64_t m_test, int32_t K,
+                     int32_t alpha_sched, const double *s_grid, int32_t n_grid, float beta0,
+                     float tau, int32_t max_iter, double *eps_out, double *err_out,
+                     int32_t *p_star, void *ws, size_t ws_bytes, void *stream) {
+    if (!valid_clouds(c) || !Y_test || m_test < 1 || K < 1 || K > POT_MAX_K || alpha_sched < 0 ||
+        alpha_sched > 2 || !s_grid || n_grid < 1 || n_grid > POT_MAX_GRID || !finite_pos(beta0) ||
+        !finite_pos(tau) || max_iter < 1 || !eps_out || !ws)
+        return POT_ERR_INVALID;
+    for (int p = 0; p < n_grid; ++p)
+        if (!(std::isfinite(s_grid[p]) && s_grid[p] > 0.0)) return POT_ERR_INVALID;
+    const int64_t m = c->m;
+    const int d = c->d;
+    const SchedLayout S = sched_plan(m, m_test, d, n_grid);
+    if (ws_bytes < S.total) return POT_ERR_NOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *base = static_cast<char *>(ws);
+
+    // the (Y, Y) pair with the target weights on both sides; sigma from its
+    // mean cost (closed form from the FP64 moments)
+    pot_clouds cy;
+    bind_clouds(&cy, c->Y, m, c->Y, m, d, c->b, c->b, POT_PREC_FP32, ws, S.cy.total, S.cy);
+    std::vector<double> mom(moments_len(d));
+    int st = enqueue_prepare(&cy, S.cy, mom.data(), s);
+    if (st != POT_OK) return st;
+    POT_TRY(hipStreamSynchronize(s));
+    if ((st = finish_moments(&cy, mom.data())) != POT_OK) return st;
+    const double sigma = cy.mean_cost / 20.0;
+    const double eps0 = c->mean_cost / 20.0;
+    if (!(sigma > 0.0) || !(eps0 > 0.0)) return POT_ERR_NUMERIC;
+
+    std::vector<GridPoint> pts(n_grid);
+    for (int p = 0; p < n_grid; ++p) {
+        char *blk = base + S.grid + (size_t)p * S.per_p;
+        GridPoint &q = pts[p];
+        q.eps = (float)(s_grid[p] * sigma);
+        if (!finite_pos(q.eps)) return POT_ERR_INVALID;
+        q.fb[0] = reinterpret_cast<float *>(blk + S.f0);
+        q.fb[1] = reinterpret_cast<float *>(blk + S.f1);
+        q.gb[0] = reinterpret_cast<float *>(blk + S.g0);
+        q.gb[1] = reinterpret_cast<float *>(blk + S.g1);
+        q.pm = reinterpret_cast<float *>(blk + S.pm);
+        q.ps = reinterpret_cast<float *>(blk + S.ps);
+        q.errp = reinterpret_cast<float *>(blk + S.errp);
+    }
+    LseJob *jobs_dev = reinterpret_cast<LseJob *>(base + S.jobs);
+    float *errs_dev = reinterpret_cast<float *>(base + S.errs);
+    const LseJob fbase = f_job(&cy, S.cy, 1.f), gbase = g_job(&cy, S.cy, 1.f);
+
+    // Alg. 1 for every grid point, advanced together.  Iteration t: f_t
+    // (whose error partials are the row-marginal error of iterate t-1), then
+    // g_t; after both, the errors of iterate t-1 are read back and a grid
+    // point that met tau stops there (its iterate t-1 is intact in the
+    // ping-pong buffers).  At t = max_iter one more f-update gives the error
+    // of the last iterate.
+    std::vector<LseJob> fj(n_grid), gj(n_grid);
+    std::vector<int> act, err_of(n_grid);
+    std::vector<float> errs(n_grid);
+    for (int t = 1;; ++t) {
+        act.clear();
+        for (int p = 0; p < n_grid; ++p)
+            if (!pts[p].done) act.push_back(p);
+        if (act.empty()) break;
+        const int na = (int)act.size();
+        const bool probe = t == max_iter + 1;   // error of iterate max_iter only
+        for (int k = 0; k < na; ++k) {
+            const GridPoint &q = pts[act[k]];
+            LseJob f = point_job(fbase, q);
+            f.vpot = t == 1 ? nullptr : q.gb[(t - 1) & 1];
+            f.pot_old = t == 1 ? nullptr : q.fb[(t - 1) & 1];
+            f.pot_out = q.fb[t & 1];
+            f.err_part = q.errp;
+            fj[k] = f;
+            LseJob g = point_job(gbase, q);
+            g.vpot = q.fb[t & 1];
+            g.pot_out = q.gb[t & 1];
+            g.err_part = nullptr;
+            gj[k] = g;
+        }
+        POT_TRY(pot::launch_lse_update_group(fj.data(), na, jobs_dev, errs_dev, s));
+        if (!probe) POT_TRY(pot::launch_lse_update_group(gj.data(), na, jobs_dev + n_grid, nullptr, s));
+        if (t > 1) POT_TRY(hipMemcpyAsync(errs.data(), errs_dev, sizeof(float) * na, hipMemcpyDeviceToHost, s));
+        // the job tables above are read by the copies just enqueued
+        POT_TRY(hipStreamSynchronize(s));
+        if (t == 1) continue;
+        for (int k = 0; k < na; ++k) {
+            GridPoint &q = pts[act[k]];
+            const float err = errs[k];
+            if (!std::isfinite(err)) return POT_ERR_NUMERIC;
+            if (err <= tau || probe) {
+                q.done = true;
+                q.converged = err <= tau;
+                q.iters = t - 1;
+                q.err = err;
+                q.g = q.gb[(t - 1) & 1];
+            }
+        }
+    }
+
+    // hold-out scores
+    std::vector<double> sq(kSqBlocks);
+    std::vector<double> score(n_grid);
+    float *ty = reinterpret_cast<float *>(base + S.ty);
+    double *sq_dev = reinterpret_cast<double *>(base + S.sq);
+    for (int p = 0; p < n_grid; ++p) {
+        if ((st = run_map(&cy, pts[p].g, pts[p].eps, Y_test, m_test, 1.f, ty, s)) != POT_OK) return st;
+        hipLaunchKernelGGL(sqdist_partial, dim3(kSqBlocks), dim3(256), 0, s, Y_test, ty,
+                           m_test * (int64_t)d, sq_dev);
+        POT_TRY(hipGetLastError());
+        POT_TRY(hipMemcpyAsync(sq.data(), sq_dev, sizeof(double) * kSqBlocks, hipMemcpyDeviceToHost, s));
+        POT_TRY(hipStreamSynchronize(s));
+        double tot = 0.0;
+        for (double v : sq) tot += v;
+        if (!std::isfinite(tot)) return POT_ERR_NUMERIC;
+        score[p] = tot;
+    }
+    int best = 0;
+    for (int p = 1; p < n_grid; ++p)
+        if (score[p] < score[best]) best = p;
+    const double eps_final = s_grid[best] * sigma;
+
+    float alpha[POT_MAX_K];
+    alpha_schedule(K, alpha_sched, alpha);
+    if (K == 1) {
+        eps_out[0] = eps_final;
+    } else {
+        double prod = 1.0;
+        for (int k = 0; k < K; ++k) {
+            if (k > 0) prod *= 1.0 - (double)alpha[k];
+            const double tk = 1.0 - prod;
+            eps_out[k] = (1.0 - tk) * beta0 * eps0 + tk * eps_final;
+        }
+    }
+    if (err_out)
+        for (int p = 0; p < n_grid; ++p) err_out[p] = score[p];
+    if (p_star) *p_star = best;
+    bool all = true;
+    for (const GridPoint &q : pts) all = all && q.converged;
+    return all ? POT_OK : POT_WARN_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -88,6 +88,11 @@ _SIGS = {
                                  C.POINTER(C.c_float), _vp, _i64, _vp, _vp]),
     "pot_marginal_check": (C.c_int, [C.POINTER(pot_clouds), _vp, _vp, _f32, C.POINTER(C.c_double),
                                      _vp]),
+    "pot_eps_schedule_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32]),
+    "pot_eps_schedule": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _i32, _i32,
+                                   C.POINTER(C.c_double), _i32, _f32, _f32, _i32,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_int32), _vp, C.c_size_t, _vp]),
     "pot_server_arena_overhead": (C.c_size_t, [_i32]),
     "pot_server_request_bytes": (C.c_size_t, [_i64, _i64, _i32]),
     "pot_server_create": (C.c_int, [C.POINTER(C.c_void_p), _vp, C.c_size_t, _i32, _vp]),
@@ -319,6 +324,43 @@ def progot_map(cl: Clouds, G, eps, alpha, Xq, out=None):
     _check(lib().pot_progot_map(C.byref(cl.c), K, _ptr(G), e, a, _ptr(Xq), Xq.shape[0], _ptr(out),
                                 C.c_void_p(_stream())), "progot_map", False)
     return out
+
+
+@dataclass
+class EpsSchedule:
+    eps: list          # eps_k for k = 0..K-1 (feed to progot_solve(eps=...))
+    errors: list       # hold-out score of each grid scale
+    p_star: int        # first argmin of the scores
+    status: int
+
+
+DEFAULT_S_GRID = tuple(2.0 ** p for p in range(-3, 4))
+
+
+def eps_schedule(cl: Clouds, Y_test, K: int, *, alpha_sched: str = "constant", s_grid=None,
+                 beta0: float = 5.0, tau: float = 1e-3, max_iter: int = 10_000) -> EpsSchedule:
+    """Alg. 4 (eps-scheduler) on the GPU for the prepared pair ``cl``: grid of
+    Y -> Y Sinkhorn solves, hold-out map error, schedule from eps_0 (the
+    pair's mean cost / 20) to the selected eps_final."""
+    torch = _torch()
+    _dev_f32(Y_test, "Y_test")
+    if Y_test.dim() != 2 or Y_test.shape[1] != cl.d:
+        raise ValueError("Y_test must be m_test x d")
+    grid = list(DEFAULT_S_GRID if s_grid is None else s_grid)
+    G = len(grid)
+    nb = int(lib().pot_eps_schedule_bytes(cl.m, Y_test.shape[0], cl.d, G))
+    if nb == 0:
+        raise ValueError("invalid sizes for the eps-scheduler")
+    ws = torch.empty(nb, dtype=torch.uint8, device=cl.X.device)
+    grid_c = (C.c_double * G)(*[float(v) for v in grid])
+    eps_c = (C.c_double * int(K))()
+    err_c = (C.c_double * G)()
+    p_c = C.c_int32(-1)
+    st = _check(lib().pot_eps_schedule(C.byref(cl.c), _ptr(Y_test), Y_test.shape[0], int(K),
+                                       ALPHA_SCHED[alpha_sched], grid_c, G, float(beta0), float(tau),
+                                       int(max_iter), eps_c, err_c, C.byref(p_c), _ptr(ws), nb,
+                                       C.c_void_p(_stream())), "eps_schedule")
+    return EpsSchedule(list(eps_c), list(err_c), int(p_c.value), st)
 
 
 def marginal_check(cl: Clouds, f, g, eps: float):

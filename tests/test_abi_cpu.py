@@ -137,3 +137,40 @@ def test_server_rejects_invalid_before_device_work():
     p = B.pot_progot_params()
     assert lib.pot_server_submit(None, 0x1000, 8, 0x1000, 8, 4, C.byref(p), 0x1, 0x1, None,
                                  C.byref(rid)) == inv
+
+
+def test_eps_schedule_rejects_invalid_before_launch():
+    lib = P.lib()
+    inv = B.POT_ERR_INVALID
+    assert lib.pot_eps_schedule_bytes(0, 10, 4, 7) == 0
+    assert lib.pot_eps_schedule_bytes(10, 0, 4, 7) == 0
+    assert lib.pot_eps_schedule_bytes(10, 10, 4, 0) == 0
+    assert lib.pot_eps_schedule_bytes(10, 10, 4, 65) == 0
+    nb = lib.pot_eps_schedule_bytes(100, 50, 4, 7)
+    assert nb > P.workspace_bytes(100, 100, 4) and nb % 256 == 0
+    assert lib.pot_eps_schedule_bytes(100, 50, 4, 8) > nb
+    c = _fake_clouds(8, 8, 4)
+    grid = (C.c_double * 3)(0.5, 1.0, 2.0)
+    bad = (C.c_double * 3)(0.5, -1.0, 2.0)
+    eps = (C.c_double * 4)()
+    wsb = lib.pot_eps_schedule_bytes(8, 5, 4, 3)
+    args = dict(Yt=0x4000, mt=5, K=4, sched=0, grid=grid, G=3, beta0=5.0, tau=1e-3, it=100,
+                eps=eps, ws=0x2000, wsb=wsb)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return lib.pot_eps_schedule(C.byref(c), a["Yt"], a["mt"], a["K"], a["sched"], a["grid"], a["G"],
+                                    a["beta0"], a["tau"], a["it"], a["eps"], None, None, a["ws"],
+                                    a["wsb"], None)
+    assert call(Yt=None) == inv
+    assert call(mt=0) == inv
+    assert call(K=0) == inv and call(K=65) == inv
+    assert call(sched=3) == inv
+    assert call(grid=bad) == inv
+    assert call(G=0) == inv
+    assert call(beta0=0.0) == inv and call(tau=0.0) == inv and call(it=0) == inv
+    assert call(eps=None) == inv
+    assert call(ws=None) == inv
+    assert call(wsb=wsb - 1) == B.POT_ERR_NOMEM
+    assert lib.pot_eps_schedule(None, 0x4000, 5, 4, 0, grid, 3, 5.0, 1e-3, 100, eps, None, None,
+                                0x2000, wsb, None) == inv

@@ -126,7 +126,7 @@ def test_progot_c1(P, eps_mode):
     a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
     K, tau = 4, 1e-3
     if eps_mode == "alg4":
-        Yt = workloads.c1(seed=101)[1]
+        Yt = workloads.c1_holdout(seed=1, test_seed=101)
         eps_sched, _ = oracle.schedules.eps_scheduler(
             a, X, b, Y, oracle.schedules.alpha_schedule(K), Yt, beta0=5.0, tau=tau)
         eps_arg = eps_sched.astype(np.float32).astype(np.float64)

@@ -65,12 +65,30 @@ def test_tau_schedule():
     assert schedules.tau_schedule(1, 1e-2, 1e-3)[0] == 1e-3
 
 
+def test_c1_holdout_same_mixture():
+    """The hold-out targets are fresh draws of the same target mixture: a
+    large hold-out sample matches the mixture's mean (equal component
+    weights) and the training targets' statistics."""
+    import math
+    rng = np.random.default_rng(1)
+    rng.standard_normal((1024, 4))
+    mu = rng.standard_normal((4, 4)) * 2.0
+    Yt = workloads.c1_holdout(seed=1, m_test=200_000, test_seed=101).astype(np.float64)
+    assert np.abs(Yt.mean(0) - mu.mean(0)).max() < 0.03
+    Y = workloads.c1(seed=1)[1].astype(np.float64)
+    sd = Yt.std(0)
+    assert (np.abs(Y.mean(0) - Yt.mean(0)) < 4 * sd / math.sqrt(Y.shape[0]) + 0.15 * sd).all()
+    # a different test seed gives different points
+    assert not np.allclose(workloads.c1_holdout(seed=1, m_test=10, test_seed=5),
+                           workloads.c1_holdout(seed=1, m_test=10, test_seed=6))
+
+
 def test_eps_scheduler_structure():
     """Alg. 4 on a small C1-type problem: sigma is the intra-target mean cost
     / 20 (= 2 (mean |y|^2 - |ybar|^2)/20); the schedule starts at beta0 eps0,
     ends at s_{p*} sigma and, for constant speed, is linear in k/(K-1)."""
     X, Y = workloads.c1(seed=1, n=200, m=200)
-    Yt = workloads.c1(seed=101, n=200, m=200)[1]
+    Yt = workloads.c1_holdout(seed=1, n=200, m_test=200, test_seed=101)
     n = X.shape[0]
     a = np.full(n, 1.0 / n)
     alpha = schedules.alpha_schedule(4, "constant")

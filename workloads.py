@@ -54,6 +54,23 @@ def c1(seed: int = 1, n: int = 1024, m: int = 1024, d: int = 4, n_comp: int = 4)
     return _f32(X), _f32(Y)
 
 
+def c1_holdout(seed: int = 1, n: int = 1024, d: int = 4, n_comp: int = 4, m_test: int = 1024,
+               test_seed: int = 101):
+    """Fresh draws from the target mixture of c1(seed, n, ...) (same centres
+    and covariances; labels and noise from test_seed): the hold-out targets
+    of the eps-scheduler."""
+    rng = np.random.default_rng(seed)
+    rng.standard_normal((n, d))                          # the sources of c1
+    mu = rng.standard_normal((n_comp, d)) * 2.0
+    A = rng.standard_normal((n_comp, d, d)) * math.sqrt(0.5)
+    cov = A @ np.transpose(A, (0, 2, 1)) + 0.1 * np.eye(d)
+    chol = np.linalg.cholesky(cov)
+    rt = np.random.default_rng(test_seed)
+    lab = rt.integers(n_comp, size=m_test)
+    z = rt.standard_normal((m_test, d))
+    return _f32(mu[lab] + np.einsum("nij,nj->ni", chol[lab], z))
+
+
 def _gmm_cloud(rng, n, d, n_comp):
     mu = rng.standard_normal((n_comp, d)) * 3.0          # N(0, 9 I)
     sd = rng.uniform(0.5, 2.0, size=n_comp)

@@ -185,6 +185,40 @@ POT_API int pot_progot_map(const pot_clouds *c, int32_t K, const float *G, const
 POT_API int pot_marginal_check(const pot_clouds *c, const float *f, const float *g, float eps,
                        double *out, void *stream);
 
+/* Metrics of the coupling P = exp((f (+) g - C(c->xk, Y))/eps), one FP64
+ * pass over all pairs (cost in FP64, cross term on FP64 MFMA):
+ *   out[0] = |P 1 - a|_1, out[1] = |P^T 1 - b|_1,
+ *   out[2] = <f, a> + <g, b> - eps sum_ij P_ij (the objective of eq.
+ *            entdual, OT_eps of the Sinkhorn divergence, eq. sink_div),
+ *   out[3] = <P, C> (transport cost), out[4] = sum_ij P_ij log P_ij,
+ *   out[5] = sum_ij P_ij.
+ * f (device, n), g (device, m); out (host, 6 doubles).  Blocks. */
+POT_API int pot_coupling_metrics(const pot_clouds *c, const float *f, const float *g, float eps,
+                                 double *out, void *stream);
+
+/* Diagonal metrics of the coupling for n == m (the coupling-recovery
+ * benchmark of Sec. 5.3, where the true coupling is the identity / n):
+ *   out[0] = Tr P = sum_i P_ii,
+ *   out[1] = KL(I/n || P) = -log n - (1/n) sum_i log P_ii,
+ * with P_ii = exp((f_i + g_i - |x_i - y_i|^2)/eps) in FP64, O(n d).
+ * POT_ERR_INVALID if n != m.  Blocks. */
+POT_API int pot_diag_metrics(const pot_clouds *c, const float *f, const float *g, float eps,
+                             double *out, void *stream);
+
+/* Sinkhorn divergence (eq. sink_div) between weighted clouds X (n x d) and
+ * Y (m x d), device pointers, a/b device weights or NULL (uniform):
+ *   D = OT_eps(X, Y) - (OT_eps(X, X) + OT_eps(Y, Y)) / 2,
+ * OT_eps the objective of eq. entdual at Alg. 1's FP32 solution to tau
+ * (evaluated in FP64).  eps = 0 selects the paper's eps_D = 5 % of the mean
+ * cost within Y.  out (host, 5 doubles): D, OT(X,Y), OT(X,X), OT(Y,Y), eps.
+ * ws (device): pot_sinkhorn_divergence_bytes(n, m, d) bytes, reused by the
+ * three solves.  POT_WARN_NOT_CONVERGED if a solve hit max_iter.  Blocks. */
+POT_API size_t pot_sinkhorn_divergence_bytes(int64_t n, int64_t m, int32_t d);
+POT_API int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
+                                    const float *a, const float *b, float eps, float tau,
+                                    int32_t max_iter, double *out, void *ws, size_t ws_bytes,
+                                    void *stream);
+
 /* ---- Alg. 4 (eps-scheduler) ------------------------------------------------
  *
  * The schedule of regularisations that Alg. 2 consumes (pass the result as

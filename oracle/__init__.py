@@ -43,9 +43,10 @@ from .sinkhorn import (cost_matrix, sinkhorn, SinkhornResult, coupling, marginal
 from .entropic_map import entropic_map, map_weights
 from .progot import progot, progot_map, ProgOTResult
 from . import schedules
+from . import metrics
 
 __all__ = [
     "cost_matrix", "sinkhorn", "SinkhornResult", "coupling", "marginal_errors",
     "dual_objective", "primal_objective", "mean_cost", "entropic_map", "map_weights",
-    "progot", "progot_map", "ProgOTResult", "schedules",
+    "progot", "progot_map", "ProgOTResult", "schedules", "metrics",
 ]

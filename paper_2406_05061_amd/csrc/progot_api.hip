@@ -45,8 +45,8 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision) {
     L.errd = take(64);
     L.xst = take((size_t)pot::cloud_stat_blocks(n) * (d + 1) * 8);
     L.yst = take((size_t)pot::cloud_stat_blocks(m) * (d + 1) * 8);
-    L.chr = take((size_t)pot::fp64_check_blocks(n) * 3 * 8);
-    L.chc = take((size_t)pot::fp64_check_blocks(m) * 3 * 8);
+    L.chr = take((size_t)pot::fp64_check_blocks(n) * pot::kCheckParts * 8);
+    L.chc = take((size_t)pot::fp64_check_blocks(m) * pot::kCheckParts * 8);
     L.n64 = take(((size_t)n + (size_t)m) * 8);
     L.total = off;
     return L;
@@ -449,27 +449,108 @@ int pot_progot_map(const pot_clouds *c, int32_t K, const float *G, const float *
     return POT_OK;
 }
 
-int pot_marginal_check(const pot_clouds *c, const float *f, const float *g, float eps, double *out,
-                       void *stream) {
+int pot_coupling_metrics(const pot_clouds *c, const float *f, const float *g, float eps,
+                         double *out, void *stream) {
     if (!valid_clouds(c) || !f || !g || !out || !finite_pos(eps)) return POT_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout L = plan(c->n, c->m, c->d, c->precision);
     const int nbr = pot::fp64_check_blocks(c->n), nbc = pot::fp64_check_blocks(c->m);
+    constexpr int Q = pot::kCheckParts;
     POT_TRY(pot::launch_fp64_check(c->xk, c->n, c->Y, c->m, c->d, f, g, c->a, c->b, eps,
                                    at<double>(c, L.n64), at<double>(c, L.n64) + c->n,
                                    at<double>(c, L.chr), at<double>(c, L.chc), s));
-    std::vector<double> hr(3 * (size_t)nbr), hc(3 * (size_t)nbc);
+    std::vector<double> hr(Q * (size_t)nbr), hc(Q * (size_t)nbc);
     POT_TRY(hipMemcpyAsync(hr.data(), at<double>(c, L.chr), hr.size() * 8, hipMemcpyDeviceToHost, s));
     POT_TRY(hipMemcpyAsync(hc.data(), at<double>(c, L.chc), hc.size() * 8, hipMemcpyDeviceToHost, s));
     POT_TRY(hipStreamSynchronize(s));
-    double row = 0, mass = 0, fa = 0, col = 0, gb = 0;
-    for (int b = 0; b < nbr; ++b) { row += hr[3 * b]; mass += hr[3 * b + 1]; fa += hr[3 * b + 2]; }
-    for (int b = 0; b < nbc; ++b) { col += hc[3 * b]; gb += hc[3 * b + 2]; }
+    double row = 0, mass = 0, fa = 0, pc = 0, plp = 0, col = 0, gb = 0;
+    for (int b = 0; b < nbr; ++b) {
+        row += hr[Q * b]; mass += hr[Q * b + 1]; fa += hr[Q * b + 2];
+        pc += hr[Q * b + 3]; plp += hr[Q * b + 4];
+    }
+    for (int b = 0; b < nbc; ++b) { col += hc[Q * b]; gb += hc[Q * b + 2]; }
     out[0] = row;
     out[1] = col;
     out[2] = fa + gb - (double)eps * mass;
+    out[3] = pc;
+    out[4] = plp;
+    out[5] = mass;
     if (!std::isfinite(row) || !std::isfinite(col)) return POT_ERR_NUMERIC;
     return POT_OK;
+}
+
+int pot_marginal_check(const pot_clouds *c, const float *f, const float *g, float eps, double *out,
+                       void *stream) {
+    if (!out) return POT_ERR_INVALID;
+    double m6[6];
+    const int st = pot_coupling_metrics(c, f, g, eps, m6, stream);
+    if (st == POT_OK || st == POT_ERR_NUMERIC) { out[0] = m6[0]; out[1] = m6[1]; out[2] = m6[2]; }
+    return st;
+}
+
+size_t pot_sinkhorn_divergence_bytes(int64_t n, int64_t m, int32_t d) {
+    if (!valid_sizes(n, m, d, POT_PREC_FP32)) return 0;
+    return std::max({plan(n, m, d, POT_PREC_FP32).total, plan(n, n, d, POT_PREC_FP32).total,
+                     plan(m, m, d, POT_PREC_FP32).total});
+}
+
+int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
+                            const float *a, const float *b, float eps, float tau, int32_t max_iter,
+                            double *out, void *ws, size_t ws_bytes, void *stream) {
+    if (!X || !Y || !out || !ws || !valid_sizes(n, m, d, POT_PREC_FP32) || !std::isfinite(eps) ||
+        eps < 0.f || !finite_pos(tau) || max_iter < 1)
+        return POT_ERR_INVALID;
+    if (ws_bytes < pot_sinkhorn_divergence_bytes(n, m, d)) return POT_ERR_NOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // one pair at a time in the same workspace: (Y, Y) first, whose mean cost
+    // gives the default eps_D = 5 % of the mean intra-target cost
+    struct Pair { const float *U; int64_t nu; const float *wu; const float *V; int64_t nv; const float *wv; };
+    const Pair pairs[3] = {{Y, m, b, Y, m, b}, {X, n, a, Y, m, b}, {X, n, a, X, n, a}};
+    double ot[3];
+    bool all = true;
+    for (int k = 0; k < 3; ++k) {
+        const Pair &q = pairs[k];
+        const Layout L = plan(q.nu, q.nv, d, POT_PREC_FP32);
+        pot_clouds c;
+        int st = pot_prepare_clouds(&c, q.U, q.nu, q.V, q.nv, d, q.wu, q.wv, POT_PREC_FP32, ws,
+                                    L.total, stream);
+        if (st != POT_OK) return st;
+        if (k == 0 && eps == 0.f) eps = (float)(0.05 * c.mean_cost);
+        if (!finite_pos(eps)) return POT_ERR_NUMERIC;
+        SinkResult r;
+        if ((st = sinkhorn_core(&c, L, eps, tau, max_iter, nullptr, 1.f, &r, s)) != POT_OK) return st;
+        all = all && r.converged;
+        double m6[6];
+        if ((st = pot_coupling_metrics(&c, r.f, r.g, eps, m6, stream)) != POT_OK) return st;
+        ot[k] = m6[2];
+    }
+    out[0] = ot[1] - 0.5 * (ot[2] + ot[0]);
+    out[1] = ot[1];
+    out[2] = ot[2];
+    out[3] = ot[0];
+    out[4] = (double)eps;
+    return all ? POT_OK : POT_WARN_NOT_CONVERGED;
+}
+
+int pot_diag_metrics(const pot_clouds *c, const float *f, const float *g, float eps, double *out,
+                     void *stream) {
+    if (!valid_clouds(c) || !f || !g || !out || !finite_pos(eps) || c->n != c->m)
+        return POT_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Layout L = plan(c->n, c->m, c->d, c->precision);
+    // the FP64 norm region holds n + m >= 2 diag_blocks(n) doubles
+    double *part = at<double>(c, L.n64);
+    const int nb = pot::diag_blocks(c->n);
+    POT_TRY(pot::launch_diag_sums(c->xk, c->Y, c->n, c->d, f, g, eps, part, s));
+    std::vector<double> h(2 * (size_t)nb);
+    POT_TRY(hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, s));
+    POT_TRY(hipStreamSynchronize(s));
+    double tr = 0, slp = 0;
+    for (int b = 0; b < nb; ++b) { tr += h[2 * b]; slp += h[2 * b + 1]; }
+    const double n = (double)c->n;
+    out[0] = tr;
+    out[1] = -std::log(n) - slp / n;
+    return std::isfinite(tr) ? POT_OK : POT_ERR_NUMERIC;
 }
 
 }  // extern "C"

@@ -1,9 +1,11 @@
-// FP64 check of a coupling's marginals and dual objective (gfx950).
+// FP64 check and metrics of a coupling (gfx950).
 //
 // For the coupling P_ij = exp((f_i + g_j - C_ij)/eps) of the entropic dual
 // (eq. entdual), one pass over rows gives r_i = sum_j P_ij, the row-marginal
-// L1 sum_i |r_i - a_i|, the mass sum_ij P_ij and <f, a>; the same kernel over
-// columns gives the column-marginal L1 and <g, b>.  Everything is FP64:
+// L1 sum_i |r_i - a_i|, the mass sum_ij P_ij, <f, a>, the transport cost
+// <P, C> = sum_ij P_ij C_ij and sum_ij P_ij log P_ij (log P_ij is the exponent
+// itself, so both are one FMA each per pair); the same kernel over columns
+// gives the column-marginal L1 and <g, b>.  Everything is FP64:
 // C_ij = |x_i|^2 + |y_j|^2 - 2 <x_i, y_j> with FP64 norms of the FP32 inputs
 // and the cross term on v_mfma_f64_16x16x4_f64 (FP64 products of the exact
 // FP32 values, FP64 accumulation), FP64 exp, FP64 sums.
@@ -52,6 +54,7 @@ __global__ __launch_bounds__(256) void fp64_rowsums(
     constexpr int STRIDE = D + 2;
     __shared__ double vt[BN * STRIDE];
     __shared__ double vb[BN];
+    __shared__ double vs[BN];
     __shared__ double red[256];
 
     const int tid = threadIdx.x;
@@ -67,8 +70,9 @@ __global__ __launch_bounds__(256) void fp64_rowsums(
         ub[k] = (live && f < d) ? (double)U[row * d + f] : 0.0;
     }
     const double base = live ? (double)pu[row] - usq[row] : 0.0;   // f_i - |x_i|^2
+    const double usq_i = live ? usq[row] : 0.0;
     const double inv_eps = 1.0 / eps;
-    double rsum = 0.0;
+    double rsum = 0.0, pc = 0.0, plp = 0.0;
 
     for (int64_t j0 = 0; j0 < nv; j0 += BN) {
         for (int e = tid; e < BN * D; e += 256) {
@@ -79,6 +83,7 @@ __global__ __launch_bounds__(256) void fp64_rowsums(
         if (tid < BN) {
             const int64_t j = j0 + tid;
             vb[tid] = j < nv ? (double)pv[j] - vsq[j] : -INFINITY;   // g_j - |y_j|^2
+            vs[tid] = j < nv ? vsq[j] : 0.0;
         }
         __syncthreads();
         d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -87,15 +92,30 @@ __global__ __launch_bounds__(256) void fp64_rowsums(
         // The FP64 16x16 accumulator interleaves its rows: register r of lane
         // l holds row 4 r + l/16 (measured), so acc[r] = <y_{j0 + 4 r + lq}, x_row>.
 #pragma unroll
-        for (int r = 0; r < 4; ++r) rsum += exp((base + vb[4 * r + lq] + 2.0 * acc[r]) * inv_eps);
+        for (int r = 0; r < 4; ++r) {
+            const int jl = 4 * r + lq;
+            const double t = (base + vb[jl] + 2.0 * acc[r]) * inv_eps;   // log P_ij
+            const double p = exp(t);
+            rsum += p;
+            if (vb[jl] > -INFINITY) {
+                pc = fma(p, usq_i + vs[jl] - 2.0 * acc[r], pc);
+                plp = fma(p, t, plp);
+            }
+        }
         __syncthreads();
     }
     rsum += __shfl_xor(rsum, 16);
     rsum += __shfl_xor(rsum, 32);
+    pc += __shfl_xor(pc, 16);
+    pc += __shfl_xor(pc, 32);
+    plp += __shfl_xor(plp, 16);
+    plp += __shfl_xor(plp, 32);
     const bool own = live && lq == 0;
     const double w = own ? (w_in ? (double)w_in[row] : 1.0 / (double)nu) : 0.0;
-    const double vals[3] = {own ? fabs(rsum - w) : 0.0, own ? rsum : 0.0, own ? (double)pu[row] * w : 0.0};
-    for (int q = 0; q < 3; ++q) {
+    const double vals[kCheckParts] = {own ? fabs(rsum - w) : 0.0, own ? rsum : 0.0,
+                                      own ? (double)pu[row] * w : 0.0, own ? pc : 0.0,
+                                      own ? plp : 0.0};
+    for (int q = 0; q < kCheckParts; ++q) {
         __syncthreads();
         red[tid] = vals[q];
         __syncthreads();
@@ -103,7 +123,39 @@ __global__ __launch_bounds__(256) void fp64_rowsums(
             if (tid < s) red[tid] += red[tid + s];
             __syncthreads();
         }
-        if (tid == 0) part[(int64_t)blockIdx.x * 3 + q] = red[0];
+        if (tid == 0) part[(int64_t)blockIdx.x * kCheckParts + q] = red[0];
+    }
+}
+
+// Diagonal of the coupling (n == m): per block, sum_i P_ii and
+// sum_i log P_ii with P_ii = exp((f_i + g_i - |x_i - y_i|^2)/eps), the cost by
+// FP64 direct differences.
+__global__ __launch_bounds__(256) void diag_sums(const float *__restrict__ X, const float *__restrict__ Y,
+                                                 int64_t n, int d, const float *__restrict__ f,
+                                                 const float *__restrict__ g, double eps,
+                                                 double *__restrict__ part) {
+    __shared__ double red[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double lp = 0.0, p = 0.0;
+    if (i < n) {
+        double c = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double e = (double)X[i * d + k] - (double)Y[i * d + k];
+            c = fma(e, e, c);
+        }
+        lp = ((double)f[i] + (double)g[i] - c) / eps;
+        p = exp(lp);
+    }
+    const double vals[2] = {p, lp};
+    for (int q = 0; q < 2; ++q) {
+        __syncthreads();
+        red[threadIdx.x] = vals[q];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * 2 + q] = red[0];
     }
 }
 
@@ -128,6 +180,14 @@ void rowsums(const float *U, int64_t nu, const float *V, int64_t nv, int d, cons
 }  // namespace
 
 int fp64_check_blocks(int64_t n) { return (int)((n + 63) / 64); }
+int diag_blocks(int64_t n) { return (int)((n + 255) / 256); }
+
+hipError_t launch_diag_sums(const float *X, const float *Y, int64_t n, int d, const float *f,
+                            const float *g, float eps, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(diag_sums, dim3((unsigned)diag_blocks(n)), dim3(256), 0, s, X, Y, n, d, f, g,
+                       (double)eps, part);
+    return hipGetLastError();
+}
 
 hipError_t launch_fp64_check(const float *X, int64_t n, const float *Y, int64_t m, int d,
                              const float *f, const float *g, const float *a, const float *b,

@@ -127,14 +127,21 @@ hipError_t launch_bf16_transpose(const float *Y, int64_t m, int d, void *yt, hip
 
 // FP64 check: FP64 norms of X and Y into xsq64/ysq64 (n and m doubles),
 // then row sums and column sums of P in FP64 reduced to per-block partials
-// part[0..3*nb) of (sum |r_i - a_i|, sum r_i, sum f_i a_i) and
-// (sum |c_j - b_j|, sum c_j, sum g_j b_j).  Weights a, b: caller arrays or
-// NULL (uniform, 1/n in FP64).
+// part[0..kCheckParts*nb) of (sum |r_i - a_i|, sum r_i, sum f_i a_i,
+// sum P_ij C_ij, sum P_ij log P_ij) and the same over columns (|c_j - b_j|,
+// c_j, g_j b_j, ...).  Weights a, b: caller arrays or NULL (uniform, 1/n in
+// FP64).
 hipError_t launch_fp64_check(const float *X, int64_t n, const float *Y, int64_t m, int d,
                              const float *f, const float *g, const float *a,
                              const float *b, float eps, double *xsq64, double *ysq64,
                              double *part_rows, double *part_cols, hipStream_t s);
 int fp64_check_blocks(int64_t n);
+constexpr int kCheckParts = 5;
+// Diagonal of the coupling (n == m): per-block partials (sum P_ii,
+// sum log P_ii), diag_blocks(n) blocks of 2 doubles.
+hipError_t launch_diag_sums(const float *X, const float *Y, int64_t n, int d, const float *f,
+                            const float *g, float eps, double *part, hipStream_t s);
+int diag_blocks(int64_t n);
 
 // Launch timing (see pot_timing_enable): kind 0 = cost + log-sum-exp
 // partial kernel, kind 1 = entropic-map kernel.  timing_begin returns an

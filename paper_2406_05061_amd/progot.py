@@ -88,6 +88,12 @@ _SIGS = {
                                  C.POINTER(C.c_float), _vp, _i64, _vp, _vp]),
     "pot_marginal_check": (C.c_int, [C.POINTER(pot_clouds), _vp, _vp, _f32, C.POINTER(C.c_double),
                                      _vp]),
+    "pot_coupling_metrics": (C.c_int, [C.POINTER(pot_clouds), _vp, _vp, _f32, C.POINTER(C.c_double),
+                                       _vp]),
+    "pot_diag_metrics": (C.c_int, [C.POINTER(pot_clouds), _vp, _vp, _f32, C.POINTER(C.c_double), _vp]),
+    "pot_sinkhorn_divergence_bytes": (C.c_size_t, [_i64, _i64, _i32]),
+    "pot_sinkhorn_divergence": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _f32, _f32, _i32,
+                                          C.POINTER(C.c_double), _vp, C.c_size_t, _vp]),
     "pot_eps_schedule_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32]),
     "pot_eps_schedule": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _i32, _i32,
                                    C.POINTER(C.c_double), _i32, _f32, _f32, _i32,
@@ -361,6 +367,56 @@ def eps_schedule(cl: Clouds, Y_test, K: int, *, alpha_sched: str = "constant", s
                                        int(max_iter), eps_c, err_c, C.byref(p_c), _ptr(ws), nb,
                                        C.c_void_p(_stream())), "eps_schedule")
     return EpsSchedule(list(eps_c), list(err_c), int(p_c.value), st)
+
+
+def coupling_metrics(cl: Clouds, f, g, eps: float) -> dict:
+    """FP64 metrics of P = exp((f (+) g - C)/eps) on the current source
+    iterate: marginal L1 errors, the objective of eq. entdual, <P, C>,
+    sum P log P and the mass."""
+    _dev_f32(f, "f", (cl.n,))
+    _dev_f32(g, "g", (cl.m,))
+    out = (C.c_double * 6)()
+    _check(lib().pot_coupling_metrics(C.byref(cl.c), _ptr(f), _ptr(g), float(eps), out,
+                                      C.c_void_p(_stream())), "coupling_metrics", False)
+    return {"row_err": out[0], "col_err": out[1], "ot": out[2], "transport_cost": out[3],
+            "p_log_p": out[4], "mass": out[5]}
+
+
+def diag_metrics(cl: Clouds, f, g, eps: float):
+    """(Tr P, KL(I/n || P)) for n == m (coupling-recovery benchmark)."""
+    _dev_f32(f, "f", (cl.n,))
+    _dev_f32(g, "g", (cl.m,))
+    out = (C.c_double * 2)()
+    _check(lib().pot_diag_metrics(C.byref(cl.c), _ptr(f), _ptr(g), float(eps), out,
+                                  C.c_void_p(_stream())), "diag_metrics", False)
+    return out[0], out[1]
+
+
+def sinkhorn_divergence(X, Y, a=None, b=None, eps: float = 0.0, tau: float = 1e-3,
+                        max_iter: int = 10_000) -> dict:
+    """Sinkhorn divergence (eq. sink_div); eps = 0 uses 5 % of the mean cost
+    within Y (the paper's eps_D)."""
+    torch = _torch()
+    for t, nm in ((X, "X"), (Y, "Y")):
+        _dev_f32(t, nm)
+    n, d = X.shape
+    m = Y.shape[0]
+    if Y.shape[1] != d:
+        raise ValueError("X and Y must have the same dimension")
+    if a is not None:
+        _dev_f32(a, "a", (n,))
+    if b is not None:
+        _dev_f32(b, "b", (m,))
+    nb = int(lib().pot_sinkhorn_divergence_bytes(n, m, d))
+    if nb == 0:
+        raise ValueError("invalid sizes")
+    ws = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    out = (C.c_double * 5)()
+    st = _check(lib().pot_sinkhorn_divergence(_ptr(X), n, _ptr(Y), m, d, _ptr(a), _ptr(b), float(eps),
+                                              float(tau), int(max_iter), out, _ptr(ws), nb,
+                                              C.c_void_p(_stream())), "sinkhorn_divergence")
+    return {"D": out[0], "ot_xy": out[1], "ot_xx": out[2], "ot_yy": out[3], "eps": out[4],
+            "status": st}
 
 
 def marginal_check(cl: Clouds, f, g, eps: float):

@@ -174,3 +174,26 @@ def test_eps_schedule_rejects_invalid_before_launch():
     assert call(wsb=wsb - 1) == B.POT_ERR_NOMEM
     assert lib.pot_eps_schedule(None, 0x4000, 5, 4, 0, grid, 3, 5.0, 1e-3, 100, eps, None, None,
                                 0x2000, wsb, None) == inv
+
+
+def test_metrics_reject_invalid_before_launch():
+    lib = P.lib()
+    inv = B.POT_ERR_INVALID
+    c = _fake_clouds(8, 6, 4)
+    out = (C.c_double * 6)()
+    assert lib.pot_coupling_metrics(C.byref(c), 0x3000, 0x3000, 0.0, out, None) == inv
+    assert lib.pot_coupling_metrics(C.byref(c), None, 0x3000, 1.0, out, None) == inv
+    assert lib.pot_coupling_metrics(C.byref(c), 0x3000, 0x3000, 1.0, None, None) == inv
+    assert lib.pot_diag_metrics(C.byref(c), 0x3000, 0x3000, 1.0, out, None) == inv   # n != m
+    assert lib.pot_sinkhorn_divergence_bytes(0, 5, 4) == 0
+    nb = lib.pot_sinkhorn_divergence_bytes(100, 50, 4)
+    assert nb >= P.workspace_bytes(100, 100, 4)
+    o5 = (C.c_double * 5)()
+    assert lib.pot_sinkhorn_divergence(0x1000, 100, 0x1000, 50, 4, None, None, -1.0, 1e-3, 10, o5,
+                                       0x2000, nb, None) == inv
+    assert lib.pot_sinkhorn_divergence(0x1000, 100, 0x1000, 50, 4, None, None, 0.0, 0.0, 10, o5,
+                                       0x2000, nb, None) == inv
+    assert lib.pot_sinkhorn_divergence(None, 100, 0x1000, 50, 4, None, None, 0.0, 1e-3, 10, o5,
+                                       0x2000, nb, None) == inv
+    assert lib.pot_sinkhorn_divergence(0x1000, 100, 0x1000, 50, 4, None, None, 0.0, 1e-3, 10, o5,
+                                       0x2000, nb - 1, None) == B.POT_ERR_NOMEM

@@ -225,12 +225,97 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+NEXT_WORKLOADS = ("alg4_c1", "divergence_gmm16k")
+
+
+def next_bench(args):
+    """Steps beyond the ProgOT solve, each timed beside the FP64 oracle:
+    alg4_c1 -- Alg. 4 (eps-scheduler, 7 grid scales) on the small ProgOT
+    workload (n = m = 1024, d = 4, 1024 hold-out targets), against the
+    oracle's Alg. 4 on the same problem; divergence_gmm16k -- the Sinkhorn
+    divergence (eq. sink_div, eps_D default, tau 1e-3) of the benchmark's
+    clouds (16384^2, d = 64), against the oracle on a 2048^2 subsample."""
+    import torch
+    import paper_2406_05061_amd as P
+    import oracle
+    from oracle import metrics
+    osk = __import__("importlib").import_module("oracle.sinkhorn")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        P.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        lse_ms, lse_n, _, _ = P.timing_read()
+        P.timing_enable(False)
+        return r, dt, lse_ms / reps, lse_n // reps
+
+    out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    if args.workload == "alg4_c1":
+        X, Y = workloads.c1(seed=1)
+        Yt = workloads.c1_holdout(seed=1, test_seed=101)
+        K, tau = 4, args.tau
+        cl = P.prepare_clouds(P.to_device(X), P.to_device(Y))
+        Ytd = P.to_device(Yt)
+        sched, dt, lse_ms, lse_n = timed(lambda: P.eps_schedule(cl, Ytd, K, tau=tau), args.steps)
+        log(f"bench: alg4_c1: {dt * 1e3:.1f} ms per schedule, p* {sched.p_star}, "
+            f"{lse_n} potential launches")
+        a = np.full(1024, 1.0 / 1024)
+        t0 = time.perf_counter()
+        ref, info = oracle.schedules.eps_scheduler(a, X, a, Y, oracle.schedules.alpha_schedule(K), Yt,
+                                                    beta0=5.0, tau=tau)
+        t_cpu = time.perf_counter() - t0
+        out.update({"value": dt * 1e3, "unit": "ms per schedule", "ms_per_step": dt * 1e3,
+                    "config": {"workload": "alg4_c1", "n": 1024, "m": 1024, "d": 4, "K": K,
+                               "grid": "2^-3..2^3", "m_test": 1024, "tau": tau},
+                    "p_star": sched.p_star, "oracle_p_star": info["p_star"],
+                    "eps": sched.eps, "potential_launches": lse_n,
+                    "potential_kernel_ms": lse_ms,
+                    "cpu_baseline": {"value": t_cpu * 1e3, "unit": "ms per schedule",
+                                     "cores": osk.THREADS, "kind": "oracle",
+                                     "sample": "the full problem (FP64 oracle Alg. 4, 7 grid solves "
+                                               "of 1024 x 1024, hold-out maps)"}})
+    else:
+        X, Y = make_clouds(WORKLOADS["gmm16k_d64_fp32"][0])
+        Xd, Yd = P.to_device(X), P.to_device(Y)
+        res, dt, lse_ms, lse_n = timed(lambda: P.sinkhorn_divergence(Xd, Yd, tau=args.tau), args.steps)
+        n, d = X.shape
+        flops = 2.0 * n * n * d * lse_n
+        log(f"bench: divergence_gmm16k: D {res['D']:.6g} eps {res['eps']:.4g} in {dt * 1e3:.1f} ms, "
+            f"{lse_n} potential launches")
+        idx = workloads.subsample_index(n, 2048, seed=33)
+        idy = workloads.subsample_index(n, 2048, seed=34)
+        a = np.full(2048, 1.0 / 2048)
+        t0 = time.perf_counter()
+        refD = metrics.sinkhorn_divergence(a, X[idx], a, Y[idy], eps=res["eps"], tau=args.tau)
+        t_cpu = time.perf_counter() - t0
+        out.update({"value": dt * 1e3, "unit": "ms per divergence", "ms_per_step": dt * 1e3,
+                    "config": {"workload": "divergence_gmm16k", "n": n, "m": n, "d": d,
+                               "eps": "5% of the mean cost within Y", "tau": args.tau},
+                    "D": res["D"], "eps_D": res["eps"], "potential_launches": lse_n,
+                    "roofline": {"bound": "mfma", "achieved": flops / (lse_ms * 1e-3) / 1e12,
+                                 "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                                 "frac": flops / (lse_ms * 1e-3) / 1e12 / PEAK["fp32"],
+                                 "traffic": None, "kernel": "lse_partial (fused cost + log-sum-exp)"},
+                    "cpu_baseline": {"value": t_cpu * 1e3, "unit": "ms per divergence",
+                                     "cores": osk.THREADS, "kind": "oracle",
+                                     "sample": f"FP64 oracle divergence on a 2048 x 2048 seeded "
+                                               f"subsample (D = {refD[0]:.6g}), same eps_D and tau"}})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gmm16k_d64_fp32", choices=sorted(WORKLOADS) + ["serve"])
+    ap.add_argument("--workload", default="gmm16k_d64_fp32",
+                    choices=sorted(WORKLOADS) + ["serve", *NEXT_WORKLOADS])
     ap.add_argument("--requests", type=int, default=128, help="serve: number of requests")
     ap.add_argument("--max-active", type=int, default=128, help="serve: server slots")
     ap.add_argument("--arena-gib", type=int, default=16, help="serve: HBM budget of the server")
@@ -255,6 +340,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "serve":
         serve_bench(args)
+        return
+    if args.workload in NEXT_WORKLOADS:
+        next_bench(args)
         return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20

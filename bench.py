@@ -34,7 +34,7 @@ METRIC = "ProgOT solve time @ marginal err 1e-3; n·m·iters/s; serve p50/p99 la
 # BF16 products per algorithmic product, so its ceiling is the BF16 peak / 3.
 PEAK = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3}
 PAD = {16: 16, 64: 64, 128: 128, 256: 256}  # template dimension of the kernel per d
-QB = {16: 2, 64: 2, 128: 2, 256: 1}
+QB = {16: 4, 64: 4, 128: 2, 256: 1}
 
 _SPHERE64K = dict(kind="sphere", seed=3, n=65536, m=65536, d=256, n_clusters=32)
 _SPHERE256K = dict(kind="sphere", seed=5, n=262144, m=262144, d=128, n_clusters=64,

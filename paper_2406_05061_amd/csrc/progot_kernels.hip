@@ -223,16 +223,6 @@ __global__ __launch_bounds__(256) void lse_partial_f32(LseJob J) {
     lse_partial_body<D, QB>(J, blockIdx.x / J.S, blockIdx.x % J.S, vt, bt);
 }
 
-// d <= 64: the register budget of 3 waves per SIMD holds without spills and
-// the extra wave hides the log-sum-exp epilogue behind other waves' MFMAs.
-template <int D, int QB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
-void lse_partial_f32_o3(LseJob J) {
-    __shared__ float vt[2][Tile<D>::BN * Tile<D>::STRIDE];
-    __shared__ float bt[2][Tile<D>::BN];
-    lse_partial_body<D, QB>(J, blockIdx.x / J.S, blockIdx.x % J.S, vt, bt);
-}
-
 // Index of the job owning flattened block `item` (jobs sorted by `begin`).
 template <bool MERGE>
 __device__ __forceinline__ int find_job(const LseJob *__restrict__ jobs, int njobs, int64_t item) {
@@ -250,8 +240,7 @@ __device__ __forceinline__ int find_job(const LseJob *__restrict__ jobs, int njo
 // first-block offsets and runs the same body as the single-job kernel, so
 // every problem gets the same bits as when it runs alone.
 template <int D, int QB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(D <= 64 ? 3 : 1, 8)))
-void lse_partial_f32_group(const LseJob *__restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(256) void lse_partial_f32_group(const LseJob *__restrict__ jobs, int njobs) {
     __shared__ float vt[2][Tile<D>::BN * Tile<D>::STRIDE];
     __shared__ float bt[2][Tile<D>::BN];
     const LseJob &J = jobs[find_job<false>(jobs, njobs, blockIdx.x)];
@@ -585,10 +574,7 @@ template <int D, int QB>
 hipError_t lse_launch_t(const LseJob &j, hipStream_t s) {
     // the plan must cover every row tile of this kernel variant
     if (j.blocks != (j.nu + 64 * QB - 1) / (64 * QB) * j.S) return hipErrorInvalidValue;
-    if constexpr (D <= 64)
-        hipLaunchKernelGGL((lse_partial_f32_o3<D, QB>), dim3((unsigned)j.blocks), dim3(256), 0, s, j);
-    else
-        hipLaunchKernelGGL((lse_partial_f32<D, QB>), dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+    hipLaunchKernelGGL((lse_partial_f32<D, QB>), dim3((unsigned)j.blocks), dim3(256), 0, s, j);
     return hipGetLastError();
 }
 
@@ -617,10 +603,14 @@ int padded_dim(int d) {
 }
 
 int qb_for(int D) { return D >= 256 ? 1 : 2; }
+// Row blocks per wave of the potential kernel: four for D <= 64 (each column
+// fragment read from LDS feeds four MFMA chains; measured 5 % faster on the
+// benchmark workload than two, at two waves per SIMD instead of three).
+constexpr int lse_qb(int D) { return D <= 64 ? 4 : (D >= 256 ? 1 : 2); }
 
 }  // namespace
 
-int lse_rows_per_block(int d) { return 64 * qb_for(padded_dim(d)); }
+int lse_rows_per_block(int d) { return 64 * lse_qb(padded_dim(d)); }
 int map_rows_per_block(int d) { return 64 * qb_for(padded_dim(d)); }
 
 int padded_dim_f32(int d) { return padded_dim(d); }
@@ -671,11 +661,11 @@ hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
     if (j.precision != 0) {
         e = launch_lse_partial_bf16(j, s);
     } else switch (padded_dim(j.d)) {
-        case 16: e = lse_launch_t<16, 2>(j, s); break;
-        case 32: e = lse_launch_t<32, 2>(j, s); break;
-        case 64: e = lse_launch_t<64, 2>(j, s); break;
-        case 128: e = lse_launch_t<128, 2>(j, s); break;
-        default: e = lse_launch_t<256, 1>(j, s); break;
+        case 16: e = lse_launch_t<16, lse_qb(16)>(j, s); break;
+        case 32: e = lse_launch_t<32, lse_qb(32)>(j, s); break;
+        case 64: e = lse_launch_t<64, lse_qb(64)>(j, s); break;
+        case 128: e = lse_launch_t<128, lse_qb(128)>(j, s); break;
+        default: e = lse_launch_t<256, lse_qb(256)>(j, s); break;
     }
     timing_end(slot, s);
     if (e != hipSuccess) return e;
@@ -703,11 +693,11 @@ hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, fl
     if (e != hipSuccess) return e;
     const int64_t slot = timing_begin(0, s);
     switch (D) {
-        case 16: e = lse_group_launch_t<16, 2>(jobs_dev, njobs, blk, s); break;
-        case 32: e = lse_group_launch_t<32, 2>(jobs_dev, njobs, blk, s); break;
-        case 64: e = lse_group_launch_t<64, 2>(jobs_dev, njobs, blk, s); break;
-        case 128: e = lse_group_launch_t<128, 2>(jobs_dev, njobs, blk, s); break;
-        default: e = lse_group_launch_t<256, 1>(jobs_dev, njobs, blk, s); break;
+        case 16: e = lse_group_launch_t<16, lse_qb(16)>(jobs_dev, njobs, blk, s); break;
+        case 32: e = lse_group_launch_t<32, lse_qb(32)>(jobs_dev, njobs, blk, s); break;
+        case 64: e = lse_group_launch_t<64, lse_qb(64)>(jobs_dev, njobs, blk, s); break;
+        case 128: e = lse_group_launch_t<128, lse_qb(128)>(jobs_dev, njobs, blk, s); break;
+        default: e = lse_group_launch_t<256, lse_qb(256)>(jobs_dev, njobs, blk, s); break;
     }
     timing_end(slot, s);
     if (e != hipSuccess) return e;

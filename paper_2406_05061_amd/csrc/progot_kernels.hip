@@ -28,8 +28,8 @@
 namespace pot {
 namespace {
 
-template <int D> struct Tile {
-    static constexpr int BN = D >= 256 ? 32 : 64;   // columns per LDS tile
+template <int D, int BN_ = (D >= 256 ? 32 : 64)> struct Tile {
+    static constexpr int BN = BN_;                 // columns per LDS tile
     static constexpr int NSUB = BN / 16;           // 16-column subtiles
     static constexpr int KD = D / 4;               // features per lane group
     static constexpr int STRIDE = D + 4;           // padded LDS row (floats)
@@ -39,10 +39,10 @@ template <int D> struct Tile {
 
 // Load one BN x D column tile (rows j0.., zero-padded beyond nv and beyond
 // feature d) into registers; thread t takes float4 slots t, t+256, ...
-template <int D>
+template <int D, int BN>
 __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t nv, int d,
-                                           int64_t j0, f4 (&pre)[Tile<D>::PER_T]) {
-    using T = Tile<D>;
+                                           int64_t j0, f4 (&pre)[Tile<D, BN>::PER_T]) {
+    using T = Tile<D, BN>;
 #pragma unroll
     for (int r = 0; r < T::PER_T; ++r) {
         const int e = threadIdx.x + 256 * r;
@@ -67,9 +67,9 @@ __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t 
     }
 }
 
-template <int D>
-__device__ __forceinline__ void tile_store(float *__restrict__ lds, const f4 (&pre)[Tile<D>::PER_T]) {
-    using T = Tile<D>;
+template <int D, int BN>
+__device__ __forceinline__ void tile_store(float *__restrict__ lds, const f4 (&pre)[Tile<D, BN>::PER_T]) {
+    using T = Tile<D, BN>;
 #pragma unroll
     for (int r = 0; r < T::PER_T; ++r) {
         const int e = threadIdx.x + 256 * r;
@@ -84,11 +84,16 @@ __device__ __forceinline__ void tile_store(float *__restrict__ lds, const f4 (&p
 // Partial log-sum-exp of t_ij over one column split, for ROWS = 64*QB rows
 // (row tile `tile`, column split `split` of job J).
 // Output: part_m/part_s[split*nu + i] = (max, sum 2^{t - max}) in log2 units.
+// Column tile of the potential kernel (128 columns at D = 64 measured 6 %
+// slower than 64: one workgroup fewer per CU by LDS).
+constexpr int lse_bn(int D) { return D >= 256 ? 32 : 64; }
+template <int D> using LseTile = Tile<D, lse_bn(D)>;
+
 template <int D, int QB>
 __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, int split,
-                                                 float (&vt)[2][Tile<D>::BN * Tile<D>::STRIDE],
-                                                 float (&bt)[2][Tile<D>::BN]) {
-    using T = Tile<D>;
+                                                 float (&vt)[2][LseTile<D>::BN * LseTile<D>::STRIDE],
+                                                 float (&bt)[2][LseTile<D>::BN]) {
+    using T = LseTile<D>;
     constexpr int ROWS = 64 * QB;
     const float *__restrict__ U = J.U;
     const float *__restrict__ V = J.V;
@@ -136,9 +141,9 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
         }
     };
     if (ntiles > 0) {
-        tile_fetch<D>(V, c1, d, c0, pre);
+        tile_fetch<D, T::BN>(V, c1, d, c0, pre);
         fetch_beta(c0);
-        tile_store<D>(vt[0], pre);
+        tile_store<D, T::BN>(vt[0], pre);
         if (tid < T::BN) bt[0][tid] = bpre;
     }
     __syncthreads();
@@ -148,7 +153,7 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
         const bool more = t + 1 < ntiles;
         if (more) {
             const int64_t jn = c0 + (int64_t)(t + 1) * T::BN;
-            tile_fetch<D>(V, c1, d, jn, pre);
+            tile_fetch<D, T::BN>(V, c1, d, jn, pre);
             fetch_beta(jn);
         }
         const float *vb = vt[buf];
@@ -189,7 +194,7 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
             run_m[qb] = mn;
         }
         if (more) {
-            tile_store<D>(vt[buf ^ 1], pre);
+            tile_store<D, T::BN>(vt[buf ^ 1], pre);
             if (tid < T::BN) bt[buf ^ 1][tid] = bpre;
         }
         __syncthreads();
@@ -218,8 +223,8 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
 // b mod 8, so with S = 8 each XCD streams one eighth of the columns).
 template <int D, int QB>
 __global__ __launch_bounds__(256) void lse_partial_f32(LseJob J) {
-    __shared__ float vt[2][Tile<D>::BN * Tile<D>::STRIDE];
-    __shared__ float bt[2][Tile<D>::BN];
+    __shared__ float vt[2][LseTile<D>::BN * LseTile<D>::STRIDE];
+    __shared__ float bt[2][LseTile<D>::BN];
     lse_partial_body<D, QB>(J, blockIdx.x / J.S, blockIdx.x % J.S, vt, bt);
 }
 
@@ -241,8 +246,8 @@ __device__ __forceinline__ int find_job(const LseJob *__restrict__ jobs, int njo
 // every problem gets the same bits as when it runs alone.
 template <int D, int QB>
 __global__ __launch_bounds__(256) void lse_partial_f32_group(const LseJob *__restrict__ jobs, int njobs) {
-    __shared__ float vt[2][Tile<D>::BN * Tile<D>::STRIDE];
-    __shared__ float bt[2][Tile<D>::BN];
+    __shared__ float vt[2][LseTile<D>::BN * LseTile<D>::STRIDE];
+    __shared__ float bt[2][LseTile<D>::BN];
     const LseJob &J = jobs[find_job<false>(jobs, njobs, blockIdx.x)];
     if (J.ctl && *(volatile const int *)J.ctl != 0) return;   // loop already stopped
     const int64_t local = (int64_t)blockIdx.x - J.blk_begin;
@@ -445,9 +450,9 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
         }
     };
     if (ntiles > 0) {
-        tile_fetch<D>(Y, m, d, 0, pre);
+        tile_fetch<D, T::BN>(Y, m, d, 0, pre);
         fetch_beta(0);
-        tile_store<D>(vt[0], pre);
+        tile_store<D, T::BN>(vt[0], pre);
         if (tid < T::BN) bt[0][tid] = bpre;
     }
     __syncthreads();
@@ -457,7 +462,7 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
         const bool more = t + 1 < ntiles;
         if (more) {
             const int64_t jn = (int64_t)(t + 1) * T::BN;
-            tile_fetch<D>(Y, m, d, jn, pre);
+            tile_fetch<D, T::BN>(Y, m, d, jn, pre);
             fetch_beta(jn);
         }
         const float *vb = vt[buf];
@@ -523,7 +528,7 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
                 }
         }
         if (more) {
-            tile_store<D>(vt[buf ^ 1], pre);
+            tile_store<D, T::BN>(vt[buf ^ 1], pre);
             if (tid < T::BN) bt[buf ^ 1][tid] = bpre;
         }
         __syncthreads();

@@ -35,6 +35,10 @@ Readings of the paper adopted here (garbled or silent passages):
   printed; a switch selects (1 - alpha_{k-1}).
 * a stopped-at-max_iter solve is reported, not fatal ("infinite iteration
   budget" in Sec. 5.2 is not runnable).
+* general costs (``pcost``): h = (1/p)|.|_p^p, the form of Sec. 5.2 and of
+  the map appendix (whose "1.5 |.|_1.5" is read as this h with p = 1.5);
+  potentials keep the convention above and the per-step eps rule uses the
+  mean of h over all pairs.
 
 Parity pins for every function are in ``tests/test_oracle_*.py``.
 """
@@ -44,9 +48,10 @@ from .entropic_map import entropic_map, map_weights
 from .progot import progot, progot_map, ProgOTResult
 from . import schedules
 from . import metrics
+from . import pcost
 
 __all__ = [
     "cost_matrix", "sinkhorn", "SinkhornResult", "coupling", "marginal_errors",
     "dual_objective", "primal_objective", "mean_cost", "entropic_map", "map_weights",
-    "progot", "progot_map", "ProgOTResult", "schedules", "metrics",
+    "progot", "progot_map", "ProgOTResult", "schedules", "metrics", "pcost",
 ]

@@ -225,7 +225,13 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
-NEXT_WORKLOADS = ("alg4_c1", "divergence_gmm16k")
+NEXT_WORKLOADS = ("alg4_c1", "divergence_gmm16k", "pcost_4i_d47")
+# The cost h = (1/p)|.|_p^p, p = 1.5, at the shape of the paper's coupling
+# experiment on single-cell data (about 11000 control and 2800 treated cells,
+# 47 features), K = 4 constant speed, eps_k = 2^-4 mean cost / 20, tau 1e-3:
+# two 10-component Gaussian mixtures stand in for the cells.
+_PCOST = dict(kind="gmm", seed=12, n=11000, m=2800, d=47, n_comp=10)
+HBM_PEAK_GBS = 8000.0
 
 
 def next_bench(args):
@@ -256,6 +262,9 @@ def next_bench(args):
 
     out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": 1, "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    if args.workload == "pcost_4i_d47":
+        pcost_bench(args, out)
+        return
     if args.workload == "alg4_c1":
         X, Y = workloads.c1(seed=1)
         Yt = workloads.c1_holdout(seed=1, test_seed=101)
@@ -309,6 +318,79 @@ def next_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def pcost_bench(args, out):
+    """ProgOT with h = (1/p)|.|_p^p, p = 1.5 (Sec. 5.2's second cost).  A step
+    is one ProgOT solve: per step the cost matrix of (X^(k), Y) is built once
+    (VALU), each Sinkhorn half-iteration streams it (row or column
+    log-sum-exp), and the McCann step runs the fused p-cost map.  The
+    roofline is the potential kernels' HBM bound: algorithmic bytes per
+    launch = n m 4 (the cost matrix read once) over the average launch."""
+    import torch
+    import paper_2406_05061_amd as P
+    from oracle import pcost
+    osk = __import__("importlib").import_module("oracle.sinkhorn")
+    p, K, theta, tau = 1.5, 4, 2.0 ** -4, args.tau
+    X, Y = make_clouds(_PCOST)
+    n, d = X.shape
+    m = Y.shape[0]
+    log(f"bench: pcost_4i_d47: n={n} m={m} d={d} p={p} K={K} theta={theta} tau={tau}")
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), cost_p=p)
+
+    def step():
+        # run to convergence, as the coupling experiment does; the last solve
+        # starts cold (the printed warm start scales by 1 - alpha_{K-1} = 0)
+        return P.progot_solve(cl, K, theta=theta, tau_first=tau, tau_last=tau,
+                              max_iter=args.max_iter)
+
+    _, _, _, info = step()
+    log(f"bench: warmup: iters {info.iters} in {info.seconds:.3f} s")
+    torch.cuda.synchronize()
+    P.timing_enable(True)
+    iters_total, infos = 0, []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f, G, TX, info = step()
+        iters_total += sum(info.iters)
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lse_ms, lse_n, map_ms, map_n = P.timing_read()
+    P.timing_enable(False)
+    row, col, _ = P.marginal_check(cl, f, G[-1], infos[-1].eps[-1])
+    avg_lse = lse_ms * 1e-3 / max(lse_n, 1)
+    gbs = n * m * 4 / avg_lse / 1e9
+    log(f"bench: {args.steps} solves in {elapsed:.3f} s; iters {infos[-1].iters}; potential launch "
+        f"{avg_lse * 1e6:.1f} us = {gbs:.0f} GB/s; FP64 marginal L1 row {row:.3e} col {col:.3e}")
+    out.update({"value": n * m * iters_total / elapsed, "unit": "n·m·iters/s", "higher_is_better": True,
+                "ms_per_step": elapsed / args.steps * 1e3, "solve_time_s": elapsed / args.steps,
+                "config": {"workload": "pcost_4i_d47", "n": n, "m": m, "d": d, "cost": "(1/p)|.|_p^p",
+                           "p": p, "K": K, "theta": theta, "tau": tau, "alpha": "constant speed"},
+                "sinkhorn_iters_per_solve": infos[-1].iters,
+                "final_marginal_l1_fp64": {"row": row, "col": col},
+                "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                             "kernel": "pcost_lse_rows / pcost_lse_cols (resident cost matrix)",
+                             "avg_launch_us": avg_lse * 1e6, "launches": lse_n,
+                             "bytes_per_launch": n * m * 4},
+                "map_kernel": {"avg_launch_us": map_ms * 1e3 / max(map_n, 1), "launches": map_n}})
+    if not args.no_cpu_baseline:
+        ns, ms, it = 2048, 512, 100
+        idx = workloads.subsample_index(n, ns, seed=33)
+        idy = workloads.subsample_index(m, ms, seed=34)
+        t0 = time.perf_counter()
+        Cs = pcost.cost_matrix_p(X[idx], Y[idy], p)
+        r = osk.sinkhorn(np.full(ns, 1.0 / ns), X[idx], np.full(ms, 1.0 / ms), Y[idy],
+                         theta * Cs.mean() / 20.0, tau, max_iter=it, C=Cs)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": ns * ms * r.iters / dt, "unit": "n·m·iters/s", "cores": osk.THREADS,
+            "kind": "oracle",
+            "sample": f"FP64 oracle Sinkhorn for the same cost on a {ns}x{ms} seeded subsample, "
+                      f"eps = 2^-4 mean cost/20, tau {tau}, {r.iters} iterations (max {it}), cost "
+                      f"matrix build included, {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +402,7 @@ def main():
     ap.add_argument("--max-active", type=int, default=128, help="serve: server slots")
     ap.add_argument("--arena-gib", type=int, default=16, help="serve: HBM budget of the server")
     ap.add_argument("--tau", type=float, default=1e-3)
+    ap.add_argument("--max-iter", type=int, default=100_000, help="pcost_4i_d47: per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--cpu-iters", type=int, default=20)

@@ -87,9 +87,12 @@ typedef struct pot_clouds {
     float *log_a, *log_b;  /* log weights (device)                              */
     void *x_lp, *y_lp;     /* BF16 [hi | lo] copies of xk and Y (BF16 forms)   */
     void *yt_lp;           /* transposed BF16 [hi | lo] copy of Y (BF16 forms)  */
-    double mean_cost;      /* (1/nm) sum_ij |x_i - y_j|^2 for the current xk    */
+    double mean_cost;      /* (1/nm) sum_ij h(x_i - y_j) for the current xk     */
     void *ws;              /* workspace base (device)                           */
     size_t ws_bytes;
+    float cost_p;          /* 0: h = |.|^2; p > 1: h = (1/p)|.|_p^p             */
+    float *cmat;           /* cost_p > 0: C_ij = h(xk_i - y_j), n x ldc (device) */
+    int64_t ldc;           /* row stride of cmat (m rounded up to 4)            */
 } pot_clouds;
 
 /* Bytes of device workspace pot_prepare_clouds needs for these sizes (the
@@ -107,6 +110,35 @@ POT_API size_t pot_workspace_bytes(int64_t n, int64_t m, int32_t d, int32_t prec
 POT_API int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
                        int32_t d, const float *a, const float *b, int32_t precision,
                        void *ws, size_t ws_bytes, void *stream);
+
+/* ---- General costs h(z) = (1/p) sum_k |z_k|^p ---------------------------
+ *
+ * ProgOT holds for any strictly convex translation-invariant cost (Sec. 3);
+ * the coupling experiments of Sec. 5.2 and the map appendix use this h with
+ * p = 1.5.  Clouds prepared with pot_prepare_clouds_pcost run every call
+ * below with that cost instead of |x - y|^2:
+ *   pot_sinkhorn_solve, pot_progot_solve: Alg. 1 / Alg. 2 on C_ij =
+ *     h(x_i - y_j), the potentials in the same convention (P_ij =
+ *     exp((f_i + g_j - C_ij)/eps)); eps_mode 0 uses theta * mean_ij C_ij/20
+ *     per step (App. C);
+ *   pot_entropic_map, pot_progot_map: the step of Alg. 2 / Alg. 3 for h,
+ *     Xout = Xq - alpha grad h*(sum_j p_j grad h(Xq - y_j)), p_j =
+ *     softmax_j((g_j - h(Xq - y_j))/eps), with grad h(z)_k = sign(z_k)
+ *     |z_k|^(p-1) and grad h*(w)_k = sign(w_k) |w_k|^(1/(p-1)) (eq. Tent;
+ *     alpha = 1 gives T itself);
+ *   pot_coupling_metrics, pot_marginal_check, pot_diag_metrics: C in FP64 by
+ *     direct differences.
+ * FP32 only (there is no inner-product form to put on MFMA).  The cost
+ * matrix of the current source iterate is kept in the workspace (n x ldc
+ * floats, rebuilt when the iterate moves), so the workspace grows with n m.
+ * pot_eps_schedule and the serving form take squared-Euclidean clouds only
+ * (POT_ERR_INVALID otherwise).
+ *   1 < p <= 16; p == 1.5 takes a square-root path, other p a log/exp path.
+ *   Limits: n * m <= 2^36. */
+POT_API size_t pot_workspace_bytes_pcost(int64_t n, int64_t m, int32_t d, float p);
+POT_API int pot_prepare_clouds_pcost(pot_clouds *c, const float *X, int64_t n, const float *Y,
+                                     int64_t m, int32_t d, const float *a, const float *b, float p,
+                                     void *ws, size_t ws_bytes, void *stream);
 
 typedef struct {
     int32_t iters;         /* full (f, g) iterations of the returned iterate     */
@@ -234,7 +266,8 @@ POT_API int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, i
  *           (1 - alpha_l) of the alpha schedule (K = 1: eps_final).
  * The grid solves run in FP32 and advance together in grouped launches; each
  * gets the same result as pot_sinkhorn_solve on (Y, Y) at its eps.
- *   c: prepared clouds (any precision; only Y, b, m, d, mean_cost are used).
+ *   c: prepared clouds (any precision, squared-Euclidean cost; only Y, b, m,
+ *      d, mean_cost are used).
  *   Y_test (device, m_test*d): hold-out targets.
  *   s_grid (host, n_grid doubles > 0), 1 <= n_grid <= POT_MAX_GRID.
  *   eps_out (host, K doubles); err_out (host, n_grid doubles) and p_star

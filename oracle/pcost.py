@@ -137,7 +137,8 @@ def progot_p(a, X, b, Y, K: int, p: float, *, alpha_kind: str = "constant", eps=
     """Alg. 2 for the cost h: K warm-started Sinkhorn solves on C(X^(k), Y),
     each followed by X^(k+1) = X^(k) - alpha_k Z (warm start (1 - alpha_k),
     as printed).  eps: None for eps_k = theta * mean C(X^(k), Y)/20, or an
-    explicit schedule."""
+    explicit schedule.  n_iter: None (stop on tau), one count for every
+    solve, or one count per solve."""
     alpha = schedules.alpha_schedule(K, alpha_kind)
     taus = np.broadcast_to(np.asarray(tau, dtype=np.float64), (K,))
     Xk = _f64(X).copy()
@@ -147,6 +148,7 @@ def progot_p(a, X, b, Y, K: int, p: float, *, alpha_kind: str = "constant", eps=
     G = np.zeros((K, m))
     eps_used = np.zeros(K)
     out = ProgOTpResult(f=f, G=G, eps=eps_used, alpha=alpha)
+    its = [n_iter] * K if n_iter is None or np.isscalar(n_iter) else list(n_iter)
     for k in range(K):
         C = cost_matrix_p(Xk, Yd, p)
         mc = float(C.mean())
@@ -155,7 +157,7 @@ def progot_p(a, X, b, Y, K: int, p: float, *, alpha_kind: str = "constant", eps=
         eps_used[k] = eps_k
         w = alpha[k]
         res = sinkhorn(a, Xk, b, Yd, eps_k, float(taus[k]), (1.0 - w) * f, (1.0 - w) * g_prev,
-                       max_iter=max_iter, n_iter=n_iter, C=C)
+                       max_iter=max_iter, n_iter=its[k], C=C)
         f = res.f
         G[k] = res.g
         g_prev = res.g

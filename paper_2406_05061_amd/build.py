@@ -14,7 +14,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libprogot.so"
 SOURCES = ["progot_kernels.hip", "progot_kernels_bf16.hip", "progot_check.hip", "progot_api.hip", "progot_server.hip",
-           "progot_sched.hip", "progot_timing.hip"]
+           "progot_sched.hip", "progot_timing.hip", "progot_pcost.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -18,7 +18,7 @@ namespace host {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision) {
+Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
@@ -48,9 +48,17 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision) {
     L.chr = take((size_t)pot::fp64_check_blocks(n) * pot::kCheckParts * 8);
     L.chc = take((size_t)pot::fp64_check_blocks(m) * pot::kCheckParts * 8);
     L.n64 = take(((size_t)n + (size_t)m) * 8);
+    // general costs: the cost matrix of (xk, Y), its block sums (+ the
+    // total), and the accumulator partials of the split map kernel
+    const bool pc = cost_p != 0.f;
+    L.cm = take(pc ? (size_t)n * (size_t)pot::pcost_ldc(m) * 4 : 0);
+    L.cmp = take(pc ? ((size_t)pot::pcost_matrix_blocks(n, m) + 1) * 8 : 0);
+    L.mpa = take(pc ? (size_t)pot::pcost_map_max_split() * n * pot::pcost_pad_dim(d) * 4 : 0);
     L.total = off;
     return L;
 }
+
+bool valid_cost_p(float p) { return p == 0.f || (std::isfinite(p) && p > 1.f && p <= 16.f); }
 
 bool valid_sizes(int64_t n, int64_t m, int32_t d, int32_t precision) {
     return n >= 1 && m >= 1 && d >= 1 && d <= POT_MAX_D &&
@@ -61,9 +69,11 @@ bool valid_sizes(int64_t n, int64_t m, int32_t d, int32_t precision) {
 
 bool valid_clouds(const pot_clouds *c) {
     if (!c || !c->ws || !c->X || !c->Y || !c->xk) return false;
-    if (!valid_sizes(c->n, c->m, c->d, c->precision)) return false;
+    if (!valid_sizes(c->n, c->m, c->d, c->precision) || !valid_cost_p(c->cost_p)) return false;
     if (c->precision != POT_PREC_FP32 && (!c->x_lp || !c->y_lp || !c->yt_lp)) return false;
-    return c->ws_bytes >= plan(c->n, c->m, c->d, c->precision).total;
+    if (c->cost_p != 0.f && (c->precision != POT_PREC_FP32 || !c->cmat || c->ldc != pot::pcost_ldc(c->m)))
+        return false;
+    return c->ws_bytes >= plan(c->n, c->m, c->d, c->precision, c->cost_p).total;
 }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
@@ -74,7 +84,7 @@ double now_s() {
 
 void bind_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
                  const float *a, const float *b, int32_t precision, void *ws, size_t ws_bytes,
-                 const Layout &L) {
+                 const Layout &L, float cost_p) {
     std::memset(c, 0, sizeof(*c));
     c->n = n; c->m = m; c->d = d; c->precision = precision;
     c->X = X; c->Y = Y; c->a = a; c->b = b; c->ws = ws; c->ws_bytes = ws_bytes;
@@ -86,6 +96,21 @@ void bind_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64
     c->x_lp = precision != POT_PREC_FP32 ? at<void>(c, L.xlp) : nullptr;
     c->y_lp = precision != POT_PREC_FP32 ? at<void>(c, L.ylp) : nullptr;
     c->yt_lp = precision != POT_PREC_FP32 ? at<void>(c, L.ytl) : nullptr;
+    c->cost_p = cost_p;
+    c->cmat = cost_p != 0.f ? at<float>(c, L.cm) : nullptr;
+    c->ldc = cost_p != 0.f ? pot::pcost_ldc(m) : 0;
+}
+
+int refresh_pcost(pot_clouds *c, const Layout &L, hipStream_t s) {
+    double *part = at<double>(c, L.cmp);
+    const int64_t nb = pot::pcost_matrix_blocks(c->n, c->m);
+    POT_TRY(pot::launch_pcost_matrix(c->xk, c->n, c->Y, c->m, c->d, c->cost_p, c->cmat, c->ldc, part,
+                                     part + nb, s));
+    double sum = 0.0;
+    POT_TRY(hipMemcpyAsync(&sum, part + nb, sizeof(double), hipMemcpyDeviceToHost, s));
+    POT_TRY(hipStreamSynchronize(s));
+    c->mean_cost = sum / ((double)c->n * (double)c->m);
+    return std::isfinite(c->mean_cost) ? POT_OK : POT_ERR_NUMERIC;
 }
 
 int enqueue_moments(pot_clouds *c, const Layout &L, double *host, hipStream_t s) {
@@ -123,6 +148,7 @@ LseJob f_job(const pot_clouds *c, const Layout &L, float eps) {
     a.V = c->Y; a.V_lp = c->y_lp; a.nv = c->m; a.vsq = c->y_sqn;
     a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
     a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = at<float>(c, L.errp);
+    if (c->cost_p != 0.f) { a.cmat = c->cmat; a.ldc = c->ldc; a.cmat_cols = 0; a.usq = nullptr; }
     return a;
 }
 
@@ -132,6 +158,7 @@ LseJob g_job(const pot_clouds *c, const Layout &L, float eps) {
     a.V = c->xk; a.V_lp = c->x_lp; a.nv = c->n; a.vsq = c->x_sqn;
     a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
     a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = nullptr;
+    if (c->cost_p != 0.f) { a.cmat = c->cmat; a.ldc = c->ldc; a.cmat_cols = 1; a.usq = nullptr; }
     return a;
 }
 
@@ -181,6 +208,16 @@ int step_values(const pot_progot_params *p, const float *alpha, int k, double me
 
 int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
             float alpha, float *Xout, hipStream_t s) {
+    if (c->cost_p != 0.f) {
+        const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
+        pot::PcostMapArgs a{};
+        a.Xq = Xq; a.nq = nq; a.Y = c->Y; a.m = c->m; a.g = g;
+        a.eps = eps; a.alpha = alpha; a.p = c->cost_p; a.d = c->d; a.Xout = Xout;
+        a.pm = at<float>(c, L.pm); a.ps = at<float>(c, L.ps); a.pacc = at<float>(c, L.mpa);
+        a.cap_q = c->n;
+        POT_TRY(pot::launch_pcost_map(a, s));
+        return POT_OK;
+    }
     MapArgs a{};
     a.Xq = Xq; a.nq = nq; a.Y = c->Y; a.Y_lp = c->y_lp; a.m = c->m; a.ysq = c->y_sqn; a.g = g;
     a.eps = eps; a.alpha = alpha; a.d = c->d; a.precision = c->precision;
@@ -215,8 +252,10 @@ float *pinned_slot() {
     return g_pinned.buf;
 }
 
-// Synchronous mean-cost refresh of the source iterate (single-problem path).
+// Synchronous mean-cost refresh of the source iterate (single-problem path);
+// for a general cost, the cost matrix is rebuilt with it.
 int refresh_mean_cost(pot_clouds *c, const Layout &L, hipStream_t s) {
+    if (c->cost_p != 0.f) return refresh_pcost(c, L, s);
     std::vector<double> host(moments_len(c->d));
     int st = enqueue_moments(c, L, host.data(), s);
     if (st != POT_OK) return st;
@@ -320,14 +359,12 @@ size_t pot_workspace_bytes(int64_t n, int64_t m, int32_t d, int32_t precision) {
     return plan(n, m, d, precision).total;
 }
 
-int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
-                       int32_t d, const float *a, const float *b, int32_t precision, void *ws,
-                       size_t ws_bytes, void *stream) {
-    if (!c || !X || !Y || !ws || !valid_sizes(n, m, d, precision)) return POT_ERR_INVALID;
-    const Layout L = plan(n, m, d, precision);
-    if (ws_bytes < L.total) return POT_ERR_NOMEM;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    // Weights, when given, must be positive and sum to 1 within 1e-5.
+}  // extern "C"
+
+namespace {
+
+// Weights, when given, must be positive and sum to 1 within 1e-5.
+int check_weights(const float *a, int64_t n, const float *b, int64_t m, hipStream_t s) {
     for (int side = 0; side < 2; ++side) {
         const float *w = side ? b : a;
         const int64_t len = side ? m : n;
@@ -342,12 +379,52 @@ int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y,
         }
         if (std::fabs(tot - 1.0) > 1e-5) return POT_ERR_INVALID;
     }
-    bind_clouds(c, X, n, Y, m, d, a, b, precision, ws, ws_bytes, L);
-    std::vector<double> host(moments_len(d));
-    const int st = enqueue_prepare(c, L, host.data(), s);
+    return POT_OK;
+}
+
+int prepare(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
+            const float *a, const float *b, int32_t precision, float cost_p, void *ws,
+            size_t ws_bytes, hipStream_t s) {
+    const Layout L = plan(n, m, d, precision, cost_p);
+    if (ws_bytes < L.total) return POT_ERR_NOMEM;
+    int st = check_weights(a, n, b, m, s);
     if (st != POT_OK) return st;
+    bind_clouds(c, X, n, Y, m, d, a, b, precision, ws, ws_bytes, L, cost_p);
+    std::vector<double> host(moments_len(d));
+    if ((st = enqueue_prepare(c, L, host.data(), s)) != POT_OK) return st;
     POT_TRY(hipStreamSynchronize(s));
-    return finish_moments(c, host.data());
+    if ((st = finish_moments(c, host.data())) != POT_OK) return st;
+    return cost_p != 0.f ? refresh_pcost(c, L, s) : POT_OK;
+}
+
+bool valid_pcost_sizes(int64_t n, int64_t m, int32_t d, float p) {
+    return p != 0.f && valid_cost_p(p) && valid_sizes(n, m, d, POT_PREC_FP32) &&
+           (double)n * (double)pot::pcost_ldc(m) <= (double)(int64_t(1) << 36);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
+                       int32_t d, const float *a, const float *b, int32_t precision, void *ws,
+                       size_t ws_bytes, void *stream) {
+    if (!c || !X || !Y || !ws || !valid_sizes(n, m, d, precision)) return POT_ERR_INVALID;
+    return prepare(c, X, n, Y, m, d, a, b, precision, 0.f, ws, ws_bytes,
+                   static_cast<hipStream_t>(stream));
+}
+
+size_t pot_workspace_bytes_pcost(int64_t n, int64_t m, int32_t d, float p) {
+    if (!valid_pcost_sizes(n, m, d, p)) return 0;
+    return plan(n, m, d, POT_PREC_FP32, p).total;
+}
+
+int pot_prepare_clouds_pcost(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
+                             int32_t d, const float *a, const float *b, float p, void *ws,
+                             size_t ws_bytes, void *stream) {
+    if (!c || !X || !Y || !ws || !valid_pcost_sizes(n, m, d, p)) return POT_ERR_INVALID;
+    return prepare(c, X, n, Y, m, d, a, b, POT_PREC_FP32, p, ws, ws_bytes,
+                   static_cast<hipStream_t>(stream));
 }
 
 int pot_sinkhorn_solve(pot_clouds *c, float eps, float tau, int32_t max_iter, const float *f_init,
@@ -359,7 +436,7 @@ int pot_sinkhorn_solve(pot_clouds *c, float eps, float tau, int32_t max_iter, co
         return POT_ERR_INVALID;
     const double t0 = now_s();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = plan(c->n, c->m, c->d, c->precision);
+    const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
     SinkResult r;
     int st = sinkhorn_core(c, L, eps, tau, max_iter, g_init, 1.f, &r, s);
     if (st != POT_OK) return st;
@@ -387,7 +464,7 @@ int pot_progot_solve(pot_clouds *c, const pot_progot_params *p, float *f, float 
     if (!valid_clouds(c) || !valid_params(p) || !f || !G) return POT_ERR_INVALID;
     const double t0 = now_s();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = plan(c->n, c->m, c->d, c->precision);
+    const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
     const int K = p->K;
     const int64_t n = c->n, m = c->m;
     float alpha[POT_MAX_K];
@@ -453,12 +530,16 @@ int pot_coupling_metrics(const pot_clouds *c, const float *f, const float *g, fl
                          double *out, void *stream) {
     if (!valid_clouds(c) || !f || !g || !out || !finite_pos(eps)) return POT_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = plan(c->n, c->m, c->d, c->precision);
+    const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
     const int nbr = pot::fp64_check_blocks(c->n), nbc = pot::fp64_check_blocks(c->m);
     constexpr int Q = pot::kCheckParts;
-    POT_TRY(pot::launch_fp64_check(c->xk, c->n, c->Y, c->m, c->d, f, g, c->a, c->b, eps,
-                                   at<double>(c, L.n64), at<double>(c, L.n64) + c->n,
-                                   at<double>(c, L.chr), at<double>(c, L.chc), s));
+    if (c->cost_p != 0.f)
+        POT_TRY(pot::launch_fp64_check_pcost(c->xk, c->n, c->Y, c->m, c->d, c->cost_p, f, g, c->a,
+                                             c->b, eps, at<double>(c, L.chr), at<double>(c, L.chc), s));
+    else
+        POT_TRY(pot::launch_fp64_check(c->xk, c->n, c->Y, c->m, c->d, f, g, c->a, c->b, eps,
+                                       at<double>(c, L.n64), at<double>(c, L.n64) + c->n,
+                                       at<double>(c, L.chr), at<double>(c, L.chc), s));
     std::vector<double> hr(Q * (size_t)nbr), hc(Q * (size_t)nbc);
     POT_TRY(hipMemcpyAsync(hr.data(), at<double>(c, L.chr), hr.size() * 8, hipMemcpyDeviceToHost, s));
     POT_TRY(hipMemcpyAsync(hc.data(), at<double>(c, L.chc), hc.size() * 8, hipMemcpyDeviceToHost, s));
@@ -537,11 +618,11 @@ int pot_diag_metrics(const pot_clouds *c, const float *f, const float *g, float 
     if (!valid_clouds(c) || !f || !g || !out || !finite_pos(eps) || c->n != c->m)
         return POT_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = plan(c->n, c->m, c->d, c->precision);
+    const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
     // the FP64 norm region holds n + m >= 2 diag_blocks(n) doubles
     double *part = at<double>(c, L.n64);
     const int nb = pot::diag_blocks(c->n);
-    POT_TRY(pot::launch_diag_sums(c->xk, c->Y, c->n, c->d, f, g, eps, part, s));
+    POT_TRY(pot::launch_diag_sums(c->xk, c->Y, c->n, c->d, f, g, eps, c->cost_p, part, s));
     std::vector<double> h(2 * (size_t)nb);
     POT_TRY(hipMemcpyAsync(h.data(), part, h.size() * 8, hipMemcpyDeviceToHost, s));
     POT_TRY(hipStreamSynchronize(s));

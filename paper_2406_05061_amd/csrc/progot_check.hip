@@ -127,12 +127,111 @@ __global__ __launch_bounds__(256) void fp64_rowsums(
     }
 }
 
+// |e|^p in FP64 (p = 1.5 as |e| sqrt|e|).
+__device__ __forceinline__ double pow_abs64(double e, double p) {
+    const double a = fabs(e);
+    return p == 1.5 ? a * sqrt(a) : (a == 0.0 ? 0.0 : pow(a, p));
+}
+
+// The same row pass for the cost h(z) = (1/p) sum_k |z_k|^p, whose C_ij has
+// no inner-product form: each lane group adds its quarter of the features'
+// |x_ik - y_jk|^p for 4 columns of a 16-column LDS tile (FP64 differences of
+// the FP32 inputs, FP64 powers), the 4 groups' partials are summed across
+// lanes, and row i's sums are accumulated as above.
+template <int D>
+__global__ __launch_bounds__(256) void pcost_rowsums(
+    const float *__restrict__ U, int64_t nu, const float *__restrict__ V, int64_t nv, int d,
+    double p, const float *__restrict__ pu, const float *__restrict__ pv,
+    const float *__restrict__ w_in, double eps, double *__restrict__ part) {
+    constexpr int KD = D / 4;
+    constexpr int BN = 16;
+    constexpr int STRIDE = D + 2;
+    __shared__ double vt[BN * STRIDE];
+    __shared__ double vb[BN];
+    __shared__ double red[256];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lq = lane >> 4;
+    const int64_t row = (int64_t)blockIdx.x * 64 + wave * 16 + li;
+    const bool live = row < nu;
+    double ub[KD];
+#pragma unroll
+    for (int k = 0; k < KD; ++k) {
+        const int f = lq * KD + k;
+        ub[k] = (live && f < d) ? (double)U[row * d + f] : 0.0;
+    }
+    const double fu = live ? (double)pu[row] : 0.0;
+    const double inv_eps = 1.0 / eps, inv_p = 1.0 / p;
+    double rsum = 0.0, pc = 0.0, plp = 0.0;
+    for (int64_t j0 = 0; j0 < nv; j0 += BN) {
+        for (int e = tid; e < BN * D; e += 256) {
+            const int r = e / D, c = e % D;
+            const int64_t j = j0 + r;
+            vt[r * STRIDE + c] = (j < nv && c < d) ? (double)V[j * d + c] : 0.0;
+        }
+        if (tid < BN) vb[tid] = j0 + tid < nv ? (double)pv[j0 + tid] : -INFINITY;
+        __syncthreads();
+#pragma unroll 1
+        for (int jl = 0; jl < BN; ++jl) {
+            double c = 0.0;
+#pragma unroll
+            for (int k = 0; k < KD; ++k) c += pow_abs64(ub[k] - vt[jl * STRIDE + lq * KD + k], p);
+            c += __shfl_xor(c, 16);
+            c += __shfl_xor(c, 32);
+            c *= inv_p;
+            if (vb[jl] > -INFINITY) {
+                const double t = (fu + vb[jl] - c) * inv_eps;   // log P_ij
+                const double pr = exp(t);
+                rsum += pr;
+                pc = fma(pr, c, pc);
+                plp = fma(pr, t, plp);
+            }
+        }
+        __syncthreads();
+    }
+    // every lane of a row holds the row's sums; the lq == 0 lane reports them
+    const bool own = live && lq == 0;
+    const double w = own ? (w_in ? (double)w_in[row] : 1.0 / (double)nu) : 0.0;
+    const double vals[kCheckParts] = {own ? fabs(rsum - w) : 0.0, own ? rsum : 0.0,
+                                      own ? (double)pu[row] * w : 0.0, own ? pc : 0.0,
+                                      own ? plp : 0.0};
+    for (int q = 0; q < kCheckParts; ++q) {
+        __syncthreads();
+        red[tid] = vals[q];
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) part[(int64_t)blockIdx.x * kCheckParts + q] = red[0];
+    }
+}
+
+template <int D>
+void prowsums_t(const float *U, int64_t nu, const float *V, int64_t nv, int d, double p,
+                const float *pu, const float *pv, const float *w, double eps, double *part,
+                hipStream_t s) {
+    hipLaunchKernelGGL((pcost_rowsums<D>), dim3((unsigned)fp64_check_blocks(nu)), dim3(256), 0, s, U,
+                       nu, V, nv, d, p, pu, pv, w, eps, part);
+}
+
+void prowsums(const float *U, int64_t nu, const float *V, int64_t nv, int d, double p,
+              const float *pu, const float *pv, const float *w, double eps, double *part,
+              hipStream_t s) {
+    if (d <= 16) prowsums_t<16>(U, nu, V, nv, d, p, pu, pv, w, eps, part, s);
+    else if (d <= 32) prowsums_t<32>(U, nu, V, nv, d, p, pu, pv, w, eps, part, s);
+    else if (d <= 64) prowsums_t<64>(U, nu, V, nv, d, p, pu, pv, w, eps, part, s);
+    else if (d <= 128) prowsums_t<128>(U, nu, V, nv, d, p, pu, pv, w, eps, part, s);
+    else prowsums_t<256>(U, nu, V, nv, d, p, pu, pv, w, eps, part, s);
+}
+
 // Diagonal of the coupling (n == m): per block, sum_i P_ii and
 // sum_i log P_ii with P_ii = exp((f_i + g_i - |x_i - y_i|^2)/eps), the cost by
 // FP64 direct differences.
 __global__ __launch_bounds__(256) void diag_sums(const float *__restrict__ X, const float *__restrict__ Y,
                                                  int64_t n, int d, const float *__restrict__ f,
-                                                 const float *__restrict__ g, double eps,
+                                                 const float *__restrict__ g, double eps, double cp,
                                                  double *__restrict__ part) {
     __shared__ double red[256];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -141,8 +240,9 @@ __global__ __launch_bounds__(256) void diag_sums(const float *__restrict__ X, co
         double c = 0.0;
         for (int k = 0; k < d; ++k) {
             const double e = (double)X[i * d + k] - (double)Y[i * d + k];
-            c = fma(e, e, c);
+            c = cp > 0.0 ? c + pow_abs64(e, cp) : fma(e, e, c);
         }
+        if (cp > 0.0) c /= cp;
         lp = ((double)f[i] + (double)g[i] - c) / eps;
         p = exp(lp);
     }
@@ -183,9 +283,19 @@ int fp64_check_blocks(int64_t n) { return (int)((n + 63) / 64); }
 int diag_blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 hipError_t launch_diag_sums(const float *X, const float *Y, int64_t n, int d, const float *f,
-                            const float *g, float eps, double *part, hipStream_t s) {
+                            const float *g, float eps, float cost_p, double *part, hipStream_t s) {
     hipLaunchKernelGGL(diag_sums, dim3((unsigned)diag_blocks(n)), dim3(256), 0, s, X, Y, n, d, f, g,
-                       (double)eps, part);
+                       (double)eps, (double)cost_p, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_fp64_check_pcost(const float *X, int64_t n, const float *Y, int64_t m, int d,
+                                   float p, const float *f, const float *g, const float *a,
+                                   const float *b, float eps, double *part_rows,
+                                   double *part_cols, hipStream_t s) {
+    // h is even, so the columns' pass is the rows' pass with the roles swapped
+    prowsums(X, n, Y, m, d, (double)p, f, g, a, (double)eps, part_rows, s);
+    prowsums(Y, m, X, n, d, (double)p, g, f, b, (double)eps, part_cols, s);
     return hipGetLastError();
 }
 

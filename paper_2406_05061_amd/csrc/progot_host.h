@@ -16,10 +16,13 @@ namespace host {
 struct Layout {
     size_t xk, xsq, ysq, la, lb, xlp, ylp, ytl, f0, f1, g0, g1, pm, ps, errp, errd, xst, yst, chr, chc,
         n64;
+    size_t cm, cmp, mpa;   // general costs: cost matrix, its block sums, map partials
     size_t total;
 };
 
-Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision);
+// cost_p = 0: squared-Euclidean cost; cost_p > 1: (1/p)|.|_p^p (FP32).
+Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p = 0.f);
+bool valid_cost_p(float p);
 
 template <typename T> T *at(const pot_clouds *c, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(c->ws) + off);
@@ -33,7 +36,10 @@ double now_s();
 // Fill the views of c over the workspace (no device work).
 void bind_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
                  const float *a, const float *b, int32_t precision, void *ws, size_t ws_bytes,
-                 const Layout &L);
+                 const Layout &L, float cost_p = 0.f);
+// General costs: rebuild the cost matrix of the current source iterate and
+// set c->mean_cost from its sum (blocks until the sum is on the host).
+int refresh_pcost(pot_clouds *c, const Layout &L, hipStream_t s);
 
 // Number of doubles of a moments read-back: (sum_i x_i, sum |x|^2) for the
 // source iterate and for the targets.

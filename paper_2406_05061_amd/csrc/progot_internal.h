@@ -57,6 +57,14 @@ struct LseJob {
     int iter;
     int max_iter;
     float tau;
+    // general costs h = (1/p)|.|_p^p: the cost matrix of the pair (n x ldc,
+    // row-major, rows = source points).  When set, usq is NULL and the
+    // update reads C instead of computing the cost: the f-update reduces
+    // rows of C (cmat_cols = 0), the g-update columns (cmat_cols = 1); cps
+    // then counts columns (rows) of C per split.
+    const float *cmat;
+    int64_t ldc;
+    int cmat_cols;
 };
 typedef LseJob LseArgs;
 
@@ -112,6 +120,43 @@ struct MapArgs {
 };
 hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s);
 
+// General costs h(z) = (1/p) sum_k |z_k|^p (FP32 on the VALU).
+int pcost_pad_dim(int d);                 // padded dimension of the map kernel
+int64_t pcost_ldc(int64_t m);             // row stride of the cost matrix (m rounded up to 4)
+int64_t pcost_matrix_blocks(int64_t n, int64_t m);
+int pcost_map_max_split();
+// C_ij = h(x_i - y_j) for all pairs, and sum_ij C_ij (FP64) into *sum_out;
+// part holds pcost_matrix_blocks(n, m) doubles.
+hipError_t launch_pcost_matrix(const float *X, int64_t n, const float *Y, int64_t m, int d, float p,
+                               float *Cm, int64_t ldc, double *part, double *sum_out,
+                               hipStream_t s);
+void plan_pcost_job(LseJob &j);
+hipError_t launch_pcost_partial(const LseJob &j, hipStream_t s);   // planned job
+// Xout_i = Xq_i - alpha grad h*(sum_j p_j grad h(Xq_i - y_j)),
+// p_j = softmax_j((g_j - h(Xq_i - y_j))/eps).  With few queries the targets
+// are split and the partials go to pm/ps (pcost_map_max_split() x cap_q
+// floats each) and pacc (that many x pcost_pad_dim(d) floats); more than
+// cap_q queries are processed in chunks.  Xout may alias Xq.
+struct PcostMapArgs {
+    const float *Xq;
+    int64_t nq;
+    const float *Y;
+    int64_t m;
+    const float *g;
+    float eps, alpha, p;
+    int d;
+    float *Xout;
+    float *pm, *ps, *pacc;
+    int64_t cap_q;
+};
+hipError_t launch_pcost_map(const PcostMapArgs &a, hipStream_t s);
+// FP64 check for the cost h: the same partials as launch_fp64_check, with
+// C_ij = h(x_i - y_j) by FP64 direct differences.
+hipError_t launch_fp64_check_pcost(const float *X, int64_t n, const float *Y, int64_t m, int d,
+                                   float p, const float *f, const float *g, const float *a,
+                                   const float *b, float eps, double *part_rows,
+                                   double *part_cols, hipStream_t s);
+
 // BF16 forms (precision 1: one BF16 product; 2: hi/lo split, three products).
 int bf16_dim(int d);                 // padded dimension of the BF16 copies
 int64_t bf16_mpad(int64_t m);        // padded row count of the BF16 copies (multiple of 64)
@@ -138,9 +183,10 @@ hipError_t launch_fp64_check(const float *X, int64_t n, const float *Y, int64_t 
 int fp64_check_blocks(int64_t n);
 constexpr int kCheckParts = 5;
 // Diagonal of the coupling (n == m): per-block partials (sum P_ii,
-// sum log P_ii), diag_blocks(n) blocks of 2 doubles.
+// sum log P_ii), diag_blocks(n) blocks of 2 doubles; cost_p = 0 is the
+// squared-Euclidean cost, cost_p > 1 the cost (1/p)|.|_p^p.
 hipError_t launch_diag_sums(const float *X, const float *Y, int64_t n, int d, const float *f,
-                            const float *g, float eps, double *part, hipStream_t s);
+                            const float *g, float eps, float cost_p, double *part, hipStream_t s);
 int diag_blocks(int64_t n);
 
 // Launch timing (see pot_timing_enable): kind 0 = cost + log-sum-exp

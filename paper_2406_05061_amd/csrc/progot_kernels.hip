@@ -290,7 +290,7 @@ __device__ __forceinline__ void lse_merge_body(const LseJob &J, int64_t blk, flo
         }
         const float L = M + log2f(sum);
         const float lw = J.logw[i];
-        const float pot = fmaf(eps, lw, J.usq[i]) - eps * kLn2 * L;
+        const float pot = fmaf(eps, lw, J.usq ? J.usq[i] : 0.f) - eps * kLn2 * L;
         if (J.pot_old) e = expf(lw) * fabsf(expm1f((J.pot_old[i] - pot) / eps));
         J.pot_out[i] = pot;
     }
@@ -660,10 +660,13 @@ void plan_lse_job(LseJob &j) {
 
 hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
     LseJob j = a;
-    plan_lse_job(j);
+    if (j.cmat) plan_pcost_job(j);
+    else plan_lse_job(j);
     hipError_t e;
     const int64_t slot = timing_begin(0, s);
-    if (j.precision != 0) {
+    if (j.cmat) {
+        e = launch_pcost_partial(j, s);
+    } else if (j.precision != 0) {
         e = launch_lse_partial_bf16(j, s);
     } else switch (padded_dim(j.d)) {
         case 16: e = lse_launch_t<16, lse_qb(16)>(j, s); break;
@@ -686,6 +689,7 @@ hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, fl
     int nerr = 0;
     const int D = padded_dim(jobs[0].d);
     for (int k = 0; k < njobs; ++k) {
+        if (jobs[k].cmat) return hipErrorInvalidValue;
         plan_lse_job(jobs[k]);
         if (jobs[k].precision != 0 || padded_dim(jobs[k].d) != D) return hipErrorInvalidValue;
         jobs[k].blk_begin = blk;

@@ -116,7 +116,7 @@ int pot_eps_schedule(const pot_clouds *c, const float *Y_test, int64_t m_test, i
                      int32_t *p_star, void *ws, size_t ws_bytes, void *stream) {
     if (!valid_clouds(c) || !Y_test || m_test < 1 || K < 1 || K > POT_MAX_K || alpha_sched < 0 ||
         alpha_sched > 2 || !s_grid || n_grid < 1 || n_grid > POT_MAX_GRID || !finite_pos(beta0) ||
-        !finite_pos(tau) || max_iter < 1 || !eps_out || !ws)
+        !finite_pos(tau) || max_iter < 1 || !eps_out || !ws || c->cost_p != 0.f)
         return POT_ERR_INVALID;
     for (int p = 0; p < n_grid; ++p)
         if (!(std::isfinite(s_grid[p]) && s_grid[p] > 0.0)) return POT_ERR_INVALID;

@@ -48,6 +48,7 @@ class pot_clouds(C.Structure):
         ("log_a", C.c_void_p), ("log_b", C.c_void_p),
         ("x_lp", C.c_void_p), ("y_lp", C.c_void_p), ("yt_lp", C.c_void_p),
         ("mean_cost", C.c_double), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
+        ("cost_p", C.c_float), ("cmat", C.c_void_p), ("ldc", C.c_int64),
     ]
 
 
@@ -79,6 +80,9 @@ _SIGS = {
     "pot_workspace_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32]),
     "pot_prepare_clouds": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _vp, _i64, _i32, _vp, _vp,
                                      _i32, _vp, C.c_size_t, _vp]),
+    "pot_workspace_bytes_pcost": (C.c_size_t, [_i64, _i64, _i32, _f32]),
+    "pot_prepare_clouds_pcost": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _vp, _i64, _i32, _vp,
+                                           _vp, _f32, _vp, C.c_size_t, _vp]),
     "pot_sinkhorn_solve": (C.c_int, [C.POINTER(pot_clouds), _f32, _f32, _i32, _vp, _vp, _vp, _vp,
                                      C.POINTER(pot_sinkhorn_info), _vp]),
     "pot_entropic_map": (C.c_int, [C.POINTER(pot_clouds), _vp, _f32, _vp, _i64, _f32, _vp, _vp]),
@@ -145,7 +149,11 @@ def version() -> str:
     return lib().pot_version().decode()
 
 
-def workspace_bytes(n: int, m: int, d: int, precision: str = "fp32") -> int:
+def workspace_bytes(n: int, m: int, d: int, precision: str = "fp32", cost_p: float = 0.0) -> int:
+    if cost_p:
+        if precision != "fp32":
+            return 0
+        return int(lib().pot_workspace_bytes_pcost(n, m, d, float(cost_p)))
     return int(lib().pot_workspace_bytes(n, m, d, PREC[precision]))
 
 
@@ -181,9 +189,11 @@ def _ptr(t):
 
 class Clouds:
     """A prepared pair of clouds: inputs, workspace and the pot_clouds POD.
-    Keeps references to every tensor the library points into."""
+    Keeps references to every tensor the library points into.  cost_p = 0
+    selects the squared-Euclidean cost; cost_p > 1 the cost
+    h(z) = (1/p) sum_k |z_k|^p (FP32 only)."""
 
-    def __init__(self, X, Y, a=None, b=None, precision: str = "fp32"):
+    def __init__(self, X, Y, a=None, b=None, precision: str = "fp32", cost_p: float = 0.0):
         torch = _torch()
         _dev_f32(X, "X")
         _dev_f32(Y, "Y")
@@ -195,20 +205,38 @@ class Clouds:
             _dev_f32(a, "a", (n,))
         if b is not None:
             _dev_f32(b, "b", (m,))
-        nbytes = workspace_bytes(n, m, d, precision)
+        nbytes = workspace_bytes(n, m, d, precision, cost_p)
         if nbytes == 0:
             raise PotError(POT_ERR_INVALID, "workspace_bytes")
         self.X, self.Y, self.a, self.b = X, Y, a, b
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
         self.c = pot_clouds()
         self.n, self.m, self.d, self.precision = n, m, d, precision
-        _check(lib().pot_prepare_clouds(C.byref(self.c), _ptr(X), n, _ptr(Y), m, d, _ptr(a),
-                                        _ptr(b), PREC[precision], _ptr(self.ws), nbytes,
-                                        C.c_void_p(_stream())), "prepare_clouds", False)
+        self.cost_p = float(cost_p)
+        if cost_p:
+            _check(lib().pot_prepare_clouds_pcost(C.byref(self.c), _ptr(X), n, _ptr(Y), m, d,
+                                                  _ptr(a), _ptr(b), float(cost_p), _ptr(self.ws),
+                                                  nbytes, C.c_void_p(_stream())),
+                   "prepare_clouds_pcost", False)
+        else:
+            _check(lib().pot_prepare_clouds(C.byref(self.c), _ptr(X), n, _ptr(Y), m, d, _ptr(a),
+                                            _ptr(b), PREC[precision], _ptr(self.ws), nbytes,
+                                            C.c_void_p(_stream())), "prepare_clouds", False)
 
     @property
     def mean_cost(self) -> float:
         return float(self.c.mean_cost)
+
+    def cost_matrix(self):
+        """General costs: a copy of the resident cost matrix C_ij = h(x_i - y_j)
+        of the current source iterate (n x m)."""
+        if not self.cost_p:
+            raise ValueError("the squared-Euclidean cost is never materialised")
+        torch = _torch()
+        off = self.c.cmat - self.ws.data_ptr()
+        ldc = int(self.c.ldc)
+        flat = self.ws[off:off + self.n * ldc * 4].view(torch.float32)
+        return flat.view(self.n, ldc)[:, :self.m].clone()
 
     def xk(self):
         """A copy of the current source iterate X^(k) (n x d), taken on the
@@ -219,8 +247,8 @@ class Clouds:
         return self.ws[off:off + nbytes].view(torch.float32).view(self.n, self.d).clone()
 
 
-def prepare_clouds(X, Y, a=None, b=None, precision: str = "fp32") -> Clouds:
-    return Clouds(X, Y, a, b, precision)
+def prepare_clouds(X, Y, a=None, b=None, precision: str = "fp32", cost_p: float = 0.0) -> Clouds:
+    return Clouds(X, Y, a, b, precision, cost_p)
 
 
 @dataclass

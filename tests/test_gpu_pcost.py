@@ -1,0 +1,229 @@
+"""GPU parity of the general-cost path, h(z) = (1/p) sum_k |z_k|^p, against
+the FP64 oracle (oracle.pcost) on the same seeded FP32 inputs, through the
+C ABI.  Bars as for the squared-Euclidean path: potentials 1e-4 relative,
+maps 1e-3 relative, marginal L1 1e-3 after convergence.  p = 1.5 runs the
+square-root kernels, p = 2.5 the log/exp kernels; p = 2 is checked against
+the squared-Euclidean GPU path (half the cost, so the same problem at twice
+eps)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pcost, metrics
+import workloads
+from tests.parity import pot_err, map_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2406_05061_amd as P
+    P.lib()
+    return P
+
+
+def _clouds(P, X, Y, p, a=None, b=None):
+    return P.prepare_clouds(P.to_device(X), P.to_device(Y),
+                            None if a is None else P.to_device(a),
+                            None if b is None else P.to_device(b), cost_p=p)
+
+
+COST_SHAPES = [(130, 70, 3), (257, 300, 47), (64, 65, 100), (33, 200, 256), (1, 1, 1), (5, 1, 7)]
+
+
+@pytest.mark.parametrize("n,m,d", COST_SHAPES)
+@pytest.mark.parametrize("p", [1.5, 2.5])
+def test_cost_matrix(P, n, m, d, p):
+    X, Y = workloads.gmm(seed=300 + d, n=n, m=m, d=d, n_comp=3)
+    print(f"case cost n={n} m={m} d={d} p={p}", flush=True)
+    cl = _clouds(P, X, Y, p)
+    Cg = cl.cost_matrix().cpu().numpy().astype(np.float64)
+    Cr = pcost.cost_matrix_p(X, Y, p)
+    # FP32 sums of d non-negative terms: relative error within a few ulps x d
+    assert np.abs(Cg - Cr).max() <= 2e-6 * max(1.0, d / 16) * np.abs(Cr).max() + 1e-30
+    assert abs(cl.mean_cost / Cr.mean() - 1) < 1e-6
+
+
+SINK_SHAPES = [(256, 256, 4), (1000, 777, 16), (700, 1300, 47), (300, 513, 100), (64, 2000, 256),
+               (1, 5, 3), (7, 1, 3)]
+
+
+@pytest.mark.parametrize("n,m,d", SINK_SHAPES)
+@pytest.mark.parametrize("p,weighted", [(1.5, False), (1.5, True), (2.5, False)])
+def test_sinkhorn_fixed_iterations(P, n, m, d, p, weighted):
+    X, Y = workloads.gmm(seed=310 + n + d, n=n, m=m, d=d, n_comp=3)
+    wa = workloads.weights(n, seed=1) if weighted else None
+    wb = workloads.weights(m, seed=2) if weighted else None
+    a = np.full(n, 1.0 / n) if wa is None else wa.astype(np.float64)
+    b = np.full(m, 1.0 / m) if wb is None else wb.astype(np.float64)
+    C = pcost.cost_matrix_p(X, Y, p)
+    eps = float(np.float32(0.05 * C.mean()))
+    print(f"case sinkhorn n={n} m={m} d={d} p={p} weighted={weighted}", flush=True)
+    cl = _clouds(P, X, Y, p, wa, wb)
+    for it in (1, 13):
+        f, g, info = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=it)
+        ref = oracle.sinkhorn(a, X, b, Y, eps, 0.0, n_iter=it, C=C)
+        assert info.iters == it and info.status == 0
+        ef = pot_err(f.cpu().numpy(), ref.f, eps)
+        eg = pot_err(g.cpu().numpy(), ref.g, eps)
+        assert ef < 1e-4 and eg < 1e-4, (it, ef, eg)
+        assert abs(info.err - ref.err) <= 1e-5 + 2e-3 * ref.err, (info.err, ref.err)
+
+
+MAP_CASES = [(700, 900, 4, 1.0), (513, 1000, 47, 0.3), (300, 800, 64, 1.0), (100, 3000, 128, 0.7),
+             (64, 257, 256, 1.0), (1, 33, 5, 1.0), (3000, 400, 16, 0.5)]
+
+
+@pytest.mark.parametrize("nq,m,d,alpha", MAP_CASES)
+@pytest.mark.parametrize("p", [1.5, 2.5])
+def test_entropic_map(P, nq, m, d, alpha, p):
+    X, Y = workloads.gmm(seed=320 + d, n=nq, m=m, d=d, n_comp=4)
+    Q = workloads.gmm(seed=321 + d, n=nq, m=4, d=d, n_comp=4)[0]
+    a, b = np.full(nq, 1.0 / nq), np.full(m, 1.0 / m)
+    C = pcost.cost_matrix_p(X, Y, p)
+    eps = float(np.float32(0.05 * C.mean()))
+    g32 = oracle.sinkhorn(a, X, b, Y, eps, 1e-6, C=C).g.astype(np.float32)
+    print(f"case map nq={nq} m={m} d={d} alpha={alpha} p={p}", flush=True)
+    cl = _clouds(P, X, Y, p)
+    out = P.entropic_map(cl, P.to_device(g32), eps, P.to_device(Q), alpha=alpha)
+    ref = pcost.entropic_map_p(Q, Y, g32, eps, p, alpha=alpha)
+    e = map_err(out.cpu().numpy(), ref, Y)
+    print(f"  map err {e:.2e}", flush=True)
+    assert e < 1e-3
+    Qd = P.to_device(Q)
+    P.entropic_map(cl, P.to_device(g32), eps, Qd, alpha=alpha, out=Qd)   # in place
+    assert np.array_equal(Qd.cpu().numpy(), out.cpu().numpy())
+
+
+def test_map_query_chunks(P):
+    """More queries than source points with split targets: the queries run in
+    chunks of n through the split partials."""
+    X, Y = workloads.gmm(seed=330, n=100, m=2000, d=12, n_comp=3)
+    Q = workloads.gmm(seed=331, n=700, m=4, d=12, n_comp=3)[0]
+    g = np.random.default_rng(3).standard_normal(2000).astype(np.float32)
+    eps = float(np.float32(0.05 * pcost.cost_matrix_p(X, Y, 1.5).mean()))
+    cl = _clouds(P, X, Y, 1.5)
+    out = P.entropic_map(cl, P.to_device(g), eps, P.to_device(Q), alpha=1.0)
+    ref = pcost.entropic_map_p(Q, Y, g, eps, 1.5)
+    assert map_err(out.cpu().numpy(), ref, Y) < 1e-3
+
+
+def test_p2_matches_squared_euclidean_gpu(P):
+    """Two independent GPU paths: the VALU cost kernels at p = 2 (log/exp
+    form) and the MFMA squared-Euclidean kernels at twice eps."""
+    X, Y = workloads.gmm(seed=340, n=900, m=700, d=24, n_comp=4)
+    cl2 = _clouds(P, X, Y, 2.0)
+    cls = P.prepare_clouds(P.to_device(X), P.to_device(Y))
+    assert abs(cl2.mean_cost / (cls.mean_cost / 2) - 1) < 1e-5
+    eps = float(np.float32(cl2.mean_cost / 20))
+    f2, g2, _ = P.sinkhorn_solve(cl2, eps, tau=0.0, max_iter=20)
+    fs, gs, _ = P.sinkhorn_solve(cls, 2 * eps, tau=0.0, max_iter=20)
+    assert pot_err(2 * f2.cpu().numpy(), fs.cpu().numpy(), 2 * eps) < 1e-4
+    assert pot_err(2 * g2.cpu().numpy(), gs.cpu().numpy(), 2 * eps) < 1e-4
+    Q = P.to_device(workloads.gmm(seed=341, n=500, m=4, d=24)[0])
+    t2 = P.entropic_map(cl2, g2, eps, Q, alpha=0.6)
+    ts = P.entropic_map(cls, gs, 2 * eps, Q, alpha=0.6)
+    assert map_err(t2.cpu().numpy(), ts.cpu().numpy(), Y) < 1e-4
+
+
+def _progot_case(P, theta):
+    X, Y = workloads.gmm(seed=350, n=1100, m=700, d=47, n_comp=6)
+    cl = _clouds(P, X, Y, 1.5)
+    f, G, TX, info = P.progot_solve(cl, 4, theta=theta, tau_first=1e-3, tau_last=1e-3)
+    return X, Y, cl, f, G, TX, info
+
+
+def test_progot(P):
+    """ProgOT (Alg. 2) and T_Prog (Alg. 3) for h with p = 1.5 on a small
+    stand-in of the paper's coupling workload (d = 47, n > m), K = 4,
+    constant speed, eps_k = mean cost / 20, tau 1e-3: the whole trajectory
+    against the oracle's."""
+    X, Y, cl, f, G, TX, info = _progot_case(P, 1.0)
+    n, m = X.shape[0], Y.shape[0]
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    ref = pcost.progot_p(a, X, b, Y, 4, 1.5, theta=1.0, tau=1e-3)
+    print(f"case progot: gpu iters {info.iters} oracle {ref.iters}", flush=True)
+    assert info.converged
+    np.testing.assert_allclose(info.eps, ref.eps, rtol=1e-4)
+    assert all(abs(u - v) <= 2 for u, v in zip(info.iters, ref.iters))
+    assert map_err(TX.cpu().numpy(), ref.TX, Y) < 1e-3
+    chk = P.marginal_check(cl, f, G[-1], info.eps[-1])
+    assert chk[0] <= 1e-3 * 1.01 and chk[1] <= 1e-4
+    Gh = G.cpu().numpy().astype(np.float64)
+    Q = workloads.gmm(seed=351, n=400, m=4, d=47, n_comp=6)[0]
+    out = P.progot_map(cl, G, info.eps, info.alpha, P.to_device(Q))
+    refq = pcost.progot_map_p(Q, Y, Gh, info.eps, info.alpha, 1.5)
+    assert map_err(out.cpu().numpy(), refq, Y) < 1e-3
+    tx2 = P.progot_map(cl, G, info.eps, info.alpha, P.to_device(X))
+    assert map_err(tx2.cpu().numpy(), TX.cpu().numpy(), Y) < 1e-5
+
+
+def test_progot_small_eps_last_step(P):
+    """theta = 1/16, the regularisation of the paper's coupling figure.  At
+    this eps the composition of K maps is chaotic at some training points
+    (in the oracle itself, a 1e-6 relative change of the potentials moves
+    Alg. 3's endpoint there by O(1)), so the comparison is per step: the last
+    solve of the GPU run is repeated by the oracle from the GPU's own
+    X^(K-1) (its warm start is zero: alpha_{K-1} = 1), and the GPU's last map
+    is checked against the oracle's map of that X^(K-1)."""
+    X, Y, cl, f, G, TX, info = _progot_case(P, 1.0 / 16)
+    n, m = X.shape[0], Y.shape[0]
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    print(f"case progot theta=1/16: gpu iters {info.iters}", flush=True)
+    assert info.converged
+    xl = cl.xk().cpu().numpy()
+    C = pcost.cost_matrix_p(xl, Y, 1.5)
+    assert abs(info.eps[-1] / (C.mean() / 16 / 20) - 1) < 1e-5
+    eps = float(np.float32(info.eps[-1]))
+    ref = oracle.sinkhorn(a, xl, b, Y, eps, 0.0, n_iter=info.iters[-1], C=C)
+    assert pot_err(f.cpu().numpy(), ref.f, eps) < 1e-4
+    assert pot_err(G[-1].cpu().numpy(), ref.g, eps) < 1e-4
+    chk = P.marginal_check(cl, f, G[-1], eps)
+    assert chk[0] <= 1e-3 * 1.01 and chk[1] <= 1e-4
+    g32 = G[-1].cpu().numpy()
+    assert map_err(TX.cpu().numpy(), pcost.entropic_map_p(xl, Y, g32, eps, 1.5), Y) < 1e-3
+    tx2 = P.progot_map(cl, G, info.eps, info.alpha, P.to_device(X))
+    assert np.array_equal(tx2.cpu().numpy(), TX.cpu().numpy())
+
+
+@pytest.mark.parametrize("p", [1.5, 2.5])
+def test_coupling_metrics(P, p):
+    X, Y = workloads.gmm(seed=360, n=600, m=450, d=20)
+    wa, wb = workloads.weights(600, seed=3), workloads.weights(450, seed=4)
+    cl = _clouds(P, X, Y, p, wa, wb)
+    eps = float(np.float32(cl.mean_cost / 20))
+    f, g, _ = P.sinkhorn_solve(cl, eps, tau=1e-4)
+    met = P.coupling_metrics(cl, f, g, eps)
+    C = pcost.cost_matrix_p(X, Y, p)
+    f64, g64 = f.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+    aa, bb = wa.astype(np.float64), wb.astype(np.float64)
+    Pm = oracle.coupling(f64, g64, C, eps)
+    row, col = oracle.marginal_errors(f64, g64, C, eps, aa, bb)
+    ref = {"transport_cost": metrics.transport_cost(Pm, C), "p_log_p": metrics.p_log_p(Pm),
+           "mass": float(Pm.sum()), "ot": oracle.dual_objective(f64, g64, C, eps, aa, bb)}
+    for k, v in ref.items():
+        assert abs(met[k] - v) <= 1e-9 * max(abs(v), 1.0), (k, met[k], v)
+    assert abs(met["row_err"] - row) <= 1e-9 + 1e-6 * row
+    assert abs(met["col_err"] - col) <= 1e-9 + 1e-6 * col
+
+
+def test_diag_metrics(P):
+    X, Y = workloads.spd_pair(seed=9, n=400, d=6)
+    cl = _clouds(P, X, Y, 1.5)
+    eps = float(np.float32(0.1 * cl.mean_cost / 20))
+    f, g, _ = P.sinkhorn_solve(cl, eps, tau=1e-4)
+    tr, kl = P.diag_metrics(cl, f, g, eps)
+    C = pcost.cost_matrix_p(X, Y, 1.5)
+    rt, rk = metrics.diag_metrics(oracle.coupling(f.cpu().numpy(), g.cpu().numpy(), C, eps))
+    assert abs(tr - rt) <= 1e-9 * rt and abs(kl - rk) <= 1e-9 * max(1.0, abs(rk))
+
+
+def test_scheduler_rejects_general_cost(P):
+    X, Y = workloads.c1(seed=1, n=256, m=256, d=4)
+    cl = _clouds(P, X, Y, 1.5)
+    with pytest.raises(P.PotError):
+        P.eps_schedule(cl, P.to_device(Y[:64]), 4)

@@ -41,7 +41,9 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p) {
     L.g1 = take((size_t)m * 4);
     L.pm = take((size_t)pot::kMaxSplit * nm * 4);
     L.ps = take((size_t)pot::kMaxSplit * nm * 4);
-    L.errp = take(((nm + 255) / 256) * 4);
+    // error partials: one per 256 rows from the merge kernel, or one per 4
+    // rows from the fused row update of the general-cost path
+    L.errp = take((cost_p != 0.f ? (nm + 3) / 4 : (nm + 255) / 256) * 4);
     L.errd = take(64);
     L.xst = take((size_t)pot::cloud_stat_blocks(n) * (d + 1) * 8);
     L.yst = take((size_t)pot::cloud_stat_blocks(m) * (d + 1) * 8);

@@ -131,7 +131,11 @@ hipError_t launch_pcost_matrix(const float *X, int64_t n, const float *Y, int64_
                                float *Cm, int64_t ldc, double *part, double *sum_out,
                                hipStream_t s);
 void plan_pcost_job(LseJob &j);
+// The row update with one split writes the potential and the error partials
+// itself (no merge launch; mblocks error partials).
+bool pcost_fused(const LseJob &j);
 hipError_t launch_pcost_partial(const LseJob &j, hipStream_t s);   // planned job
+hipError_t launch_pcost_merge(const LseJob &j, hipStream_t s);     // planned, not fused
 // Xout_i = Xq_i - alpha grad h*(sum_j p_j grad h(Xq_i - y_j)),
 // p_j = softmax_j((g_j - h(Xq_i - y_j))/eps).  With few queries the targets
 // are split and the partials go to pm/ps (pcost_map_max_split() x cap_q

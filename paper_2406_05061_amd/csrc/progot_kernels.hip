@@ -677,6 +677,11 @@ hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
     }
     timing_end(slot, s);
     if (e != hipSuccess) return e;
+    if (j.cmat) {
+        if (!pcost_fused(j) && (e = launch_pcost_merge(j, s)) != hipSuccess) return e;
+        if (n_err_part) *n_err_part = j.pot_old ? (int)j.mblocks : 0;
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(lse_merge, dim3((unsigned)j.mblocks), dim3(256), 0, s, j);
     if (n_err_part) *n_err_part = j.pot_old ? (int)j.mblocks : 0;
     return hipGetLastError();

@@ -21,11 +21,13 @@
 //     beyond a handful.
 //   * f-update: pcost_lse_rows, one wave per row of C and column split,
 //     float4 loads (8 in flight per lane), per-lane running (max, sum) in
-//     log2 units with one rescale per 32 values, then a wave reduction.
+//     log2 units with one rescale per 32 values, then a wave reduction;
+//     with one split (n large enough to fill the chip) the wave writes the
+//     potential and its marginal-error term itself.
 //   * g-update: pcost_lse_cols, 256 columns per workgroup (4 per lane, so a
-//     wave reads 1 KB of each row), the 4 waves walk interleaved 8-row
-//     chunks of the split's rows and combine through LDS.
-//   * both write the same per-split (max, sum) partials as the
+//     wave reads 1 KB of each row), 8 waves walk interleaved 8-row chunks
+//     of the split's rows and combine through LDS.
+//   * split updates write the same per-split (max, sum) partials as the
 //     squared-Euclidean potential kernels, and the same merge kernel turns
 //     them into the potential and the row-marginal error.
 //   * map (eq. Tent / Alg. 2 and 3 step x - alpha grad h*(sum_j p_j grad
@@ -162,22 +164,28 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 // f-update partials: row i of C against the split's columns,
 //   t_ij = (gamma vpot_j - C_ij) log2(e)/eps,  (max_j t, sum_j 2^(t - max)).
+// FUSE (one split): the wave holds the whole row, so it writes the potential
+// and its row-marginal error term itself (the merge kernel's arithmetic),
+// and the workgroup writes one error partial per 4 rows.
+template <bool FUSE>
 __global__ __launch_bounds__(256) void pcost_lse_rows(LseJob J) {
+    __shared__ float errw[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int S = J.S;
     const int split = (int)(blockIdx.x % S);
     const int64_t row = (int64_t)(blockIdx.x / S) * 4 + wave;
-    if (row >= J.nu) return;   // whole wave; no workgroup barrier below
+    const bool live = row < J.nu;
+    if (!FUSE && !live) return;   // whole wave; no workgroup barrier in this form
     const int64_t c_lo = (int64_t)split * J.cps;
     const int64_t c_hi = std::min(J.nv, c_lo + J.cps);
     const float k = J.bscale, gk = J.gamma * J.bscale;
-    const float *__restrict__ crow = J.cmat + row * J.ldc;
+    const float *__restrict__ crow = J.cmat + (live ? row : 0) * J.ldc;
     const float *__restrict__ vp = J.vpot;
     // vector loads of the potential only where it is 16-byte aligned (a row
     // of a caller's K x m array need not be)
     const bool vp4 = vp && (reinterpret_cast<uintptr_t>(vp) & 15) == 0;
     float M = kNegBig, s = 0.f;
-    for (int64_t c = c_lo + 4 * lane; c < c_hi; c += 256 * 8) {
+    for (int64_t c = c_lo + 4 * lane; live && c < c_hi; c += 256 * 8) {
         float t[32];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -214,17 +222,69 @@ __global__ __launch_bounds__(256) void pcost_lse_rows(LseJob J) {
     }
     const float Mw = wave_max(M);
     s = wave_sum(s * ex2(M - Mw));
-    if (lane == 0) {
-        J.part_m[(int64_t)split * J.nu + row] = Mw;
-        J.part_s[(int64_t)split * J.nu + row] = s;
+    if (!FUSE) {
+        if (lane == 0) {
+            J.part_m[(int64_t)split * J.nu + row] = Mw;
+            J.part_s[(int64_t)split * J.nu + row] = s;
+        }
+        return;
+    }
+    float e = 0.f;
+    if (live && lane == 0) {
+        const float L = Mw + log2f(s);
+        const float lw = J.logw[row];
+        const float pot = fmaf(J.eps, lw, 0.f) - J.eps * kLn2 * L;
+        if (J.pot_old) e = expf(lw) * fabsf(expm1f((J.pot_old[row] - pot) / J.eps));
+        J.pot_out[row] = pot;
+    }
+    if (J.pot_old) {
+        if (lane == 0) errw[wave] = e;
+        __syncthreads();
+        if (threadIdx.x == 0) J.err_part[blockIdx.x] = (errw[0] + errw[1]) + (errw[2] + errw[3]);
+    }
+}
+
+// Merge of split partials for the general-cost updates: one wave per
+// output (its lanes fold the splits), the potential as in the squared
+// path's merge, one error partial per 4 outputs.
+__global__ __launch_bounds__(256) void pcost_merge(LseJob J) {
+    __shared__ float errw[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 4 + wave;
+    const bool live = i < J.nu;
+    float M = kNegBig, sum = 0.f;
+    for (int s = lane; live && s < J.S; s += 64) {
+        const float m = J.part_m[(int64_t)s * J.nu + i], v = J.part_s[(int64_t)s * J.nu + i];
+        const float Mn = fmaxf(M, m);
+        sum = sum * ex2(M - Mn) + v * ex2(m - Mn);
+        M = Mn;
+    }
+    const float Mw = wave_max(M);
+    sum = wave_sum(sum * ex2(M - Mw));
+    float e = 0.f;
+    if (live && lane == 0) {
+        const float L = Mw + log2f(sum);
+        const float lw = J.logw[i];
+        const float pot = fmaf(J.eps, lw, 0.f) - J.eps * kLn2 * L;
+        if (J.pot_old) e = expf(lw) * fabsf(expm1f((J.pot_old[i] - pot) / J.eps));
+        J.pot_out[i] = pot;
+    }
+    if (J.pot_old) {
+        if (lane == 0) errw[wave] = e;
+        __syncthreads();
+        if (threadIdx.x == 0) J.err_part[blockIdx.x] = (errw[0] + errw[1]) + (errw[2] + errw[3]);
     }
 }
 
 // g-update partials: column j of C (the output index, J.nu = m columns)
 // against the split's rows (J.cps rows per split, J.nv = n rows),
 //   t_ij = (gamma vpot_i - C_ij) log2(e)/eps.
-__global__ __launch_bounds__(256) void pcost_lse_cols(LseJob J) {
-    __shared__ float sm[4][256], ss[4][256];
+// kColWaves waves share the workgroup's 256 columns and walk interleaved
+// 8-row chunks, so one split covers kColWaves x more rows per launch and the
+// merge has fewer splits to fold.
+constexpr int kColWaves = 8;
+__global__ __launch_bounds__(64 * kColWaves) void pcost_lse_cols(LseJob J) {
+    __shared__ float sm[kColWaves][256], ss[kColWaves][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int S = J.S;
     const int split = (int)(blockIdx.x % S);
@@ -237,7 +297,7 @@ __global__ __launch_bounds__(256) void pcost_lse_cols(LseJob J) {
     const float *__restrict__ vp = J.vpot;
     float M[4] = {kNegBig, kNegBig, kNegBig, kNegBig};
     float s[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t r = r_lo + 8 * wave; r < r_hi; r += 32) {
+    for (int64_t r = r_lo + 8 * wave; r < r_hi; r += 8 * kColWaves) {
         f4 cv[8];
         float fv[8];
 #pragma unroll
@@ -273,13 +333,13 @@ __global__ __launch_bounds__(256) void pcost_lse_cols(LseJob J) {
     }
     __syncthreads();
     const int64_t j = jb + tid;
-    if (j < J.nu) {
+    if (tid < 256 && j < J.nu) {
         float Mx = sm[0][tid];
 #pragma unroll
-        for (int w = 1; w < 4; ++w) Mx = fmaxf(Mx, sm[w][tid]);
+        for (int w = 1; w < kColWaves; ++w) Mx = fmaxf(Mx, sm[w][tid]);
         float tot = 0.f;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) tot += ss[w][tid] * ex2(sm[w][tid] - Mx);
+        for (int w = 0; w < kColWaves; ++w) tot += ss[w][tid] * ex2(sm[w][tid] - Mx);
         J.part_m[(int64_t)split * J.nu + j] = Mx;
         J.part_s[(int64_t)split * J.nu + j] = tot;
     }
@@ -506,26 +566,40 @@ void plan_pcost_job(LseJob &j) {
         per = (j.nv + S - 1) / S;
         per = (per + 3) / 4 * 4;
     } else {
-        // columns of C: 256 per workgroup, >= 64 rows per split
+        // columns of C: 256 per workgroup, >= 128 rows per split, >= 4096
+        // waves in the grid; the split partials (kMaxSplit x max(n, m)
+        // floats) hold up to kMaxSplit max(n, m) / m splits of m columns
         tiles = (j.nu + 255) / 256;
-        S = tiles >= 1024 ? 1 : (1024 + tiles - 1) / tiles;
-        S = std::min<int64_t>(S, std::max<int64_t>(1, j.nv / 64));
-        S = std::min<int64_t>(S, kMaxSplit);
+        const int64_t target = 4096 / kColWaves;
+        S = tiles >= target ? 1 : (target + tiles - 1) / tiles;
+        S = std::min<int64_t>(S, std::max<int64_t>(1, j.nv / 128));
+        S = std::min<int64_t>(S, kMaxSplit * std::max(j.nu, j.nv) / j.nu);
         per = (j.nv + S - 1) / S;
     }
     S = (j.nv + per - 1) / per;
     j.S = (int)S;
     j.cps = per;
     j.blocks = tiles * S;
-    j.mblocks = (j.nu + 255) / 256;
+    // one split of rows: the partial kernel writes the potential itself;
+    // otherwise the merge runs 4 outputs per workgroup
+    j.mblocks = (!j.cmat_cols && S == 1) ? tiles : (j.nu + 3) / 4;
+}
+
+bool pcost_fused(const LseJob &j) { return !j.cmat_cols && j.S == 1; }
+
+hipError_t launch_pcost_merge(const LseJob &j, hipStream_t s) {
+    hipLaunchKernelGGL(pcost_merge, dim3((unsigned)j.mblocks), dim3(256), 0, s, j);
+    return hipGetLastError();
 }
 
 hipError_t launch_pcost_partial(const LseJob &j, hipStream_t s) {
     if (j.blocks > 0x7fffffff || !j.cmat || j.ldc % 4) return hipErrorInvalidValue;
-    if (!j.cmat_cols)
-        hipLaunchKernelGGL(pcost_lse_rows, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+    if (pcost_fused(j))
+        hipLaunchKernelGGL(pcost_lse_rows<true>, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+    else if (!j.cmat_cols)
+        hipLaunchKernelGGL(pcost_lse_rows<false>, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
     else
-        hipLaunchKernelGGL(pcost_lse_cols, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+        hipLaunchKernelGGL(pcost_lse_cols, dim3((unsigned)j.blocks), dim3(64 * kColWaves), 0, s, j);
     return hipGetLastError();
 }
 

@@ -39,6 +39,8 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p) {
     L.f1 = take((size_t)n * 4);
     L.g0 = take((size_t)m * 4);
     L.g1 = take((size_t)m * 4);
+    L.f2 = take((size_t)n * 4);
+    L.g2 = take((size_t)m * 4);
     L.pm = take((size_t)pot::kMaxSplit * nm * 4);
     L.ps = take((size_t)pot::kMaxSplit * nm * 4);
     // error partials: one per 256 rows from the merge kernel, or one per 4
@@ -272,7 +274,7 @@ struct SinkResult {
     const float *f = nullptr, *g = nullptr;
 };
 
-// Enqueue err = sum of the error partials and its copy to the pinned slot.
+// Enqueue err = sum of the error partials and its copy to a pinned slot.
 int enqueue_err_readback(const pot_clouds *c, const Layout &L, int nparts, float *host,
                          hipEvent_t ev, hipStream_t s) {
     float *dev = at<float>(c, L.errd);
@@ -283,58 +285,79 @@ int enqueue_err_readback(const pot_clouds *c, const Layout &L, int nparts, float
 }
 
 // Alg. 1 on c->xk.  Iteration t: f_t from g_{t-1} (whose error partials are
-// the row-marginal error of iterate t-1), then g_t from f_t.  While g_t runs
-// the host reads err_{t-1}; the ping-pong buffers keep iterate t-1 intact
-// so it can be returned.
+// the row-marginal error of iterate t-1), then g_t from f_t.  The host
+// checks the errors kLag iterations behind the work it has enqueued, so the
+// stream always holds the next iterations while the host waits on a
+// read-back; the potentials live in a ring of kLag + 1 slots, so the
+// iterate whose error is being read is still intact when it is returned.
+// Errors are checked in order and the first iterate with err <= tau is
+// returned, as in a loop that checks every iteration before going on.
+constexpr int kLag = 2;
+constexpr int kRing = kLag + 1;
+
+struct Events {
+    hipEvent_t ev[kRing] = {};
+    ~Events() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
 int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, int max_iter,
                   const float *g_init, float gamma, SinkResult *out, hipStream_t s) {
-    float *fb[2] = {at<float>(c, L.f0), at<float>(c, L.f1)};
-    float *gb[2] = {at<float>(c, L.g0), at<float>(c, L.g1)};
+    float *fb[kRing] = {at<float>(c, L.f0), at<float>(c, L.f1), at<float>(c, L.f2)};
+    float *gb[kRing] = {at<float>(c, L.g0), at<float>(c, L.g1), at<float>(c, L.g2)};
     float *host = pinned_slot();
     if (!host) return POT_ERR_DEVICE;
-    hipEvent_t ev;
-    POT_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    int status = POT_OK;
+    Events E;
+    for (hipEvent_t &e : E.ev) POT_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     LseJob fa = f_job(c, L, eps);
     LseJob ga = g_job(c, L, eps);
-    for (int t = 1;; ++t) {
-        fa.vpot = t == 1 ? g_init : gb[(t - 1) & 1];
-        fa.gamma = t == 1 ? gamma : 1.f;
-        fa.pot_old = t == 1 ? nullptr : fb[(t - 1) & 1];
-        fa.pot_out = fb[t & 1];
-        int nparts = 0;
-        if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) { status = POT_ERR_DEVICE; break; }
-        if (t > 1 && (status = enqueue_err_readback(c, L, nparts, host, ev, s)) != POT_OK) break;
-        ga.vpot = fb[t & 1];
-        ga.pot_out = gb[t & 1];
-        if (pot::launch_lse_update(ga, s, nullptr) != hipSuccess) { status = POT_ERR_DEVICE; break; }
-        if (t > 1) {
-            if (hipEventSynchronize(ev) != hipSuccess) { status = POT_ERR_DEVICE; break; }
-            const float err = *host;
-            if (!std::isfinite(err)) { status = POT_ERR_NUMERIC; break; }
-            if (tau > 0.f && err <= tau) {
-                out->iters = t - 1; out->err = err; out->converged = true;
-                out->f = fb[(t - 1) & 1]; out->g = gb[(t - 1) & 1];
-                break;
-            }
+    // read err_k (its copy was enqueued with f_{k+1}); true when the loop ends at k
+    auto check = [&](int k, int *status) -> bool {
+        if (hipEventSynchronize(E.ev[k % kRing]) != hipSuccess) { *status = POT_ERR_DEVICE; return true; }
+        const float err = host[k % kRing];
+        if (!std::isfinite(err)) { *status = POT_ERR_NUMERIC; return true; }
+        if (tau > 0.f && err <= tau) {
+            out->iters = k; out->err = err; out->converged = true;
+            out->f = fb[k % kRing]; out->g = gb[k % kRing];
+            return true;
         }
+        return false;
+    };
+    int status = POT_OK;
+    for (int t = 1;; ++t) {
+        fa.vpot = t == 1 ? g_init : gb[(t - 1) % kRing];
+        fa.gamma = t == 1 ? gamma : 1.f;
+        fa.pot_old = t == 1 ? nullptr : fb[(t - 1) % kRing];
+        fa.pot_out = fb[t % kRing];
+        int nparts = 0;
+        if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) return POT_ERR_DEVICE;
+        if (t > 1 && (status = enqueue_err_readback(c, L, nparts, host + (t - 1) % kRing,
+                                                    E.ev[(t - 1) % kRing], s)) != POT_OK)
+            return status;
+        ga.vpot = fb[t % kRing];
+        ga.pot_out = gb[t % kRing];
+        if (pot::launch_lse_update(ga, s, nullptr) != hipSuccess) return POT_ERR_DEVICE;
+        // err_{t-kLag}: its slots are not written before iteration t + 1
+        if (t - kLag >= 1 && check(t - kLag, &status)) return status;
         if (t == max_iter) {
-            // err of the last iterate: one more f-update into the spare buffer.
-            fa.vpot = gb[t & 1]; fa.gamma = 1.f;
-            fa.pot_old = fb[t & 1]; fa.pot_out = fb[(t + 1) & 1];
-            if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) { status = POT_ERR_DEVICE; break; }
-            if ((status = enqueue_err_readback(c, L, nparts, host, ev, s)) != POT_OK) break;
-            if (hipEventSynchronize(ev) != hipSuccess) { status = POT_ERR_DEVICE; break; }
-            const float err = *host;
-            if (!std::isfinite(err)) { status = POT_ERR_NUMERIC; break; }
-            out->iters = t; out->err = err;
-            out->converged = tau > 0.f ? err <= tau : true;
-            out->f = fb[t & 1]; out->g = gb[t & 1];
-            break;
+            for (int k = std::max(1, t - kLag + 1); k < t; ++k)
+                if (check(k, &status)) return status;
+            // err of the last iterate: one more f-update into the free slot
+            fa.vpot = gb[t % kRing]; fa.gamma = 1.f;
+            fa.pot_old = fb[t % kRing]; fa.pot_out = fb[(t + 1) % kRing];
+            if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) return POT_ERR_DEVICE;
+            if ((status = enqueue_err_readback(c, L, nparts, host + t % kRing, E.ev[t % kRing], s)) !=
+                POT_OK)
+                return status;
+            if (check(t, &status)) return status;
+            out->iters = t; out->err = host[t % kRing];
+            out->converged = tau > 0.f ? out->err <= tau : true;
+            out->f = fb[t % kRing]; out->g = gb[t % kRing];
+            return POT_OK;
         }
     }
-    (void)hipEventDestroy(ev);
-    return status;
 }
 
 }  // namespace

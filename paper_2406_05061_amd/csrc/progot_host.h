@@ -16,6 +16,7 @@ namespace host {
 struct Layout {
     size_t xk, xsq, ysq, la, lb, xlp, ylp, ytl, f0, f1, g0, g1, pm, ps, errp, errd, xst, yst, chr, chc,
         n64;
+    size_t f2, g2;         // third potential slots of the single-problem Sinkhorn loop
     size_t cm, cmp, mpa;   // general costs: cost matrix, its block sums, map partials
     size_t total;
 };

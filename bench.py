@@ -77,23 +77,29 @@ KERNEL_SOURCES = ["paper_2406_05061_amd/csrc/progot_kernels.hip",
                   "paper_2406_05061_amd/build.py"]
 
 
-def kernel_source_sha() -> str:
+# ... and the general-cost potential kernels.
+PCOST_SOURCES = ["paper_2406_05061_amd/csrc/progot_pcost.hip",
+                 "paper_2406_05061_amd/csrc/progot_device.h",
+                 "paper_2406_05061_amd/csrc/progot_internal.h",
+                 "paper_2406_05061_amd/build.py"]
+
+
+def kernel_source_sha(sources=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (KERNEL_SOURCES if sources is None else sources):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str, workload: str):
+def recorded_traffic(kernel: str, workload: str, sources=None):
     """HBM bytes per launch from the committed rocprofv3 --pmc record, or None
     when there is none or the kernel source changed since it was taken."""
-    import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
     except (OSError, KeyError, ValueError):
         return None
-    if rec.get("kernel_sha256_16") != kernel_source_sha() or rec.get("workload") != workload:
+    if rec.get("kernel_sha256_16") != kernel_source_sha(sources) or rec.get("workload") != workload:
         return None
     return float(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
 
@@ -368,7 +374,8 @@ def pcost_bench(args, out):
                 "sinkhorn_iters_per_solve": infos[-1].iters,
                 "final_marginal_l1_fp64": {"row": row, "col": col},
                 "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                             "frac": gbs / HBM_PEAK_GBS,
+                             "traffic": recorded_traffic("pcost_lse", "pcost_4i_d47", PCOST_SOURCES),
                              "kernel": "pcost_lse_rows / pcost_lse_cols (resident cost matrix)",
                              "avg_launch_us": avg_lse * 1e6, "launches": lse_n,
                              "bytes_per_launch": n * m * 4},

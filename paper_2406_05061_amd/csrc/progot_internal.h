@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstddef>
 #include <cstdint>
 
@@ -193,10 +194,27 @@ hipError_t launch_diag_sums(const float *X, const float *Y, int64_t n, int d, co
                             const float *g, float eps, float cost_p, double *part, hipStream_t s);
 int diag_blocks(int64_t n);
 
-// Launch timing (see pot_timing_enable): kind 0 = cost + log-sum-exp
-// partial kernel, kind 1 = entropic-map kernel.  timing_begin returns an
-// opaque slot (or -1 when timing is off); timing_end closes it.
-int64_t timing_begin(int kind, hipStream_t s);
-void timing_end(int64_t slot, hipStream_t s);
+// Launch timing (see pot_timing_enable): kind 0 = potential (cost +
+// log-sum-exp) partial kernel, kind 1 = entropic-map kernel.  When timing is
+// on, timed_launch hands a start and a stop event to the dispatch itself
+// (hipExtLaunchKernelGGL), so each interval is the kernel's execution alone,
+// without the gap to the previous command on the stream.
+struct TimedEvents {
+    hipEvent_t start, stop;
+};
+TimedEvents timing_events(int kind);          // both null when timing is off
+void timing_commit(int kind, TimedEvents t);  // after the launch that records them
+
+template <typename... KArgs, typename... Args>
+void timed_launch(int kind, void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shmem,
+                  hipStream_t s, Args... args) {
+    const TimedEvents t = timing_events(kind);
+    if (t.start) {
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0, args...);
+        timing_commit(kind, t);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+    }
+}
 
 }  // namespace pot

@@ -579,23 +579,22 @@ template <int D, int QB>
 hipError_t lse_launch_t(const LseJob &j, hipStream_t s) {
     // the plan must cover every row tile of this kernel variant
     if (j.blocks != (j.nu + 64 * QB - 1) / (64 * QB) * j.S) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((lse_partial_f32<D, QB>), dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+    timed_launch(0, lse_partial_f32<D, QB>, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
     return hipGetLastError();
 }
 
 template <int D, int QB>
 hipError_t lse_group_launch_t(const LseJob *jobs_dev, int njobs, int64_t total, hipStream_t s) {
-    hipLaunchKernelGGL((lse_partial_f32_group<D, QB>), dim3((unsigned)total), dim3(256), 0, s,
-                       jobs_dev, njobs);
+    timed_launch(0, lse_partial_f32_group<D, QB>, dim3((unsigned)total), dim3(256), 0, s, jobs_dev,
+                 njobs);
     return hipGetLastError();
 }
 
 template <int D, int QB>
 hipError_t map_launch_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     const int64_t tiles = (a.nq + 64 * QB - 1) / (64 * QB);
-    hipLaunchKernelGGL((entropic_map_f32<D, QB>), dim3((unsigned)tiles), dim3(256), 0, s, a.Xq,
-                       a.nq, a.d, a.Y, a.ysq, a.g, a.m, scale2, bscale, a.alpha, a.Xout,
-                       a.out_sqn);
+    timed_launch(1, entropic_map_f32<D, QB>, dim3((unsigned)tiles), dim3(256), 0, s, a.Xq, a.nq, a.d,
+                 a.Y, a.ysq, a.g, a.m, scale2, bscale, a.alpha, a.Xout, a.out_sqn);
     return hipGetLastError();
 }
 
@@ -663,7 +662,6 @@ hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
     if (j.cmat) plan_pcost_job(j);
     else plan_lse_job(j);
     hipError_t e;
-    const int64_t slot = timing_begin(0, s);
     if (j.cmat) {
         e = launch_pcost_partial(j, s);
     } else if (j.precision != 0) {
@@ -675,7 +673,6 @@ hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
         case 128: e = lse_launch_t<128, lse_qb(128)>(j, s); break;
         default: e = lse_launch_t<256, lse_qb(256)>(j, s); break;
     }
-    timing_end(slot, s);
     if (e != hipSuccess) return e;
     if (j.cmat) {
         if (!pcost_fused(j) && (e = launch_pcost_merge(j, s)) != hipSuccess) return e;
@@ -705,7 +702,6 @@ hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, fl
     }
     hipError_t e = hipMemcpyAsync(jobs_dev, jobs, sizeof(LseJob) * njobs, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
-    const int64_t slot = timing_begin(0, s);
     switch (D) {
         case 16: e = lse_group_launch_t<16, lse_qb(16)>(jobs_dev, njobs, blk, s); break;
         case 32: e = lse_group_launch_t<32, lse_qb(32)>(jobs_dev, njobs, blk, s); break;
@@ -713,7 +709,6 @@ hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, fl
         case 128: e = lse_group_launch_t<128, lse_qb(128)>(jobs_dev, njobs, blk, s); break;
         default: e = lse_group_launch_t<256, lse_qb(256)>(jobs_dev, njobs, blk, s); break;
     }
-    timing_end(slot, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(lse_merge_group, dim3((unsigned)mblk), dim3(256), 0, s, jobs_dev, njobs);
     if (nerr > 0)
@@ -757,7 +752,6 @@ hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s) {
     if (a.nq == 0) return hipSuccess;
     const float scale2 = 2.f * kLog2e / a.eps;
     const float bscale = kLog2e / a.eps;
-    const int64_t slot = timing_begin(1, s);
     hipError_t e;
     if (a.precision != 0) {
         e = launch_map_bf16(a, scale2, bscale, s);
@@ -768,7 +762,6 @@ hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s) {
         case 128: e = map_launch_t<128, 2>(a, scale2, bscale, s); break;
         default: e = map_launch_t<256, 1>(a, scale2, bscale, s); break;
     }
-    timing_end(slot, s);
     return e;
 }
 

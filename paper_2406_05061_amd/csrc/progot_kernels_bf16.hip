@@ -763,9 +763,9 @@ hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     if (a.blocks != (a.nu + 64 * QB - 1) / (64 * QB) * a.S || a.cps % 64 != 0)
         return hipErrorInvalidValue;
     const int64_t vstride = bf16_mpad(a.nv) * D;
-    hipLaunchKernelGGL((lse_partial_bf16<D, QB, NPART>), dim3((unsigned)a.blocks), dim3(256), 0, s,
-                       a.U, a.nu, a.d, (const __bf16 *)a.V_lp, a.nv, vstride, a.vsq, a.vpot,
-                       a.gamma, a.scale2, a.bscale, a.S, a.cps, a.part_m, a.part_s);
+    timed_launch(0, lse_partial_bf16<D, QB, NPART>, dim3((unsigned)a.blocks), dim3(256), 0, s, a.U,
+                 a.nu, a.d, (const __bf16 *)a.V_lp, a.nv, vstride, a.vsq, a.vpot, a.gamma, a.scale2,
+                 a.bscale, a.S, a.cps, a.part_m, a.part_s);
     return hipGetLastError();
 }
 
@@ -773,9 +773,9 @@ template <int D, int NPART>
 hipError_t map_bf16_wide_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     if (a.mp != bf16_mpad(a.m) || a.out_sqn) return hipErrorInvalidValue;
     const int64_t tiles = (a.nq + 127) / 128;
-    hipLaunchKernelGGL((entropic_map_bf16_wide<D, NPART>), dim3((unsigned)tiles), dim3(512), 0, s,
-                       a.Xq, a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp,
-                       a.ysq, a.g, scale2, bscale, a.alpha, a.Xout);
+    timed_launch(1, entropic_map_bf16_wide<D, NPART>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
+                 a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
+                 scale2, bscale, a.alpha, a.Xout);
     return hipGetLastError();
 }
 
@@ -783,9 +783,9 @@ template <int D, int QB, int NPART>
 hipError_t map_bf16_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     if (a.mp != bf16_mpad(a.m)) return hipErrorInvalidValue;
     const int64_t tiles = (a.nq + 64 * QB - 1) / (64 * QB);
-    hipLaunchKernelGGL((entropic_map_bf16<D, QB, NPART>), dim3((unsigned)tiles), dim3(256), 0, s,
-                       a.Xq, a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m,
-                       a.mp, a.ysq, a.g, scale2, bscale, a.alpha, a.Xout, a.out_sqn);
+    timed_launch(1, entropic_map_bf16<D, QB, NPART>, dim3((unsigned)tiles), dim3(256), 0, s, a.Xq,
+                 a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
+                 scale2, bscale, a.alpha, a.Xout, a.out_sqn);
     return hipGetLastError();
 }
 

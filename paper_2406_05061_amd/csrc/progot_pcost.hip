@@ -502,9 +502,7 @@ hipError_t pmap_launch_t(const PcostMapArgs &a, hipStream_t s) {
         tps = std::max<int64_t>(2 * kMapTJ, (tps + kMapTJ - 1) / kMapTJ * kMapTJ);
         S = (a.m + tps - 1) / tps;
         if (S > 1 && (c.nq > a.cap_q || !a.pm || !a.ps || !a.pacc)) return hipErrorInvalidValue;
-        const int64_t slot = timing_begin(1, s);
-        hipLaunchKernelGGL((pcost_map<D, PK>), dim3((unsigned)(qb * S)), dim3(256), 0, s, c, (int)S, tps);
-        timing_end(slot, s);
+        timed_launch(1, pcost_map<D, PK>, dim3((unsigned)(qb * S)), dim3(256), 0, s, c, (int)S, tps);
         if (S > 1)
             hipLaunchKernelGGL((pcost_map_merge<PK>), dim3((unsigned)((c.nq * a.d + 255) / 256)), dim3(256),
                                0, s, c, (int)S, D);
@@ -595,11 +593,11 @@ hipError_t launch_pcost_merge(const LseJob &j, hipStream_t s) {
 hipError_t launch_pcost_partial(const LseJob &j, hipStream_t s) {
     if (j.blocks > 0x7fffffff || !j.cmat || j.ldc % 4) return hipErrorInvalidValue;
     if (pcost_fused(j))
-        hipLaunchKernelGGL(pcost_lse_rows<true>, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+        timed_launch(0, pcost_lse_rows<true>, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
     else if (!j.cmat_cols)
-        hipLaunchKernelGGL(pcost_lse_rows<false>, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
+        timed_launch(0, pcost_lse_rows<false>, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
     else
-        hipLaunchKernelGGL(pcost_lse_cols, dim3((unsigned)j.blocks), dim3(64 * kColWaves), 0, s, j);
+        timed_launch(0, pcost_lse_cols, dim3((unsigned)j.blocks), dim3(64 * kColWaves), 0, s, j);
     return hipGetLastError();
 }
 

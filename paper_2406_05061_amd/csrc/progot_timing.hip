@@ -1,12 +1,11 @@
 // Launch timing for the tracing aid of the C ABI (pot_timing_enable /
-// pot_timing_read): HIP timing events around kernel launches, resolved
-// lazily when read.
+// pot_timing_read): HIP timing events recorded by the kernel dispatches
+// themselves, resolved lazily when read.
 
 #include "progot.h"
 #include "progot_internal.h"
 
 #include <mutex>
-#include <unordered_map>
 #include <vector>
 
 namespace {
@@ -19,8 +18,6 @@ struct Rec {
 struct Timing {
     std::mutex mu;
     bool on = false;
-    int64_t next_id = 0;
-    std::unordered_map<int64_t, Rec> open;  // start recorded, stop pending
     std::vector<Rec> live;                  // both recorded, not yet resolved
     std::vector<hipEvent_t> pool;
     double ms[2] = {0.0, 0.0};
@@ -66,34 +63,30 @@ int resolve(Timing &t) {
 
 namespace pot {
 
-int64_t timing_begin(int kind, hipStream_t s) {
+TimedEvents timing_events(int kind) {
+    (void)kind;
     Timing &t = T();
     std::lock_guard<std::mutex> lk(t.mu);
-    if (!t.on) return -1;
-    Rec r{take(t), take(t), kind};
-    if (!r.start || !r.stop || hipEventRecord(r.start, s) != hipSuccess) {
-        if (r.start) t.pool.push_back(r.start);
-        if (r.stop) t.pool.push_back(r.stop);
-        return -1;
+    if (!t.on) return {nullptr, nullptr};
+    TimedEvents e{take(t), take(t)};
+    if (!e.start || !e.stop) {
+        if (e.start) t.pool.push_back(e.start);
+        if (e.stop) t.pool.push_back(e.stop);
+        return {nullptr, nullptr};
     }
-    const int64_t id = t.next_id++;
-    t.open.emplace(id, r);
-    return id;
+    return e;
 }
 
-void timing_end(int64_t slot, hipStream_t s) {
-    if (slot < 0) return;
+void timing_commit(int kind, TimedEvents e) {
+    if (!e.start) return;
     Timing &t = T();
     std::lock_guard<std::mutex> lk(t.mu);
-    auto it = t.open.find(slot);
-    if (it == t.open.end()) return;
-    Rec r = it->second;
-    t.open.erase(it);
-    if (hipEventRecord(r.stop, s) == hipSuccess) {
-        t.live.push_back(r);
+    // peek: the launch helper reports the launch's own error afterwards
+    if (hipPeekAtLastError() == hipSuccess) {
+        t.live.push_back(Rec{e.start, e.stop, kind});
     } else {
-        t.pool.push_back(r.start);
-        t.pool.push_back(r.stop);
+        t.pool.push_back(e.start);
+        t.pool.push_back(e.stop);
     }
 }
 

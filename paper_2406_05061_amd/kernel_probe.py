@@ -1,12 +1,15 @@
 """One launch of each hot kernel at a chosen shape, for profilers.
 
     python -m paper_2406_05061_amd.kernel_probe --n 65536 --d 128 --prec bf16
+    python -m paper_2406_05061_amd.kernel_probe --gen gmm --n 11000 --m 2800 --d 47 --cost-p 1.5 --theta 0.0625
 
-Prepares two seeded clustered unit-norm clouds (n x d each), runs `--iters`
-Sinkhorn iterations at eps = mean cost / 20 (each iteration is one f-update
-and one g-update launch of the fused cost + log-sum-exp kernel) and `--maps`
-launches of the entropic-map kernel on the source cloud, then prints the
-wall times.  Every step runs in libprogot.so; this file only drives it.
+Prepares two seeded clouds (clustered unit-norm, or Gaussian mixtures with
+--gen gmm; n x d and m x d), runs `--iters` Sinkhorn iterations at eps =
+theta * mean cost / 20 (each iteration is one f-update and one g-update of
+the potential kernels) and `--maps` launches of the entropic-map kernel on
+the source cloud, then prints the wall times.  --cost-p P selects the cost
+(1/P)|.|_P^P instead of the squared-Euclidean one.  Every step runs in
+libprogot.so; this file only drives it.
 """
 from __future__ import annotations
 
@@ -20,8 +23,12 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gen", default="sphere", choices=["sphere", "gmm"])
     ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--m", type=int, default=0, help="target points (default n)")
     ap.add_argument("--d", type=int, default=128)
+    ap.add_argument("--cost-p", type=float, default=0.0)
+    ap.add_argument("--theta", type=float, default=1.0)
     ap.add_argument("--prec", default="bf16", choices=["fp32", "bf16", "bf16x3"])
     ap.add_argument("--iters", type=int, default=1)
     ap.add_argument("--maps", type=int, default=1)
@@ -32,9 +39,13 @@ def main() -> None:
     import paper_2406_05061_amd as P
     import workloads
 
-    X, Y = workloads.sphere(seed=args.seed, n=args.n, m=args.n, d=args.d, n_clusters=64)
-    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=args.prec)
-    eps = cl.mean_cost / 20.0
+    m = args.m or args.n
+    if args.gen == "gmm":
+        X, Y = workloads.gmm(seed=args.seed, n=args.n, m=m, d=args.d, n_comp=10)
+    else:
+        X, Y = workloads.sphere(seed=args.seed, n=args.n, m=m, d=args.d, n_clusters=64)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=args.prec, cost_p=args.cost_p)
+    eps = args.theta * cl.mean_cost / 20.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, g, _ = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=args.iters)
@@ -45,7 +56,8 @@ def main() -> None:
         P.entropic_map(cl, g, eps, Xq)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    print(f"kernel_probe n={args.n} d={args.d} {args.prec}: {args.iters} Sinkhorn iterations "
+    print(f"kernel_probe n={args.n} m={m} d={args.d} {args.prec} cost_p={args.cost_p}: "
+          f"{args.iters} Sinkhorn iterations "
           f"{t1 - t0:.4f} s, {args.maps} maps {t2 - t1:.4f} s", flush=True)
 
 

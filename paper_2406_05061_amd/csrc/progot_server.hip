@@ -85,7 +85,8 @@ struct Req {
 size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
 
 // A tick gives each request up to kMaxSub iterations: about as many as fit in
-// one iteration of the largest active request (small problems would
+// one iteration of the largest active request, and the oldest request at
+// least the others' total (small problems would
 // otherwise wait on large ones for every single iteration).
 constexpr int kMaxSub = 16;
 
@@ -281,6 +282,23 @@ int pot_server_step(pot_server *S, int32_t *n_active, int32_t *n_finished) {
         const double ratio = cmax / ((double)r->c.n * r->c.m * r->c.d);
         q[i] = (int)std::min<double>(kMaxSub, std::max(1.0, std::floor(ratio)));
         Q = std::max(Q, q[i]);
+    }
+    // The oldest request also gets at least as much work as all the others
+    // together (up to kMaxSub iterations), so it advances at half speed or
+    // better however many requests join; without this, processor sharing
+    // slows a large request down by the number of comparable ones active,
+    // which is what sets the latency tail.
+    int head = -1;
+    for (int i = 0; i < ns; ++i)
+        if (head < 0 || solving[i]->id < solving[head]->id) head = i;
+    if (ns > 1) {
+        auto work = [&](int i) { return (double)solving[i]->c.n * solving[i]->c.m * solving[i]->c.d; };
+        double others = 0.0;
+        for (int i = 0; i < ns; ++i)
+            if (i != head) others += q[i] * work(i);
+        const double need = std::floor(others / work(head));
+        q[head] = (int)std::min<double>(kMaxSub, std::max<double>(q[head], need));
+        Q = std::max(Q, q[head]);
     }
     const int A = S->max_active;
     for (int sub = 0; sub < Q; ++sub) {

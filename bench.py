@@ -411,7 +411,7 @@ def main():
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=100_000, help="pcost_4i_d47: per solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--cpu-iters", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to scale "

@@ -131,8 +131,9 @@ POT_API int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const f
  * FP32 only (there is no inner-product form to put on MFMA).  The cost
  * matrix of the current source iterate is kept in the workspace (n x ldc
  * floats, rebuilt when the iterate moves), so the workspace grows with n m.
- * pot_eps_schedule and the serving form take squared-Euclidean clouds only
- * (POT_ERR_INVALID otherwise).
+ * Alg. 4 takes them too (pot_eps_schedule_pcost_bytes); the Sinkhorn
+ * divergence has its own general-cost entry point below; the serving form
+ * takes squared-Euclidean clouds only.
  *   1 < p <= 16; p == 1.5 takes a square-root path, other p a log/exp path.
  *   Limits: n * m <= 2^36. */
 POT_API size_t pot_workspace_bytes_pcost(int64_t n, int64_t m, int32_t d, float p);
@@ -250,6 +251,16 @@ POT_API int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, i
                                     const float *a, const float *b, float eps, float tau,
                                     int32_t max_iter, double *out, void *ws, size_t ws_bytes,
                                     void *stream);
+/* The same divergence with the cost h = (1/p)|.|_p^p (1 < p <= 16), as the
+ * map appendix evaluates its 1.5-norm experiments: the three solves run on
+ * general-cost clouds (see pot_prepare_clouds_pcost) and eps = 0 selects
+ * 5 % of the mean of h within Y.  Workspace:
+ * pot_sinkhorn_divergence_pcost_bytes(n, m, d, p) (0 if invalid). */
+POT_API size_t pot_sinkhorn_divergence_pcost_bytes(int64_t n, int64_t m, int32_t d, float p);
+POT_API int pot_sinkhorn_divergence_pcost(const float *X, int64_t n, const float *Y, int64_t m,
+                                          int32_t d, const float *a, const float *b, float p,
+                                          float eps, float tau, int32_t max_iter, double *out,
+                                          void *ws, size_t ws_bytes, void *stream);
 
 /* ---- Alg. 4 (eps-scheduler) ------------------------------------------------
  *
@@ -266,8 +277,8 @@ POT_API int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, i
  *           (1 - alpha_l) of the alpha schedule (K = 1: eps_final).
  * The grid solves run in FP32 and advance together in grouped launches; each
  * gets the same result as pot_sinkhorn_solve on (Y, Y) at its eps.
- *   c: prepared clouds (any precision, squared-Euclidean cost; only Y, b, m,
- *      d, mean_cost are used).
+ *   c: prepared clouds (any precision; only Y, b, m, d, mean_cost and the
+ *      cost are used).
  *   Y_test (device, m_test*d): hold-out targets.
  *   s_grid (host, n_grid doubles > 0), 1 <= n_grid <= POT_MAX_GRID.
  *   eps_out (host, K doubles); err_out (host, n_grid doubles) and p_star
@@ -276,6 +287,13 @@ POT_API int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, i
  * max_iter.  Blocks. */
 #define POT_MAX_GRID 64
 POT_API size_t pot_eps_schedule_bytes(int64_t m, int64_t m_test, int32_t d, int32_t n_grid);
+/* Clouds prepared with pot_prepare_clouds_pcost run Alg. 4 with their cost h
+ * (eps_0 and sigma from the mean of h, grid solves and maps with h; the
+ * hold-out score stays the squared distance).  The grid solves then run one
+ * after another on the resident (Y, Y) cost matrix, in a workspace of
+ * pot_eps_schedule_pcost_bytes(m, m_test, d, n_grid, p) bytes. */
+POT_API size_t pot_eps_schedule_pcost_bytes(int64_t m, int64_t m_test, int32_t d, int32_t n_grid,
+                                            float p);
 POT_API int pot_eps_schedule(const pot_clouds *c, const float *Y_test, int64_t m_test, int32_t K,
                              int32_t alpha_sched, const double *s_grid, int32_t n_grid, float beta0,
                              float tau, int32_t max_iter, double *eps_out, double *err_out,

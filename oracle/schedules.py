@@ -65,7 +65,7 @@ def tau_schedule(K: int, first: float, last: float) -> np.ndarray:
 
 
 def eps_scheduler(a, X, b, Y, alpha, Y_test, s_grid=None, beta0: float = 5.0,
-                  tau: float = 1e-3, max_iter: int = 10_000):
+                  tau: float = 1e-3, max_iter: int = 10_000, cost_p=None):
     """Alg. 4 (eps-scheduler).
 
     eps_0 = mean cost between X and Y / 20; sigma = mean intra-target cost
@@ -76,20 +76,29 @@ def eps_scheduler(a, X, b, Y, alpha, Y_test, s_grid=None, beta0: float = 5.0,
     t'_k eps_final with t'_k = 1 - prod_{l=1}^{k} (1 - alpha_l): step 0
     gets beta0 eps_0 and the last step gets eps_final.
 
+    cost_p = p runs it with h = (1/p)|.|_p^p: the mean costs, the grid
+    solves and the map use h; the hold-out score stays the squared distance.
+
     Returns (eps_schedule, info dict).
     """
     if s_grid is None:
         s_grid = [2.0 ** p for p in range(-3, 4)]
     alpha = np.asarray(alpha, dtype=np.float64)
     K = alpha.shape[0]
-    eps0 = float(cost_matrix(X, Y).mean() / 20.0)
-    Cyy = cost_matrix(Y, Y)
+    if cost_p is None:
+        cost, tmap = cost_matrix, entropic_map
+    else:
+        from . import pcost
+        cost = lambda U, V: pcost.cost_matrix_p(U, V, cost_p)
+        tmap = lambda Q, V, g, eps, alpha: pcost.entropic_map_p(Q, V, g, eps, cost_p, alpha=alpha)
+    eps0 = float(cost(X, Y).mean() / 20.0)
+    Cyy = cost(Y, Y)
     sigma = float(Cyy.mean() / 20.0)
     errors = []
     for s in s_grid:
         eps = s * sigma
         res = sinkhorn(b, Y, b, Y, eps, tau, max_iter=max_iter, C=Cyy)
-        Ty = entropic_map(Y_test, Y, res.g, eps, alpha=1.0)
+        Ty = tmap(Y_test, Y, res.g, eps, alpha=1.0)
         errors.append(float(((np.asarray(Y_test, np.float64) - Ty) ** 2).sum()))
     p_star = int(np.argmin(errors))
     eps_final = float(s_grid[p_star] * sigma)

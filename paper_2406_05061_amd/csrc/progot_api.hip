@@ -362,6 +362,21 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
 
 }  // namespace
 
+namespace pot {
+namespace host {
+
+int run_sinkhorn(const pot_clouds *c, const Layout &L, float eps, float tau, int max_iter,
+                 const float *g_init, float gamma, SinkOut *out, hipStream_t s) {
+    SinkResult r;
+    const int st = sinkhorn_core(c, L, eps, tau, max_iter, g_init, gamma, &r, s);
+    out->iters = r.iters; out->err = r.err; out->converged = r.converged;
+    out->f = r.f; out->g = r.g;
+    return st;
+}
+
+}  // namespace host
+}  // namespace pot
+
 extern "C" {
 
 const char *pot_status_string(int code) {
@@ -600,26 +615,32 @@ size_t pot_sinkhorn_divergence_bytes(int64_t n, int64_t m, int32_t d) {
                      plan(m, m, d, POT_PREC_FP32).total});
 }
 
-int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
-                            const float *a, const float *b, float eps, float tau, int32_t max_iter,
-                            double *out, void *ws, size_t ws_bytes, void *stream) {
-    if (!X || !Y || !out || !ws || !valid_sizes(n, m, d, POT_PREC_FP32) || !std::isfinite(eps) ||
-        eps < 0.f || !finite_pos(tau) || max_iter < 1)
-        return POT_ERR_INVALID;
-    if (ws_bytes < pot_sinkhorn_divergence_bytes(n, m, d)) return POT_ERR_NOMEM;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    // one pair at a time in the same workspace: (Y, Y) first, whose mean cost
-    // gives the default eps_D = 5 % of the mean intra-target cost
+size_t pot_sinkhorn_divergence_pcost_bytes(int64_t n, int64_t m, int32_t d, float p) {
+    if (!valid_pcost_sizes(n, m, d, p) || !valid_pcost_sizes(n, n, d, p) || !valid_pcost_sizes(m, m, d, p))
+        return 0;
+    return std::max({plan(n, m, d, POT_PREC_FP32, p).total, plan(n, n, d, POT_PREC_FP32, p).total,
+                     plan(m, m, d, POT_PREC_FP32, p).total});
+}
+
+}  // extern "C"
+
+namespace {
+
+// eq. sink_div: the pairs (Y, Y), (X, Y), (X, X) solved one after another in
+// the same workspace; (Y, Y) first, whose mean cost gives the default
+// eps_D = 5 % of the mean cost within Y.
+int divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d, const float *a,
+               const float *b, float cost_p, float eps, float tau, int32_t max_iter, double *out,
+               void *ws, size_t ws_bytes, hipStream_t s) {
     struct Pair { const float *U; int64_t nu; const float *wu; const float *V; int64_t nv; const float *wv; };
     const Pair pairs[3] = {{Y, m, b, Y, m, b}, {X, n, a, Y, m, b}, {X, n, a, X, n, a}};
     double ot[3];
     bool all = true;
     for (int k = 0; k < 3; ++k) {
         const Pair &q = pairs[k];
-        const Layout L = plan(q.nu, q.nv, d, POT_PREC_FP32);
+        const Layout L = plan(q.nu, q.nv, d, POT_PREC_FP32, cost_p);
         pot_clouds c;
-        int st = pot_prepare_clouds(&c, q.U, q.nu, q.V, q.nv, d, q.wu, q.wv, POT_PREC_FP32, ws,
-                                    L.total, stream);
+        int st = prepare(&c, q.U, q.nu, q.V, q.nv, d, q.wu, q.wv, POT_PREC_FP32, cost_p, ws, L.total, s);
         if (st != POT_OK) return st;
         if (k == 0 && eps == 0.f) eps = (float)(0.05 * c.mean_cost);
         if (!finite_pos(eps)) return POT_ERR_NUMERIC;
@@ -627,7 +648,7 @@ int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, int64_t m
         if ((st = sinkhorn_core(&c, L, eps, tau, max_iter, nullptr, 1.f, &r, s)) != POT_OK) return st;
         all = all && r.converged;
         double m6[6];
-        if ((st = pot_coupling_metrics(&c, r.f, r.g, eps, m6, stream)) != POT_OK) return st;
+        if ((st = pot_coupling_metrics(&c, r.f, r.g, eps, m6, s)) != POT_OK) return st;
         ot[k] = m6[2];
     }
     out[0] = ot[1] - 0.5 * (ot[2] + ot[0]);
@@ -636,6 +657,34 @@ int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, int64_t m
     out[3] = ot[0];
     out[4] = (double)eps;
     return all ? POT_OK : POT_WARN_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pot_sinkhorn_divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
+                            const float *a, const float *b, float eps, float tau, int32_t max_iter,
+                            double *out, void *ws, size_t ws_bytes, void *stream) {
+    if (!X || !Y || !out || !ws || !valid_sizes(n, m, d, POT_PREC_FP32) || !std::isfinite(eps) ||
+        eps < 0.f || !finite_pos(tau) || max_iter < 1)
+        return POT_ERR_INVALID;
+    if (ws_bytes < pot_sinkhorn_divergence_bytes(n, m, d)) return POT_ERR_NOMEM;
+    return divergence(X, n, Y, m, d, a, b, 0.f, eps, tau, max_iter, out, ws, ws_bytes,
+                      static_cast<hipStream_t>(stream));
+}
+
+int pot_sinkhorn_divergence_pcost(const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
+                                  const float *a, const float *b, float p, float eps, float tau,
+                                  int32_t max_iter, double *out, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    const size_t need = pot_sinkhorn_divergence_pcost_bytes(n, m, d, p);
+    if (!X || !Y || !out || !ws || need == 0 || !std::isfinite(eps) || eps < 0.f ||
+        !finite_pos(tau) || max_iter < 1)
+        return POT_ERR_INVALID;
+    if (ws_bytes < need) return POT_ERR_NOMEM;
+    return divergence(X, n, Y, m, d, a, b, p, eps, tau, max_iter, out, ws, ws_bytes,
+                      static_cast<hipStream_t>(stream));
 }
 
 int pot_diag_metrics(const pot_clouds *c, const float *f, const float *g, float eps, double *out,

@@ -68,6 +68,17 @@ bool valid_params(const pot_progot_params *p);
 int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
             float alpha, float *Xout, hipStream_t s);
 
+// Alg. 1 on c->xk as pot_sinkhorn_solve runs it; f and g point into the
+// clouds' workspace and stay valid until the next solve on it.
+struct SinkOut {
+    int iters;
+    float err;
+    bool converged;
+    const float *f, *g;
+};
+int run_sinkhorn(const pot_clouds *c, const Layout &L, float eps, float tau, int max_iter,
+                 const float *g_init, float gamma, SinkOut *out, hipStream_t s);
+
 }  // namespace host
 }  // namespace pot
 

@@ -1,4 +1,5 @@
-// Alg. 4 (the eps-scheduler) on the GPU.
+// Alg. 4 (the eps-scheduler) on the GPU.  (For the general cost
+// h = (1/p)|.|_p^p, see schedule_pcost below.)
 //
 // eps_0 is the mean cost of the caller's pair / 20 and sigma the mean cost of
 // the targets with themselves / 20 (closed form from the targets' FP64
@@ -100,9 +101,120 @@ LseJob point_job(const LseJob &base, const GridPoint &q) {
     return j;
 }
 
+// General costs: the (Y, Y) pair as general-cost clouds, then the mapped
+// hold-out targets and the FP64 partials.
+struct PSchedLayout {
+    Layout cy;
+    size_t ty, sq, total;
+};
+
+PSchedLayout psched_plan(int64_t m, int64_t mt, int32_t d, float p) {
+    PSchedLayout S{};
+    S.cy = plan(m, m, d, POT_PREC_FP32, p);
+    size_t off = a256(S.cy.total);
+    S.ty = off;
+    off = a256(off + (size_t)mt * d * 4);
+    S.sq = off;
+    S.total = a256(off + kSqBlocks * sizeof(double));
+    return S;
+}
+
+bool valid_pcost_pair(int64_t m, int32_t d, float p) {
+    return p != 0.f && valid_cost_p(p) && valid_sizes(m, m, d, POT_PREC_FP32) &&
+           (double)m * (double)pot::pcost_ldc(m) <= (double)(int64_t(1) << 36);
+}
+
+// Hold-out score err_p = sum |y~ - T_p(y~)|^2 of one grid solve (FP64 sum).
+int holdout_score(const pot_clouds *cy, const float *g, float eps, const float *Y_test, int64_t mt,
+                  float *ty, double *sq_dev, double *score, hipStream_t s) {
+    int st = run_map(cy, g, eps, Y_test, mt, 1.f, ty, s);
+    if (st != POT_OK) return st;
+    hipLaunchKernelGGL(sqdist_partial, dim3(kSqBlocks), dim3(256), 0, s, Y_test, ty,
+                       mt * (int64_t)cy->d, sq_dev);
+    POT_TRY(hipGetLastError());
+    std::vector<double> sq(kSqBlocks);
+    POT_TRY(hipMemcpyAsync(sq.data(), sq_dev, sizeof(double) * kSqBlocks, hipMemcpyDeviceToHost, s));
+    POT_TRY(hipStreamSynchronize(s));
+    double tot = 0.0;
+    for (double v : sq) tot += v;
+    if (!std::isfinite(tot)) return POT_ERR_NUMERIC;
+    *score = tot;
+    return POT_OK;
+}
+
+// eps_k from the selected scale (the last lines of Alg. 4).
+void write_schedule(int K, int alpha_sched, double beta0, double eps0, double eps_final,
+                    double *eps_out) {
+    float alpha[POT_MAX_K];
+    alpha_schedule(K, alpha_sched, alpha);
+    if (K == 1) {
+        eps_out[0] = eps_final;
+        return;
+    }
+    double prod = 1.0;
+    for (int k = 0; k < K; ++k) {
+        if (k > 0) prod *= 1.0 - (double)alpha[k];
+        const double tk = 1.0 - prod;
+        eps_out[k] = (1.0 - tk) * beta0 * eps0 + tk * eps_final;
+    }
+}
+
+// Alg. 4 for the cost h = (1/p)|.|_p^p: sigma from the mean of h within Y
+// (the (Y, Y) cost matrix), and the grid solves one after another on that
+// resident matrix with the single-problem loop; the hold-out score is the
+// same squared distance as for the squared-Euclidean cost.
+int schedule_pcost(const pot_clouds *c, const float *Y_test, int64_t mt, int32_t K,
+                   int32_t alpha_sched, const double *s_grid, int32_t n_grid, float beta0,
+                   float tau, int32_t max_iter, double *eps_out, double *err_out, int32_t *p_star,
+                   void *ws, size_t ws_bytes, hipStream_t s) {
+    const int64_t m = c->m;
+    const int d = c->d;
+    if (!valid_pcost_pair(m, d, c->cost_p)) return POT_ERR_INVALID;
+    const PSchedLayout S = psched_plan(m, mt, d, c->cost_p);
+    if (ws_bytes < S.total) return POT_ERR_NOMEM;
+    char *base = static_cast<char *>(ws);
+    pot_clouds cy;
+    bind_clouds(&cy, c->Y, m, c->Y, m, d, c->b, c->b, POT_PREC_FP32, ws, S.cy.total, S.cy, c->cost_p);
+    std::vector<double> mom(moments_len(d));
+    int st = enqueue_prepare(&cy, S.cy, mom.data(), s);
+    if (st != POT_OK) return st;
+    POT_TRY(hipStreamSynchronize(s));
+    if ((st = finish_moments(&cy, mom.data())) != POT_OK) return st;
+    if ((st = refresh_pcost(&cy, S.cy, s)) != POT_OK) return st;
+    const double sigma = cy.mean_cost / 20.0;
+    const double eps0 = c->mean_cost / 20.0;
+    if (!(sigma > 0.0) || !(eps0 > 0.0)) return POT_ERR_NUMERIC;
+    float *ty = reinterpret_cast<float *>(base + S.ty);
+    double *sq_dev = reinterpret_cast<double *>(base + S.sq);
+    std::vector<double> score(n_grid);
+    bool all = true;
+    for (int q = 0; q < n_grid; ++q) {
+        const float eps = (float)(s_grid[q] * sigma);
+        if (!finite_pos(eps)) return POT_ERR_INVALID;
+        SinkOut r;
+        if ((st = run_sinkhorn(&cy, S.cy, eps, tau, max_iter, nullptr, 1.f, &r, s)) != POT_OK) return st;
+        all = all && r.converged;
+        if ((st = holdout_score(&cy, r.g, eps, Y_test, mt, ty, sq_dev, &score[q], s)) != POT_OK)
+            return st;
+    }
+    int best = 0;
+    for (int q = 1; q < n_grid; ++q)
+        if (score[q] < score[best]) best = q;
+    write_schedule(K, alpha_sched, beta0, eps0, s_grid[best] * sigma, eps_out);
+    if (err_out)
+        for (int q = 0; q < n_grid; ++q) err_out[q] = score[q];
+    if (p_star) *p_star = best;
+    return all ? POT_OK : POT_WARN_NOT_CONVERGED;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t pot_eps_schedule_pcost_bytes(int64_t m, int64_t m_test, int32_t d, int32_t n_grid, float p) {
+    if (!valid_pcost_pair(m, d, p) || m_test < 1 || n_grid < 1 || n_grid > POT_MAX_GRID) return 0;
+    return psched_plan(m, m_test, d, p).total;
+}
 
 size_t pot_eps_schedule_bytes(int64_t m, int64_t m_test, int32_t d, int32_t n_grid) {
     if (!valid_sizes(m, m, d, POT_PREC_FP32) || m_test < 1 || n_grid < 1 || n_grid > POT_MAX_GRID)
@@ -116,10 +228,13 @@ int pot_eps_schedule(const pot_clouds *c, const float *Y_test, int64_t m_test, i
                      int32_t *p_star, void *ws, size_t ws_bytes, void *stream) {
     if (!valid_clouds(c) || !Y_test || m_test < 1 || K < 1 || K > POT_MAX_K || alpha_sched < 0 ||
         alpha_sched > 2 || !s_grid || n_grid < 1 || n_grid > POT_MAX_GRID || !finite_pos(beta0) ||
-        !finite_pos(tau) || max_iter < 1 || !eps_out || !ws || c->cost_p != 0.f)
+        !finite_pos(tau) || max_iter < 1 || !eps_out || !ws)
         return POT_ERR_INVALID;
     for (int p = 0; p < n_grid; ++p)
         if (!(std::isfinite(s_grid[p]) && s_grid[p] > 0.0)) return POT_ERR_INVALID;
+    if (c->cost_p != 0.f)
+        return schedule_pcost(c, Y_test, m_test, K, alpha_sched, s_grid, n_grid, beta0, tau, max_iter,
+                              eps_out, err_out, p_star, ws, ws_bytes, static_cast<hipStream_t>(stream));
     const int64_t m = c->m;
     const int d = c->d;
     const SchedLayout S = sched_plan(m, m_test, d, n_grid);
@@ -209,39 +324,17 @@ int pot_eps_schedule(const pot_clouds *c, const float *Y_test, int64_t m_test, i
     }
 
     // hold-out scores
-    std::vector<double> sq(kSqBlocks);
     std::vector<double> score(n_grid);
     float *ty = reinterpret_cast<float *>(base + S.ty);
     double *sq_dev = reinterpret_cast<double *>(base + S.sq);
-    for (int p = 0; p < n_grid; ++p) {
-        if ((st = run_map(&cy, pts[p].g, pts[p].eps, Y_test, m_test, 1.f, ty, s)) != POT_OK) return st;
-        hipLaunchKernelGGL(sqdist_partial, dim3(kSqBlocks), dim3(256), 0, s, Y_test, ty,
-                           m_test * (int64_t)d, sq_dev);
-        POT_TRY(hipGetLastError());
-        POT_TRY(hipMemcpyAsync(sq.data(), sq_dev, sizeof(double) * kSqBlocks, hipMemcpyDeviceToHost, s));
-        POT_TRY(hipStreamSynchronize(s));
-        double tot = 0.0;
-        for (double v : sq) tot += v;
-        if (!std::isfinite(tot)) return POT_ERR_NUMERIC;
-        score[p] = tot;
-    }
+    for (int p = 0; p < n_grid; ++p)
+        if ((st = holdout_score(&cy, pts[p].g, pts[p].eps, Y_test, m_test, ty, sq_dev, &score[p], s)) !=
+            POT_OK)
+            return st;
     int best = 0;
     for (int p = 1; p < n_grid; ++p)
         if (score[p] < score[best]) best = p;
-    const double eps_final = s_grid[best] * sigma;
-
-    float alpha[POT_MAX_K];
-    alpha_schedule(K, alpha_sched, alpha);
-    if (K == 1) {
-        eps_out[0] = eps_final;
-    } else {
-        double prod = 1.0;
-        for (int k = 0; k < K; ++k) {
-            if (k > 0) prod *= 1.0 - (double)alpha[k];
-            const double tk = 1.0 - prod;
-            eps_out[k] = (1.0 - tk) * beta0 * eps0 + tk * eps_final;
-        }
-    }
+    write_schedule(K, alpha_sched, beta0, eps0, s_grid[best] * sigma, eps_out);
     if (err_out)
         for (int p = 0; p < n_grid; ++p) err_out[p] = score[p];
     if (p_star) *p_star = best;

@@ -96,9 +96,13 @@ _SIGS = {
                                        _vp]),
     "pot_diag_metrics": (C.c_int, [C.POINTER(pot_clouds), _vp, _vp, _f32, C.POINTER(C.c_double), _vp]),
     "pot_sinkhorn_divergence_bytes": (C.c_size_t, [_i64, _i64, _i32]),
+    "pot_sinkhorn_divergence_pcost_bytes": (C.c_size_t, [_i64, _i64, _i32, _f32]),
+    "pot_sinkhorn_divergence_pcost": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _f32, _f32, _f32,
+                                                _i32, C.POINTER(C.c_double), _vp, C.c_size_t, _vp]),
     "pot_sinkhorn_divergence": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _f32, _f32, _i32,
                                           C.POINTER(C.c_double), _vp, C.c_size_t, _vp]),
     "pot_eps_schedule_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32]),
+    "pot_eps_schedule_pcost_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32, _f32]),
     "pot_eps_schedule": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _i32, _i32,
                                    C.POINTER(C.c_double), _i32, _f32, _f32, _i32,
                                    C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -382,7 +386,10 @@ def eps_schedule(cl: Clouds, Y_test, K: int, *, alpha_sched: str = "constant", s
         raise ValueError("Y_test must be m_test x d")
     grid = list(DEFAULT_S_GRID if s_grid is None else s_grid)
     G = len(grid)
-    nb = int(lib().pot_eps_schedule_bytes(cl.m, Y_test.shape[0], cl.d, G))
+    if cl.cost_p:
+        nb = int(lib().pot_eps_schedule_pcost_bytes(cl.m, Y_test.shape[0], cl.d, G, cl.cost_p))
+    else:
+        nb = int(lib().pot_eps_schedule_bytes(cl.m, Y_test.shape[0], cl.d, G))
     if nb == 0:
         raise ValueError("invalid sizes for the eps-scheduler")
     ws = torch.empty(nb, dtype=torch.uint8, device=cl.X.device)
@@ -421,9 +428,10 @@ def diag_metrics(cl: Clouds, f, g, eps: float):
 
 
 def sinkhorn_divergence(X, Y, a=None, b=None, eps: float = 0.0, tau: float = 1e-3,
-                        max_iter: int = 10_000) -> dict:
+                        max_iter: int = 10_000, cost_p: float = 0.0) -> dict:
     """Sinkhorn divergence (eq. sink_div); eps = 0 uses 5 % of the mean cost
-    within Y (the paper's eps_D)."""
+    within Y (the paper's eps_D); cost_p > 1 evaluates it with the cost
+    (1/p)|.|_p^p."""
     torch = _torch()
     for t, nm in ((X, "X"), (Y, "Y")):
         _dev_f32(t, nm)
@@ -435,14 +443,23 @@ def sinkhorn_divergence(X, Y, a=None, b=None, eps: float = 0.0, tau: float = 1e-
         _dev_f32(a, "a", (n,))
     if b is not None:
         _dev_f32(b, "b", (m,))
-    nb = int(lib().pot_sinkhorn_divergence_bytes(n, m, d))
+    if cost_p:
+        nb = int(lib().pot_sinkhorn_divergence_pcost_bytes(n, m, d, float(cost_p)))
+    else:
+        nb = int(lib().pot_sinkhorn_divergence_bytes(n, m, d))
     if nb == 0:
-        raise ValueError("invalid sizes")
+        raise ValueError("invalid sizes or cost")
     ws = torch.empty(nb, dtype=torch.uint8, device=X.device)
     out = (C.c_double * 5)()
-    st = _check(lib().pot_sinkhorn_divergence(_ptr(X), n, _ptr(Y), m, d, _ptr(a), _ptr(b), float(eps),
-                                              float(tau), int(max_iter), out, _ptr(ws), nb,
-                                              C.c_void_p(_stream())), "sinkhorn_divergence")
+    if cost_p:
+        st = _check(lib().pot_sinkhorn_divergence_pcost(
+            _ptr(X), n, _ptr(Y), m, d, _ptr(a), _ptr(b), float(cost_p), float(eps), float(tau),
+            int(max_iter), out, _ptr(ws), nb, C.c_void_p(_stream())), "sinkhorn_divergence_pcost")
+    else:
+        st = _check(lib().pot_sinkhorn_divergence(_ptr(X), n, _ptr(Y), m, d, _ptr(a), _ptr(b),
+                                                  float(eps), float(tau), int(max_iter), out,
+                                                  _ptr(ws), nb, C.c_void_p(_stream())),
+                    "sinkhorn_divergence")
     return {"D": out[0], "ot_xy": out[1], "ot_xx": out[2], "ot_yy": out[3], "eps": out[4],
             "status": st}
 

@@ -223,7 +223,7 @@ def test_pcost_workspace_and_prepare_reject_invalid():
 
 def test_pcost_clouds_validated():
     """A general-cost pot_clouds needs FP32, its cost matrix and its stride;
-    the scheduler refuses it."""
+    the scheduler asks for its own workspace size."""
     lib = P.lib()
     inv = B.POT_ERR_INVALID
     c = _fake_clouds(8, 8, 4)
@@ -244,8 +244,28 @@ def test_pcost_clouds_validated():
     c.precision = 1
     assert lib.pot_entropic_map(C.byref(c), 0x3000, 1.0, 0x3000, 4, 1.0, 0x3000, None) == inv
     c.precision = 0
+    # Alg. 4 on general-cost clouds takes the general-cost workspace
     grid = (C.c_double * 3)(0.5, 1.0, 2.0)
     eps = (C.c_double * 4)()
-    wsb = lib.pot_eps_schedule_bytes(8, 5, 4, 3)
+    wsb = lib.pot_eps_schedule_pcost_bytes(8, 5, 4, 3, 1.5)
+    assert wsb >= lib.pot_workspace_bytes_pcost(8, 8, 4, 1.5) and wsb % 256 == 0
+    assert lib.pot_eps_schedule_pcost_bytes(8, 5, 4, 3, 1.0) == 0
     assert lib.pot_eps_schedule(C.byref(c), 0x4000, 5, 4, 0, grid, 3, 5.0, 1e-3, 100, eps, None,
-                                None, 0x2000, wsb, None) == inv
+                                None, 0x2000, wsb - 1, None) == B.POT_ERR_NOMEM
+
+
+def test_pcost_divergence_rejects_invalid():
+    lib = P.lib()
+    inv = B.POT_ERR_INVALID
+    assert lib.pot_sinkhorn_divergence_pcost_bytes(100, 80, 8, 1.0) == 0
+    assert lib.pot_sinkhorn_divergence_pcost_bytes(0, 80, 8, 1.5) == 0
+    nb = lib.pot_sinkhorn_divergence_pcost_bytes(100, 80, 8, 1.5)
+    assert nb >= lib.pot_workspace_bytes_pcost(100, 100, 8, 1.5) and nb % 256 == 0
+    out = (C.c_double * 5)()
+    call = lambda **kw: lib.pot_sinkhorn_divergence_pcost(
+        kw.get("X", 0x1000), 100, kw.get("Y", 0x1000), 80, 8, None, None, kw.get("p", 1.5),
+        kw.get("eps", 0.0), kw.get("tau", 1e-3), kw.get("it", 100), kw.get("out", out),
+        kw.get("ws", 0x2000), kw.get("wsb", nb), None)
+    assert call(X=None) == inv and call(out=None) == inv and call(ws=None) == inv
+    assert call(p=0.5) == inv and call(eps=-1.0) == inv and call(tau=0.0) == inv and call(it=0) == inv
+    assert call(wsb=nb - 1) == B.POT_ERR_NOMEM

@@ -222,8 +222,51 @@ def test_diag_metrics(P):
     assert abs(tr - rt) <= 1e-9 * rt and abs(kl - rk) <= 1e-9 * max(1.0, abs(rk))
 
 
-def test_scheduler_rejects_general_cost(P):
-    X, Y = workloads.c1(seed=1, n=256, m=256, d=4)
+@pytest.mark.parametrize("K,alpha_sched", [(4, "constant"), (1, "constant")])
+def test_eps_schedule(P, K, alpha_sched):
+    """Alg. 4 with h = (1/p)|.|_p^p, p = 1.5, on the small ProgOT workload,
+    against the oracle's Alg. 4 with the same cost (grid 2^-3..2^3, 1024
+    hold-out targets); then ProgOT fed the GPU schedule."""
+    X, Y = workloads.c1(seed=1)
+    Yt = workloads.c1_holdout(seed=1, test_seed=101)
+    n, m = X.shape[0], Y.shape[0]
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    tau = 1e-3
+    alpha = oracle.schedules.alpha_schedule(K, alpha_sched)
+    ref, info = oracle.schedules.eps_scheduler(a, X, b, Y, alpha, Yt, beta0=5.0, tau=tau, cost_p=1.5)
     cl = _clouds(P, X, Y, 1.5)
-    with pytest.raises(P.PotError):
-        P.eps_schedule(cl, P.to_device(Y[:64]), 4)
+    out = P.eps_schedule(cl, P.to_device(Yt), K, alpha_sched=alpha_sched, beta0=5.0, tau=tau)
+    print(f"case K={K}: p* gpu {out.p_star} oracle {info['p_star']}; scores gpu "
+          f"{np.array(out.errors)} oracle {np.array(info['errors'])}", flush=True)
+    assert out.status == 0
+    np.testing.assert_allclose(out.errors, info["errors"], rtol=1e-3)
+    srt = np.sort(info["errors"])
+    if srt[1] > srt[0] * (1 + 1e-2):
+        assert out.p_star == info["p_star"]
+        np.testing.assert_allclose(out.eps, ref, rtol=1e-6)
+    else:
+        assert abs(info["errors"][out.p_star] - srt[0]) <= 1e-2 * srt[0]
+    if K > 1:
+        eps32 = np.asarray(out.eps, dtype=np.float32).astype(np.float64)
+        f, G, TX, pinfo = P.progot_solve(cl, K, eps=eps32, tau_first=tau, tau_last=tau)
+        pref = pcost.progot_p(a, X, b, Y, K, 1.5, eps=eps32, tau=tau)
+        assert pinfo.converged
+        assert map_err(TX.cpu().numpy(), pref.TX, Y) < 1e-3
+
+
+@pytest.mark.parametrize("eps", [0.0, 2.0])
+def test_sinkhorn_divergence(P, eps):
+    """eq. sink_div with h = (1/p)|.|_p^p, p = 1.5 (the map appendix's
+    1.5-norm evaluation): default eps_D = 5 % of the mean of h within Y, and
+    an explicit eps; GPU to tau = 1e-5, oracle to 1e-6."""
+    X, Y = workloads.gmm(seed=370, n=600, m=500, d=8)
+    out = P.sinkhorn_divergence(P.to_device(X), P.to_device(Y), eps=eps, tau=1e-5, cost_p=1.5)
+    e = out["eps"]
+    if eps == 0.0:
+        assert abs(e - metrics.eps_divergence_default(Y, cost_p=1.5)) <= 1e-6 * e
+    ref = metrics.sinkhorn_divergence(np.full(600, 1 / 600), X, np.full(500, 1 / 500), Y, eps=e,
+                                      tau=1e-6, cost_p=1.5)
+    print(f"eps {e:.4f}: D gpu {out['D']:.6f} oracle {ref[0]:.6f}", flush=True)
+    assert out["status"] == 0
+    for k, v in zip(("D", "ot_xy", "ot_xx", "ot_yy"), ref[:4]):
+        assert abs(out[k] - v) <= 1e-4 * e + 1e-5 * abs(v), (k, out[k], v)

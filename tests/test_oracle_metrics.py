@@ -2,6 +2,7 @@
 sum P log P, trace / KL of the coupling-recovery benchmark) against what
 the mathematics fixes."""
 import numpy as np
+import pytest
 
 import oracle
 from oracle import metrics
@@ -86,3 +87,28 @@ def test_diag_metrics_limits():
     r = oracle.sinkhorn(a, X, a, Y, 0.1 * C.mean() / 20, 1e-6, max_iter=100_000, C=C)
     tr, kl = metrics.diag_metrics(oracle.coupling(r.f, r.g, C, 0.1 * C.mean() / 20))
     assert tr > 0.99 and 0 <= kl < 0.02
+
+
+def test_divergence_general_cost_p2_is_half_squared():
+    """h = |.|^2/2: every OT_eps value is half the squared-Euclidean one at
+    twice eps (the same coupling), and the default eps_D halves with the
+    mean cost, so D_h = D/2 with both defaults."""
+    X, Y = workloads.gmm(seed=61, n=40, m=30, d=3)
+    a, b = np.full(40, 1 / 40), np.full(30, 1 / 30)
+    ds = metrics.sinkhorn_divergence(a, X, b, Y, tau=1e-10)
+    dp = metrics.sinkhorn_divergence(a, X, b, Y, tau=1e-10, cost_p=2.0)
+    assert dp[4] == pytest.approx(ds[4] / 2, rel=1e-12)
+    np.testing.assert_allclose(dp[:4], np.asarray(ds[:4]) / 2, rtol=1e-8, atol=1e-10)
+
+
+def test_divergence_general_cost_separates():
+    """p = 1.5: exp(-h/eps) is a positive-definite kernel (p <= 2), so the
+    divergence vanishes on equal clouds and is positive otherwise, growing
+    with a translation."""
+    X = workloads.gmm(seed=62, n=20, m=4, d=2)[0]
+    a = np.full(20, 1 / 20)
+    eps = 4 * metrics.eps_divergence_default(X, cost_p=1.5)
+    assert abs(metrics.sinkhorn_divergence(a, X, a, X, eps=eps, tau=1e-10, cost_p=1.5)[0]) < 1e-9
+    vals = [metrics.sinkhorn_divergence(a, X, a, X + s, eps=eps, tau=1e-10, cost_p=1.5)[0]
+            for s in (0.25, 1.0)]
+    assert 0 < vals[0] < vals[1]

@@ -188,3 +188,18 @@ def test_progot_p_k1_is_one_solve_and_map():
     assert r.eps[0] == pytest.approx(eps, rel=1e-15)
     np.testing.assert_allclose(r.G[0], s.g, rtol=1e-13, atol=1e-13)
     np.testing.assert_allclose(r.TX, pcost.entropic_map_p(X, Y, s.g, eps, 1.5), rtol=1e-13)
+
+
+def test_eps_scheduler_p2_is_half_squared():
+    """Alg. 4 with |.|^2/2: eps_0, sigma and every grid eps halve, the maps
+    and hence the hold-out scores and the selected scale are unchanged, and
+    the schedule halves."""
+    X, Y = workloads.c1(seed=2, n=80, m=70, d=3)
+    Yt = workloads.c1_holdout(seed=2, n=80, d=3, m_test=40)
+    a, b = np.full(80, 1 / 80), np.full(70, 1 / 70)
+    alpha = oracle.schedules.alpha_schedule(4)
+    rs, ins = oracle.schedules.eps_scheduler(a, X, b, Y, alpha, Yt, tau=1e-9)
+    rp, inp = oracle.schedules.eps_scheduler(a, X, b, Y, alpha, Yt, tau=1e-9, cost_p=2.0)
+    assert inp["p_star"] == ins["p_star"]
+    np.testing.assert_allclose(inp["errors"], ins["errors"], rtol=1e-7)
+    np.testing.assert_allclose(rp, rs / 2, rtol=1e-12)

@@ -270,3 +270,24 @@ def test_sinkhorn_divergence(P, eps):
     assert out["status"] == 0
     for k, v in zip(("D", "ot_xy", "ot_xx", "ot_yy"), ref[:4]):
         assert abs(out[k] - v) <= 1e-4 * e + 1e-5 * abs(v), (k, out[k], v)
+
+
+@pytest.mark.parametrize("p", [1.1, 4.0])
+def test_extreme_exponents(P, p):
+    """The log/exp kernels at the ends of the useful range: p = 1.1 (grad h*
+    raises to the power 10) and p = 4 (grad h* takes a cube root)."""
+    X, Y = workloads.gmm(seed=380, n=500, m=400, d=16, n_comp=3)
+    a, b = np.full(500, 1 / 500), np.full(400, 1 / 400)
+    C = pcost.cost_matrix_p(X, Y, p)
+    eps = float(np.float32(0.05 * C.mean()))
+    print(f"case p={p}", flush=True)
+    cl = _clouds(P, X, Y, p)
+    assert abs(cl.mean_cost / C.mean() - 1) < 1e-6
+    f, g, _ = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=10)
+    ref = oracle.sinkhorn(a, X, b, Y, eps, 0.0, n_iter=10, C=C)
+    assert pot_err(f.cpu().numpy(), ref.f, eps) < 1e-4
+    assert pot_err(g.cpu().numpy(), ref.g, eps) < 1e-4
+    g32 = g.cpu().numpy()
+    Q = workloads.gmm(seed=381, n=300, m=4, d=16, n_comp=3)[0]
+    out = P.entropic_map(cl, g, eps, P.to_device(Q), alpha=0.5)
+    assert map_err(out.cpu().numpy(), pcost.entropic_map_p(Q, Y, g32, eps, p, alpha=0.5), Y) < 1e-3

@@ -285,15 +285,33 @@ int enqueue_err_readback(const pot_clouds *c, const Layout &L, int nparts, float
 }
 
 // Alg. 1 on c->xk.  Iteration t: f_t from g_{t-1} (whose error partials are
-// the row-marginal error of iterate t-1), then g_t from f_t.  The host
-// checks the errors kLag iterations behind the work it has enqueued, so the
-// stream always holds the next iterations while the host waits on a
-// read-back; the potentials live in a ring of kLag + 1 slots, so the
-// iterate whose error is being read is still intact when it is returned.
-// Errors are checked in order and the first iterate with err <= tau is
-// returned, as in a loop that checks every iteration before going on.
-constexpr int kLag = 2;
-constexpr int kRing = kLag + 1;
+// the row-marginal error of iterate t-1), then g_t from f_t.  The host reads
+// err(t-1) back with a lag chosen from the cost of one iteration:
+//   lag 2 (cheap iterations): err(t-2) is checked after g_t is enqueued, so
+//         the stream always holds the next iterations while the host waits
+//         and no time is lost between launches;
+//   lag 1: err(t-1) is checked after g_t is enqueued (g_t runs while the
+//         host waits; one iteration past convergence is computed);
+//   lag 0 (iterations of a millisecond or more): err(t-1) is checked before
+//         g_t is enqueued, so no g-update past convergence is computed; the
+//         host's reaction time is small beside the iteration.
+// The potentials live in a ring of three slots, so the iterate whose error
+// is being read is still intact when it is returned.  Errors are checked in
+// order and the first iterate with err <= tau is returned in every mode.
+constexpr int kRing = 3;
+
+int pick_lag(const pot_clouds *c) {
+    const double nm = (double)c->n * (double)c->m;
+    double us;   // estimated time of one iteration (two potential updates)
+    if (c->cost_p != 0.f) {
+        us = 2.0 * nm * 4.0 / 5e12 * 1e6;                 // the cost matrix read twice
+    } else {
+        const double rate = c->precision == POT_PREC_FP32 ? 110e12
+                          : c->precision == POT_PREC_BF16 ? 900e12 : 400e12;
+        us = 4.0 * nm * c->d / rate * 1e6;                 // 2 n m d flops per update
+    }
+    return us < 100.0 ? 2 : us < 1000.0 ? 1 : 0;
+}
 
 struct Events {
     hipEvent_t ev[kRing] = {};
@@ -311,6 +329,7 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
     if (!host) return POT_ERR_DEVICE;
     Events E;
     for (hipEvent_t &e : E.ev) POT_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const int lag = pick_lag(c);
     LseJob fa = f_job(c, L, eps);
     LseJob ga = g_job(c, L, eps);
     // read err_k (its copy was enqueued with f_{k+1}); true when the loop ends at k
@@ -336,13 +355,14 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
         if (t > 1 && (status = enqueue_err_readback(c, L, nparts, host + (t - 1) % kRing,
                                                     E.ev[(t - 1) % kRing], s)) != POT_OK)
             return status;
+        if (lag == 0 && t > 1 && check(t - 1, &status)) return status;
         ga.vpot = fb[t % kRing];
         ga.pot_out = gb[t % kRing];
         if (pot::launch_lse_update(ga, s, nullptr) != hipSuccess) return POT_ERR_DEVICE;
-        // err_{t-kLag}: its slots are not written before iteration t + 1
-        if (t - kLag >= 1 && check(t - kLag, &status)) return status;
+        // err_{t-lag}: its slots are not written before iteration t + 1
+        if (lag > 0 && t - lag >= 1 && check(t - lag, &status)) return status;
         if (t == max_iter) {
-            for (int k = std::max(1, t - kLag + 1); k < t; ++k)
+            for (int k = std::max(1, t - lag + 1); k < t; ++k)
                 if (check(k, &status)) return status;
             // err of the last iterate: one more f-update into the free slot
             fa.vpot = gb[t % kRing]; fa.gamma = 1.f;

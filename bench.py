@@ -419,7 +419,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        log("bench.py measures one GPU only: this build has no multi-GPU path "
+        log("bench.py measures one GPU only: the library has no multi-GPU path "
             "(run with --gpus 1).")
         sys.exit(2)
 

@@ -189,3 +189,34 @@ def test_translation_invariance_gpu(P):
     assert pot_err(outs[1][0], outs[0][0], eps) < 1e-4
     assert pot_err(outs[1][1], outs[0][1], eps) < 1e-4
     assert map_err(outs[1][2], outs[0][2], Y) < 1e-4
+
+
+@pytest.mark.parametrize("K,alpha_sched,warm,weighted,taus", [
+    (1, "constant", "alpha_k", False, (1e-3, 1e-3)),
+    (3, "decelerated", "alpha_k", True, (1e-3, 1e-3)),
+    (5, "accelerated", "alpha_prev", False, (1e-2, 1e-3)),
+    (64, "constant", "alpha_k", True, (1e-3, 1e-3)),    # the largest K the ABI takes
+])
+def test_progot_variants(P, K, alpha_sched, warm, weighted, taus):
+    """Alg. 2 over the options of Sec. 4: the three alpha schedules, both
+    warm-start readings, weighted clouds, a tau schedule decreasing
+    linearly, and K from 1 to the maximum, against the oracle's Alg. 2."""
+    X, Y = workloads.gmm(seed=60 + K, n=300, m=250, d=5, n_comp=3)
+    wa, a = _weights(300, weighted, 11)
+    wb, b = _weights(250, weighted, 12)
+    print(f"case K={K} {alpha_sched} warm={warm} weighted={weighted} tau={taus}", flush=True)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y),
+                          None if wa is None else P.to_device(wa),
+                          None if wb is None else P.to_device(wb))
+    f, G, TX, info = P.progot_solve(cl, K, alpha_sched=alpha_sched, tau_first=taus[0],
+                                    tau_last=taus[1], warm_start=warm)
+    tau_sched = oracle.schedules.tau_schedule(K, taus[0], taus[1])
+    ref = oracle.progot(a, X, b, Y, K, alpha_kind=alpha_sched, tau=tau_sched, warm_start=warm)
+    print(f"  gpu iters {info.iters} oracle {ref.iters}", flush=True)
+    assert info.converged and info.K == K
+    np.testing.assert_allclose(info.alpha, ref.alpha, rtol=1e-6)
+    np.testing.assert_allclose(info.eps, ref.eps, rtol=1e-4)
+    assert all(abs(u - v) <= 2 for u, v in zip(info.iters, ref.iters))
+    assert map_err(TX.cpu().numpy(), ref.TX, Y) < 1e-3
+    chk = P.marginal_check(cl, f, G[-1], info.eps[-1])
+    assert chk[0] <= taus[1] * 1.01

@@ -241,9 +241,11 @@ POT_API int pot_diag_metrics(const pot_clouds *c, const float *f, const float *g
 /* Sinkhorn divergence (eq. sink_div) between weighted clouds X (n x d) and
  * Y (m x d), device pointers, a/b device weights or NULL (uniform):
  *   D = OT_eps(X, Y) - (OT_eps(X, X) + OT_eps(Y, Y)) / 2,
- * OT_eps the objective of eq. entdual at Alg. 1's FP32 solution to tau
- * (evaluated in FP64).  eps = 0 selects the paper's eps_D = 5 % of the mean
- * cost within Y.  out (host, 5 doubles): D, OT(X,Y), OT(X,X), OT(Y,Y), eps.
+ * OT_eps the objective of eq. entdual at Alg. 1's FP32 solution to tau,
+ * <f, a> + <g, b> - eps (the returned iterate ends with a g-update, so the
+ * coupling's mass is 1), with FP64 dot products.  eps = 0 selects the
+ * paper's eps_D = 5 % of the mean cost within Y.  out (host, 5 doubles): D,
+ * OT(X,Y), OT(X,X), OT(Y,Y), eps.
  * ws (device): pot_sinkhorn_divergence_bytes(n, m, d) bytes, reused by the
  * three solves.  POT_WARN_NOT_CONVERGED if a solve hit max_iter.  Blocks. */
 POT_API size_t pot_sinkhorn_divergence_bytes(int64_t n, int64_t m, int32_t d);

@@ -51,7 +51,7 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p) {
     L.yst = take((size_t)pot::cloud_stat_blocks(m) * (d + 1) * 8);
     L.chr = take((size_t)pot::fp64_check_blocks(n) * pot::kCheckParts * 8);
     L.chc = take((size_t)pot::fp64_check_blocks(m) * pot::kCheckParts * 8);
-    L.n64 = take(((size_t)n + (size_t)m) * 8);
+    L.n64 = take(std::max<size_t>((size_t)n + (size_t)m, 512) * 8);   // FP64 norms / partials
     // general costs: the cost matrix of (xk, Y), its block sums (+ the
     // total), and the accumulator partials of the split map kernel
     const bool pc = cost_p != 0.f;
@@ -667,9 +667,22 @@ int divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d, 
         SinkResult r;
         if ((st = sinkhorn_core(&c, L, eps, tau, max_iter, nullptr, 1.f, &r, s)) != POT_OK) return st;
         all = all && r.converged;
-        double m6[6];
-        if ((st = pot_coupling_metrics(&c, r.f, r.g, eps, m6, s)) != POT_OK) return st;
-        ot[k] = m6[2];
+        // The returned iterate ends with a g-update, so its coupling's column
+        // sums are b and its mass sum_ij P_ij is 1: the objective of eq.
+        // entdual is <f, a> + <g, b> - eps, two FP64 dot products (the FP64
+        // pass over all pairs would add only rounding of the FP32 g).
+        double *part = at<double>(&c, L.n64);   // >= 512 doubles
+        const int nbf = pot::weighted_sum_blocks(q.nu), nbg = pot::weighted_sum_blocks(q.nv);
+        POT_TRY(pot::launch_weighted_sum(r.f, q.wu, q.nu, part, s));
+        POT_TRY(pot::launch_weighted_sum(r.g, q.wv, q.nv, part + 256, s));
+        double h[512];
+        POT_TRY(hipMemcpyAsync(h, part, sizeof(double) * 512, hipMemcpyDeviceToHost, s));
+        POT_TRY(hipStreamSynchronize(s));
+        double fa = 0.0, gb = 0.0;
+        for (int b2 = 0; b2 < nbf; ++b2) fa += h[b2];
+        for (int b2 = 0; b2 < nbg; ++b2) gb += h[256 + b2];
+        ot[k] = fa + gb - (double)eps;
+        if (!std::isfinite(ot[k])) return POT_ERR_NUMERIC;
     }
     out[0] = ot[1] - 0.5 * (ot[2] + ot[0]);
     out[1] = ot[1];

@@ -20,6 +20,7 @@
 
 #include "progot_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace pot {
@@ -277,7 +278,34 @@ void rowsums(const float *U, int64_t nu, const float *V, int64_t nv, int d, cons
     else rowsums_t<256>(U, nu, V, nv, d, usq, vsq, pu, pv, w, eps, part, s);
 }
 
+// Per-block FP64 partials of sum_i v_i w_i (w == NULL: uniform 1/n).
+__global__ __launch_bounds__(256) void weighted_sum_f64(const float *__restrict__ v,
+                                                        const float *__restrict__ w, int64_t n,
+                                                        double *__restrict__ part) {
+    __shared__ double red[256];
+    double s = 0.0;
+    const double u = 1.0 / (double)n;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        s = fma((double)v[i], w ? (double)w[i] : u, s);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 }  // namespace
+
+int weighted_sum_blocks(int64_t n) { return (int)std::min<int64_t>(256, (n + 255) / 256); }
+
+hipError_t launch_weighted_sum(const float *v, const float *w, int64_t n, double *part,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(weighted_sum_f64, dim3((unsigned)weighted_sum_blocks(n)), dim3(256), 0, s, v, w,
+                       n, part);
+    return hipGetLastError();
+}
 
 int fp64_check_blocks(int64_t n) { return (int)((n + 63) / 64); }
 int diag_blocks(int64_t n) { return (int)((n + 255) / 256); }

@@ -187,6 +187,11 @@ hipError_t launch_fp64_check(const float *X, int64_t n, const float *Y, int64_t 
                              double *part_rows, double *part_cols, hipStream_t s);
 int fp64_check_blocks(int64_t n);
 constexpr int kCheckParts = 5;
+// FP64 per-block partials of sum_i v_i w_i (w NULL: uniform 1/n) into part
+// (weighted_sum_blocks(n) <= 256 doubles).
+int weighted_sum_blocks(int64_t n);
+hipError_t launch_weighted_sum(const float *v, const float *w, int64_t n, double *part,
+                               hipStream_t s);
 // Diagonal of the coupling (n == m): per-block partials (sum P_ii,
 // sum log P_ii), diag_blocks(n) blocks of 2 doubles; cost_p = 0 is the
 // squared-Euclidean cost, cost_p > 1 the cost (1/p)|.|_p^p.

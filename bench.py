@@ -340,7 +340,7 @@ def pcost_bench(args, out):
     n, d = X.shape
     m = Y.shape[0]
     log(f"bench: pcost_4i_d47: n={n} m={m} d={d} p={p} K={K} theta={theta} tau={tau}")
-    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), cost_p=p)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), cost_p=p, cost_mode=args.cost_mode)
 
     def step():
         # run to convergence, as the coupling experiment does; the last solve
@@ -370,7 +370,8 @@ def pcost_bench(args, out):
     out.update({"value": n * m * iters_total / elapsed, "unit": "n·m·iters/s", "higher_is_better": True,
                 "ms_per_step": elapsed / args.steps * 1e3, "solve_time_s": elapsed / args.steps,
                 "config": {"workload": "pcost_4i_d47", "n": n, "m": m, "d": d, "cost": "(1/p)|.|_p^p",
-                           "p": p, "K": K, "theta": theta, "tau": tau, "alpha": "constant speed"},
+                           "p": p, "K": K, "theta": theta, "tau": tau, "alpha": "constant speed",
+                           "cost_matrix": "kept" if cl.c.cmat else "on the fly"},
                 "sinkhorn_iters_per_solve": infos[-1].iters,
                 "final_marginal_l1_fp64": {"row": row, "col": col},
                 "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -410,6 +411,8 @@ def main():
     ap.add_argument("--arena-gib", type=int, default=16, help="serve: HBM budget of the server")
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--max-iter", type=int, default=100_000, help="pcost_4i_d47: per solve")
+    ap.add_argument("--cost-mode", default="auto", choices=["auto", "keep", "on_the_fly"],
+                    help="pcost_4i_d47: keep the cost matrix or form it in every update")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--cpu-iters", type=int, default=20)

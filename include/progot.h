@@ -91,8 +91,9 @@ typedef struct pot_clouds {
     void *ws;              /* workspace base (device)                           */
     size_t ws_bytes;
     float cost_p;          /* 0: h = |.|^2; p > 1: h = (1/p)|.|_p^p             */
-    float *cmat;           /* cost_p > 0: C_ij = h(xk_i - y_j), n x ldc (device) */
-    int64_t ldc;           /* row stride of cmat (m rounded up to 4)            */
+    float *cmat;           /* cost_p > 0: C_ij = h(xk_i - y_j), n x ldc (device),
+                              or NULL when the cost is formed on the fly       */
+    int64_t ldc;           /* row stride of cmat (m rounded up to 4), or 0      */
 } pot_clouds;
 
 /* Bytes of device workspace pot_prepare_clouds needs for these sizes (the
@@ -129,17 +130,25 @@ POT_API int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const f
  *   pot_coupling_metrics, pot_marginal_check, pot_diag_metrics: C in FP64 by
  *     direct differences.
  * FP32 only (there is no inner-product form to put on MFMA).  The cost
- * matrix of the current source iterate is kept in the workspace (n x ldc
- * floats, rebuilt when the iterate moves), so the workspace grows with n m.
- * Alg. 4 takes them too (pot_eps_schedule_pcost_bytes); the Sinkhorn
- * divergence has its own general-cost entry point below; the serving form
- * takes squared-Euclidean clouds only.
+ * matrix of the current source iterate is either kept in the workspace
+ * (n x ldc floats, rebuilt when the iterate moves; each potential update
+ * then reads it once) or formed on the fly in every update (d powers per
+ * pair, VALU-bound; the workspace does not grow with n m).  flags:
+ *   POT_PCOST_AUTO       keep it when it takes at most 16 GiB;
+ *   POT_PCOST_ON_THE_FLY never keep it;
+ *   POT_PCOST_KEEP       keep it (n * m <= 2^36, else POT_ERR_INVALID).
+ * Alg. 4 takes these clouds too (pot_eps_schedule_pcost_bytes); the
+ * Sinkhorn divergence has its own general-cost entry point below; the
+ * serving form takes squared-Euclidean clouds only.
  *   1 < p <= 16; p == 1.5 takes a square-root path, other p a log/exp path.
- *   Limits: n * m <= 2^36. */
-POT_API size_t pot_workspace_bytes_pcost(int64_t n, int64_t m, int32_t d, float p);
+ *   n * m <= 2^43. */
+#define POT_PCOST_AUTO 0
+#define POT_PCOST_ON_THE_FLY 1
+#define POT_PCOST_KEEP 2
+POT_API size_t pot_workspace_bytes_pcost(int64_t n, int64_t m, int32_t d, float p, int32_t flags);
 POT_API int pot_prepare_clouds_pcost(pot_clouds *c, const float *X, int64_t n, const float *Y,
                                      int64_t m, int32_t d, const float *a, const float *b, float p,
-                                     void *ws, size_t ws_bytes, void *stream);
+                                     int32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 typedef struct {
     int32_t iters;         /* full (f, g) iterations of the returned iterate     */

@@ -18,7 +18,7 @@ namespace host {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p) {
+Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p, bool keep_cost) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
@@ -55,7 +55,7 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p) {
     // general costs: the cost matrix of (xk, Y), its block sums (+ the
     // total), and the accumulator partials of the split map kernel
     const bool pc = cost_p != 0.f;
-    L.cm = take(pc ? (size_t)n * (size_t)pot::pcost_ldc(m) * 4 : 0);
+    L.cm = take(pc && keep_cost ? (size_t)n * (size_t)pot::pcost_ldc(m) * 4 : 0);
     L.cmp = take(pc ? ((size_t)pot::pcost_matrix_blocks(n, m) + 1) * 8 : 0);
     L.mpa = take(pc ? (size_t)pot::pcost_map_max_split() * n * pot::pcost_pad_dim(d) * 4 : 0);
     L.total = off;
@@ -63,6 +63,20 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p) {
 }
 
 bool valid_cost_p(float p) { return p == 0.f || (std::isfinite(p) && p > 1.f && p <= 16.f); }
+
+int pcost_keep(int64_t n, int64_t m, int32_t flags) {
+    const double entries = (double)n * (double)pot::pcost_ldc(m);
+    switch (flags) {
+        case POT_PCOST_AUTO: return entries <= (double)(int64_t(1) << 32) ? 1 : 0;
+        case POT_PCOST_ON_THE_FLY: return 0;
+        case POT_PCOST_KEEP: return entries <= (double)(int64_t(1) << 36) ? 1 : -1;
+        default: return -1;
+    }
+}
+
+Layout plan_of(const pot_clouds *c) {
+    return plan(c->n, c->m, c->d, c->precision, c->cost_p, c->cmat != nullptr);
+}
 
 bool valid_sizes(int64_t n, int64_t m, int32_t d, int32_t precision) {
     return n >= 1 && m >= 1 && d >= 1 && d <= POT_MAX_D &&
@@ -75,9 +89,11 @@ bool valid_clouds(const pot_clouds *c) {
     if (!c || !c->ws || !c->X || !c->Y || !c->xk) return false;
     if (!valid_sizes(c->n, c->m, c->d, c->precision) || !valid_cost_p(c->cost_p)) return false;
     if (c->precision != POT_PREC_FP32 && (!c->x_lp || !c->y_lp || !c->yt_lp)) return false;
-    if (c->cost_p != 0.f && (c->precision != POT_PREC_FP32 || !c->cmat || c->ldc != pot::pcost_ldc(c->m)))
+    if (c->cost_p != 0.f &&
+        (c->precision != POT_PREC_FP32 ||
+         (c->cmat ? c->ldc != pot::pcost_ldc(c->m) : c->ldc != 0)))
         return false;
-    return c->ws_bytes >= plan(c->n, c->m, c->d, c->precision, c->cost_p).total;
+    return c->ws_bytes >= plan_of(c).total;
 }
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
@@ -88,7 +104,7 @@ double now_s() {
 
 void bind_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
                  const float *a, const float *b, int32_t precision, void *ws, size_t ws_bytes,
-                 const Layout &L, float cost_p) {
+                 const Layout &L, float cost_p, bool keep_cost) {
     std::memset(c, 0, sizeof(*c));
     c->n = n; c->m = m; c->d = d; c->precision = precision;
     c->X = X; c->Y = Y; c->a = a; c->b = b; c->ws = ws; c->ws_bytes = ws_bytes;
@@ -101,8 +117,8 @@ void bind_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64
     c->y_lp = precision != POT_PREC_FP32 ? at<void>(c, L.ylp) : nullptr;
     c->yt_lp = precision != POT_PREC_FP32 ? at<void>(c, L.ytl) : nullptr;
     c->cost_p = cost_p;
-    c->cmat = cost_p != 0.f ? at<float>(c, L.cm) : nullptr;
-    c->ldc = cost_p != 0.f ? pot::pcost_ldc(m) : 0;
+    c->cmat = cost_p != 0.f && keep_cost ? at<float>(c, L.cm) : nullptr;
+    c->ldc = c->cmat ? pot::pcost_ldc(m) : 0;
 }
 
 int refresh_pcost(pot_clouds *c, const Layout &L, hipStream_t s) {
@@ -152,7 +168,7 @@ LseJob f_job(const pot_clouds *c, const Layout &L, float eps) {
     a.V = c->Y; a.V_lp = c->y_lp; a.nv = c->m; a.vsq = c->y_sqn;
     a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
     a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = at<float>(c, L.errp);
-    if (c->cost_p != 0.f) { a.cmat = c->cmat; a.ldc = c->ldc; a.cmat_cols = 0; a.usq = nullptr; }
+    if (c->cost_p != 0.f) { a.cost_p = c->cost_p; a.cmat = c->cmat; a.ldc = c->ldc; a.cmat_cols = 0; a.usq = nullptr; }
     return a;
 }
 
@@ -162,7 +178,7 @@ LseJob g_job(const pot_clouds *c, const Layout &L, float eps) {
     a.V = c->xk; a.V_lp = c->x_lp; a.nv = c->n; a.vsq = c->x_sqn;
     a.eps = eps; a.d = c->d; a.precision = c->precision; a.gamma = 1.f;
     a.part_m = at<float>(c, L.pm); a.part_s = at<float>(c, L.ps); a.err_part = nullptr;
-    if (c->cost_p != 0.f) { a.cmat = c->cmat; a.ldc = c->ldc; a.cmat_cols = 1; a.usq = nullptr; }
+    if (c->cost_p != 0.f) { a.cost_p = c->cost_p; a.cmat = c->cmat; a.ldc = c->ldc; a.cmat_cols = 1; a.usq = nullptr; }
     return a;
 }
 
@@ -213,7 +229,7 @@ int step_values(const pot_progot_params *p, const float *alpha, int k, double me
 int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
             float alpha, float *Xout, hipStream_t s) {
     if (c->cost_p != 0.f) {
-        const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
+        const Layout L = plan_of(c);
         pot::PcostMapArgs a{};
         a.Xq = Xq; a.nq = nq; a.Y = c->Y; a.m = c->m; a.g = g;
         a.eps = eps; a.alpha = alpha; a.p = c->cost_p; a.d = c->d; a.Xout = Xout;
@@ -443,13 +459,13 @@ int check_weights(const float *a, int64_t n, const float *b, int64_t m, hipStrea
 }
 
 int prepare(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
-            const float *a, const float *b, int32_t precision, float cost_p, void *ws,
+            const float *a, const float *b, int32_t precision, float cost_p, bool keep, void *ws,
             size_t ws_bytes, hipStream_t s) {
-    const Layout L = plan(n, m, d, precision, cost_p);
+    const Layout L = plan(n, m, d, precision, cost_p, keep);
     if (ws_bytes < L.total) return POT_ERR_NOMEM;
     int st = check_weights(a, n, b, m, s);
     if (st != POT_OK) return st;
-    bind_clouds(c, X, n, Y, m, d, a, b, precision, ws, ws_bytes, L, cost_p);
+    bind_clouds(c, X, n, Y, m, d, a, b, precision, ws, ws_bytes, L, cost_p, keep);
     std::vector<double> host(moments_len(d));
     if ((st = enqueue_prepare(c, L, host.data(), s)) != POT_OK) return st;
     POT_TRY(hipStreamSynchronize(s));
@@ -457,9 +473,9 @@ int prepare(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
     return cost_p != 0.f ? refresh_pcost(c, L, s) : POT_OK;
 }
 
-bool valid_pcost_sizes(int64_t n, int64_t m, int32_t d, float p) {
+bool valid_pcost_sizes(int64_t n, int64_t m, int32_t d, float p, int32_t flags) {
     return p != 0.f && valid_cost_p(p) && valid_sizes(n, m, d, POT_PREC_FP32) &&
-           (double)n * (double)pot::pcost_ldc(m) <= (double)(int64_t(1) << 36);
+           pcost_keep(n, m, flags) >= 0 && pot::pcost_matrix_blocks(n, m) <= 0x7fffffff;
 }
 
 }  // namespace
@@ -470,21 +486,21 @@ int pot_prepare_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y,
                        int32_t d, const float *a, const float *b, int32_t precision, void *ws,
                        size_t ws_bytes, void *stream) {
     if (!c || !X || !Y || !ws || !valid_sizes(n, m, d, precision)) return POT_ERR_INVALID;
-    return prepare(c, X, n, Y, m, d, a, b, precision, 0.f, ws, ws_bytes,
+    return prepare(c, X, n, Y, m, d, a, b, precision, 0.f, true, ws, ws_bytes,
                    static_cast<hipStream_t>(stream));
 }
 
-size_t pot_workspace_bytes_pcost(int64_t n, int64_t m, int32_t d, float p) {
-    if (!valid_pcost_sizes(n, m, d, p)) return 0;
-    return plan(n, m, d, POT_PREC_FP32, p).total;
+size_t pot_workspace_bytes_pcost(int64_t n, int64_t m, int32_t d, float p, int32_t flags) {
+    if (!valid_pcost_sizes(n, m, d, p, flags)) return 0;
+    return plan(n, m, d, POT_PREC_FP32, p, pcost_keep(n, m, flags) == 1).total;
 }
 
 int pot_prepare_clouds_pcost(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
-                             int32_t d, const float *a, const float *b, float p, void *ws,
-                             size_t ws_bytes, void *stream) {
-    if (!c || !X || !Y || !ws || !valid_pcost_sizes(n, m, d, p)) return POT_ERR_INVALID;
-    return prepare(c, X, n, Y, m, d, a, b, POT_PREC_FP32, p, ws, ws_bytes,
-                   static_cast<hipStream_t>(stream));
+                             int32_t d, const float *a, const float *b, float p, int32_t flags,
+                             void *ws, size_t ws_bytes, void *stream) {
+    if (!c || !X || !Y || !ws || !valid_pcost_sizes(n, m, d, p, flags)) return POT_ERR_INVALID;
+    return prepare(c, X, n, Y, m, d, a, b, POT_PREC_FP32, p, pcost_keep(n, m, flags) == 1, ws,
+                   ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 int pot_sinkhorn_solve(pot_clouds *c, float eps, float tau, int32_t max_iter, const float *f_init,
@@ -496,7 +512,7 @@ int pot_sinkhorn_solve(pot_clouds *c, float eps, float tau, int32_t max_iter, co
         return POT_ERR_INVALID;
     const double t0 = now_s();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
+    const Layout L = plan_of(c);
     SinkResult r;
     int st = sinkhorn_core(c, L, eps, tau, max_iter, g_init, 1.f, &r, s);
     if (st != POT_OK) return st;
@@ -524,7 +540,7 @@ int pot_progot_solve(pot_clouds *c, const pot_progot_params *p, float *f, float 
     if (!valid_clouds(c) || !valid_params(p) || !f || !G) return POT_ERR_INVALID;
     const double t0 = now_s();
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
+    const Layout L = plan_of(c);
     const int K = p->K;
     const int64_t n = c->n, m = c->m;
     float alpha[POT_MAX_K];
@@ -590,7 +606,7 @@ int pot_coupling_metrics(const pot_clouds *c, const float *f, const float *g, fl
                          double *out, void *stream) {
     if (!valid_clouds(c) || !f || !g || !out || !finite_pos(eps)) return POT_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
+    const Layout L = plan_of(c);
     const int nbr = pot::fp64_check_blocks(c->n), nbc = pot::fp64_check_blocks(c->m);
     constexpr int Q = pot::kCheckParts;
     if (c->cost_p != 0.f)
@@ -636,10 +652,13 @@ size_t pot_sinkhorn_divergence_bytes(int64_t n, int64_t m, int32_t d) {
 }
 
 size_t pot_sinkhorn_divergence_pcost_bytes(int64_t n, int64_t m, int32_t d, float p) {
-    if (!valid_pcost_sizes(n, m, d, p) || !valid_pcost_sizes(n, n, d, p) || !valid_pcost_sizes(m, m, d, p))
+    const int32_t A = POT_PCOST_AUTO;
+    if (!valid_pcost_sizes(n, m, d, p, A) || !valid_pcost_sizes(n, n, d, p, A) ||
+        !valid_pcost_sizes(m, m, d, p, A))
         return 0;
-    return std::max({plan(n, m, d, POT_PREC_FP32, p).total, plan(n, n, d, POT_PREC_FP32, p).total,
-                     plan(m, m, d, POT_PREC_FP32, p).total});
+    return std::max({plan(n, m, d, POT_PREC_FP32, p, pcost_keep(n, m, A) == 1).total,
+                     plan(n, n, d, POT_PREC_FP32, p, pcost_keep(n, n, A) == 1).total,
+                     plan(m, m, d, POT_PREC_FP32, p, pcost_keep(m, m, A) == 1).total});
 }
 
 }  // extern "C"
@@ -658,9 +677,11 @@ int divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d, 
     bool all = true;
     for (int k = 0; k < 3; ++k) {
         const Pair &q = pairs[k];
-        const Layout L = plan(q.nu, q.nv, d, POT_PREC_FP32, cost_p);
+        const bool keep = cost_p == 0.f || pcost_keep(q.nu, q.nv, POT_PCOST_AUTO) == 1;
+        const Layout L = plan(q.nu, q.nv, d, POT_PREC_FP32, cost_p, keep);
         pot_clouds c;
-        int st = prepare(&c, q.U, q.nu, q.V, q.nv, d, q.wu, q.wv, POT_PREC_FP32, cost_p, ws, L.total, s);
+        int st = prepare(&c, q.U, q.nu, q.V, q.nv, d, q.wu, q.wv, POT_PREC_FP32, cost_p, keep, ws, L.total,
+                         s);
         if (st != POT_OK) return st;
         if (k == 0 && eps == 0.f) eps = (float)(0.05 * c.mean_cost);
         if (!finite_pos(eps)) return POT_ERR_NUMERIC;
@@ -725,7 +746,7 @@ int pot_diag_metrics(const pot_clouds *c, const float *f, const float *g, float 
     if (!valid_clouds(c) || !f || !g || !out || !finite_pos(eps) || c->n != c->m)
         return POT_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout L = plan(c->n, c->m, c->d, c->precision, c->cost_p);
+    const Layout L = plan_of(c);
     // the FP64 norm region holds n + m >= 2 diag_blocks(n) doubles
     double *part = at<double>(c, L.n64);
     const int nb = pot::diag_blocks(c->n);

@@ -21,9 +21,16 @@ struct Layout {
     size_t total;
 };
 
-// cost_p = 0: squared-Euclidean cost; cost_p > 1: (1/p)|.|_p^p (FP32).
-Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p = 0.f);
+// cost_p = 0: squared-Euclidean cost; cost_p > 1: (1/p)|.|_p^p (FP32),
+// keeping its n x m matrix in the workspace when keep_cost is set.
+Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p = 0.f,
+            bool keep_cost = true);
 bool valid_cost_p(float p);
+// General costs: keep the cost matrix (flags 2), never (flags 1), or when
+// it takes at most 16 GiB (flags 0).  Returns -1 for invalid flags.
+int pcost_keep(int64_t n, int64_t m, int32_t flags);
+// plan() of prepared clouds (their cost and whether they keep its matrix).
+Layout plan_of(const pot_clouds *c);
 
 template <typename T> T *at(const pot_clouds *c, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(c->ws) + off);
@@ -37,9 +44,10 @@ double now_s();
 // Fill the views of c over the workspace (no device work).
 void bind_clouds(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
                  const float *a, const float *b, int32_t precision, void *ws, size_t ws_bytes,
-                 const Layout &L, float cost_p = 0.f);
-// General costs: rebuild the cost matrix of the current source iterate and
-// set c->mean_cost from its sum (blocks until the sum is on the host).
+                 const Layout &L, float cost_p = 0.f, bool keep_cost = true);
+// General costs: rebuild the cost matrix of the current source iterate (if
+// kept) and set c->mean_cost from its sum (blocks until the sum is on the
+// host).
 int refresh_pcost(pot_clouds *c, const Layout &L, hipStream_t s);
 
 // Number of doubles of a moments read-back: (sum_i x_i, sum |x|^2) for the

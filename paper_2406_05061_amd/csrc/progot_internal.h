@@ -58,11 +58,13 @@ struct LseJob {
     int iter;
     int max_iter;
     float tau;
-    // general costs h = (1/p)|.|_p^p: the cost matrix of the pair (n x ldc,
-    // row-major, rows = source points).  When set, usq is NULL and the
-    // update reads C instead of computing the cost: the f-update reduces
-    // rows of C (cmat_cols = 0), the g-update columns (cmat_cols = 1); cps
-    // then counts columns (rows) of C per split.
+    // general costs h = (1/p)|.|_p^p (cost_p = p; 0 for the squared-Euclidean
+    // cost): usq is NULL.  With the pair's cost matrix (n x ldc, row-major,
+    // rows = source points) the update reads C: the f-update reduces rows of
+    // C (cmat_cols = 0), the g-update columns (cmat_cols = 1), and cps counts
+    // columns (rows) of C per split.  Without it (cmat NULL) the update forms
+    // h(u_i - v_j) on the fly from U and V.
+    float cost_p;
     const float *cmat;
     int64_t ldc;
     int cmat_cols;
@@ -126,14 +128,15 @@ int pcost_pad_dim(int d);                 // padded dimension of the map kernel
 int64_t pcost_ldc(int64_t m);             // row stride of the cost matrix (m rounded up to 4)
 int64_t pcost_matrix_blocks(int64_t n, int64_t m);
 int pcost_map_max_split();
-// C_ij = h(x_i - y_j) for all pairs, and sum_ij C_ij (FP64) into *sum_out;
-// part holds pcost_matrix_blocks(n, m) doubles.
+// C_ij = h(x_i - y_j) for all pairs into Cm (Cm NULL: not stored), and
+// sum_ij C_ij (FP64) into *sum_out; part holds pcost_matrix_blocks(n, m)
+// doubles.
 hipError_t launch_pcost_matrix(const float *X, int64_t n, const float *Y, int64_t m, int d, float p,
                                float *Cm, int64_t ldc, double *part, double *sum_out,
                                hipStream_t s);
 void plan_pcost_job(LseJob &j);
-// The row update with one split writes the potential and the error partials
-// itself (no merge launch; mblocks error partials).
+// The row update over the cost matrix with one split writes the potential
+// and the error partials itself (no merge launch; mblocks error partials).
 bool pcost_fused(const LseJob &j);
 hipError_t launch_pcost_partial(const LseJob &j, hipStream_t s);   // planned job
 hipError_t launch_pcost_merge(const LseJob &j, hipStream_t s);     // planned, not fused

@@ -659,10 +659,10 @@ void plan_lse_job(LseJob &j) {
 
 hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
     LseJob j = a;
-    if (j.cmat) plan_pcost_job(j);
+    if (j.cost_p != 0.f) plan_pcost_job(j);
     else plan_lse_job(j);
     hipError_t e;
-    if (j.cmat) {
+    if (j.cost_p != 0.f) {
         e = launch_pcost_partial(j, s);
     } else if (j.precision != 0) {
         e = launch_lse_partial_bf16(j, s);
@@ -674,7 +674,7 @@ hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
         default: e = lse_launch_t<256, lse_qb(256)>(j, s); break;
     }
     if (e != hipSuccess) return e;
-    if (j.cmat) {
+    if (j.cost_p != 0.f) {
         if (!pcost_fused(j) && (e = launch_pcost_merge(j, s)) != hipSuccess) return e;
         if (n_err_part) *n_err_part = j.pot_old ? (int)j.mblocks : 0;
         return hipGetLastError();
@@ -691,7 +691,7 @@ hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, fl
     int nerr = 0;
     const int D = padded_dim(jobs[0].d);
     for (int k = 0; k < njobs; ++k) {
-        if (jobs[k].cmat) return hipErrorInvalidValue;
+        if (jobs[k].cost_p != 0.f) return hipErrorInvalidValue;
         plan_lse_job(jobs[k]);
         if (jobs[k].precision != 0 || padded_dim(jobs[k].d) != D) return hipErrorInvalidValue;
         jobs[k].blk_begin = blk;

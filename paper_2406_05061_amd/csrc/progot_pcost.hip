@@ -70,7 +70,7 @@ constexpr int kCT = 64;        // tile rows and columns
 constexpr int kCK = 32;        // features per LDS slice
 constexpr int kCS = kCT + 4;   // LDS stride of a transposed slice (16-byte aligned)
 
-template <int PK>
+template <int PK, bool STORE>
 __global__ __launch_bounds__(256) void pcost_matrix(const float *__restrict__ X, int64_t n,
                                                     const float *__restrict__ Y, int64_t m, int d,
                                                     float pm1, float inv_p, int64_t col_tiles,
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void pcost_matrix(const float *__restrict__ X,
             for (int b = 0; b < 4; ++b)
                 if (cc + b < m) s += (double)v[b];
             // ldc is a multiple of 4, so the 4 columns are inside the row
-            if (cc < ldc) *reinterpret_cast<f4 *>(Cm + r * ldc + cc) = v;
+            if (STORE && cc < ldc) *reinterpret_cast<f4 *>(Cm + r * ldc + cc) = v;
         }
     }
     red[tid] = s;
@@ -347,6 +347,10 @@ __global__ __launch_bounds__(64 * kColWaves) void pcost_lse_cols(LseJob J) {
 
 // ---------------------------------------------------------------- map
 constexpr int kMapTJ = 32;      // targets per LDS tile
+
+int pmap_dim(int d) {
+    return d <= 16 ? 16 : d <= 32 ? 32 : d <= 48 ? 48 : d <= 64 ? 64 : d <= 128 ? 128 : 256;
+}
 constexpr int kMapMaxSplit = 16;
 
 template <int D> struct PShape {
@@ -477,9 +481,95 @@ __global__ __launch_bounds__(256) void pcost_map_merge(PcostMapArgs A, int S, in
     A.Xout[q * d + k] = x - A.alpha * grad_h_star<PK>(a / tot, 1.f / (A.p - 1.f));
 }
 
-int pmap_dim(int d) {
-    return d <= 16 ? 16 : d <= 32 ? 32 : d <= 48 ? 48 : d <= 64 ? 64 : d <= 128 ? 128 : 256;
+// Potential update without the cost matrix (pairs too many to keep it):
+// row i of U against the split's columns of V, the cost h(u_i - v_j) formed
+// on the fly as in the map kernel (LQ lanes per row, column tiles of 32 in
+// LDS), t_ij = (gamma vpot_j - h)/eps in log2 units, running (max, sum);
+// writes the split partials that pcost_merge folds.
+template <int D, int PK>
+__global__ __launch_bounds__(256) void pcost_lse_fly(LseJob J, int64_t tps) {
+    using P = PShape<D>;
+    constexpr int F = P::F, LQ = P::LQ, QB = P::QB, SEG = P::SEG, RS = P::RS;
+    __shared__ __align__(16) float vt[kMapTJ * RS];
+    __shared__ float gt[kMapTJ];
+    const int tid = threadIdx.x, lq = tid % LQ;
+    const int d = J.d;
+    const int S = J.S;
+    const int split = (int)(blockIdx.x % S);
+    const int64_t row = (int64_t)(blockIdx.x / S) * QB + tid / LQ;
+    const bool live = row < J.nu;
+    const int f0 = lq * F;
+    float x[F];
+#pragma unroll
+    for (int k = 0; k < F; ++k) x[k] = (live && f0 + k < d) ? J.U[row * d + f0 + k] : 0.f;
+    const float k2 = J.bscale;                 // log2(e)/eps
+    const float kc = k2 / J.cost_p;            // h = c/p
+    const float gk = J.gamma * k2;
+    const float pm1 = J.cost_p - 1.f;
+    float M = kNegBig, sum = 0.f;
+    const int64_t j_lo = (int64_t)split * tps;
+    const int64_t j_hi = std::min(J.nv, j_lo + tps);
+    for (int64_t j0 = j_lo; j0 < j_hi; j0 += kMapTJ) {
+        const int64_t nt = std::min<int64_t>(kMapTJ, j_hi - j0);
+        __syncthreads();   // the previous tile is consumed
+        for (int e = tid; e < kMapTJ * D; e += 256) {
+            const int jj = e / D, kk = e % D;
+            vt[jj * RS + (kk / F) * SEG + kk % F] = (jj < nt && kk < d) ? J.V[(j0 + jj) * d + kk] : 0.f;
+        }
+        if (tid < kMapTJ)
+            gt[tid] = tid < nt ? (J.vpot ? J.vpot[j0 + tid] * gk : 0.f) : -INFINITY;
+        __syncthreads();
+        for (int jj = 0; jj < kMapTJ; ++jj) {
+            const float *vj = vt + jj * RS + lq * SEG;
+            float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+#pragma unroll
+            for (int k = 0; k < F; k += 4) {
+                const f4 vv = *reinterpret_cast<const f4 *>(vj + k);
+                float cp[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float a = fabsf(x[k + e] - vv[e]);
+                    cp[e] = a * pow_pm1<PK>(a, pm1);
+                }
+                c0 += cp[0]; c1 += cp[1]; c2 += cp[2]; c3 += cp[3];
+            }
+            const float c = group_sum<LQ>((c0 + c1) + (c2 + c3));
+            const float t = fmaf(-c, kc, gt[jj]);
+            if (__builtin_amdgcn_ballot_w64(t > M)) {
+                const float Mn = fmaxf(M, t);
+                sum *= ex2(M - Mn);
+                M = Mn;
+            }
+            sum += ex2(t - M);
+        }
+    }
+    if (live && lq == 0) {
+        J.part_m[(int64_t)split * J.nu + row] = M;
+        J.part_s[(int64_t)split * J.nu + row] = sum;
+    }
 }
+
+template <int D, int PK>
+hipError_t fly_launch_t(const LseJob &j, hipStream_t s) {
+    constexpr int QB = PShape<D>::QB;
+    const int64_t qb = (j.nu + QB - 1) / QB;
+    if (qb * j.S > 0x7fffffff) return hipErrorInvalidValue;
+    timed_launch(0, pcost_lse_fly<D, PK>, dim3((unsigned)(qb * j.S)), dim3(256), 0, s, j, j.cps);
+    return hipGetLastError();
+}
+
+template <int PK>
+hipError_t fly_launch_pk(const LseJob &j, hipStream_t s) {
+    switch (pmap_dim(j.d)) {
+        case 16: return fly_launch_t<16, PK>(j, s);
+        case 32: return fly_launch_t<32, PK>(j, s);
+        case 48: return fly_launch_t<48, PK>(j, s);
+        case 64: return fly_launch_t<64, PK>(j, s);
+        case 128: return fly_launch_t<128, PK>(j, s);
+        default: return fly_launch_t<256, PK>(j, s);
+    }
+}
+
 
 template <int D, int PK>
 hipError_t pmap_launch_t(const PcostMapArgs &a, hipStream_t s) {
@@ -540,13 +630,17 @@ hipError_t launch_pcost_matrix(const float *X, int64_t n, const float *Y, int64_
                                hipStream_t s) {
     const int64_t col_tiles = (m + kCT - 1) / kCT;
     const int64_t blocks = pcost_matrix_blocks(n, m);
-    if (blocks > 0x7fffffff || ldc < m || ldc % 4) return hipErrorInvalidValue;
-    if (is_p15(p))
-        hipLaunchKernelGGL((pcost_matrix<1>), dim3((unsigned)blocks), dim3(256), 0, s, X, n, Y, m, d,
-                           p - 1.f, 1.f / p, col_tiles, Cm, ldc, part);
-    else
-        hipLaunchKernelGGL((pcost_matrix<0>), dim3((unsigned)blocks), dim3(256), 0, s, X, n, Y, m, d,
-                           p - 1.f, 1.f / p, col_tiles, Cm, ldc, part);
+    if (blocks > 0x7fffffff || (Cm && (ldc < m || ldc % 4))) return hipErrorInvalidValue;
+    // Cm == NULL: only the FP64 sum (the matrix is formed on the fly later)
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(256), 0, s, X, n, Y, m, d, p - 1.f,
+                           1.f / p, col_tiles, Cm, ldc, part);
+    };
+    if (is_p15(p)) {
+        if (Cm) go(pcost_matrix<1, true>); else go(pcost_matrix<1, false>);
+    } else {
+        if (Cm) go(pcost_matrix<0, true>); else go(pcost_matrix<0, false>);
+    }
     hipLaunchKernelGGL(sum_f64, dim3(1), dim3(256), 0, s, part, blocks, sum_out);
     return hipGetLastError();
 }
@@ -555,6 +649,22 @@ void plan_pcost_job(LseJob &j) {
     j.scale2 = 0.f;
     j.bscale = kLog2e / j.eps;
     int64_t tiles, S, per;
+    if (!j.cmat) {
+        // on the fly: QB rows per workgroup, columns split so that the grid
+        // holds >= 1024 workgroups, in whole tiles of kMapTJ columns
+        const int QBr = 256 / (pmap_dim(j.d) <= 48 ? 1 : pmap_dim(j.d) / 32);
+        tiles = (j.nu + QBr - 1) / QBr;
+        S = 1;
+        while (S * tiles < 1024 && S < kMaxSplit) S <<= 1;
+        per = (j.nv + S - 1) / S;
+        per = std::max<int64_t>(2 * kMapTJ, (per + kMapTJ - 1) / kMapTJ * kMapTJ);
+        S = (j.nv + per - 1) / per;
+        j.S = (int)S;
+        j.cps = per;
+        j.blocks = tiles * S;
+        j.mblocks = (j.nu + 3) / 4;
+        return;
+    }
     if (!j.cmat_cols) {
         // rows of C: 4 rows (one per wave) per workgroup, >= 256 columns per split
         tiles = (j.nu + 3) / 4;
@@ -583,7 +693,7 @@ void plan_pcost_job(LseJob &j) {
     j.mblocks = (!j.cmat_cols && S == 1) ? tiles : (j.nu + 3) / 4;
 }
 
-bool pcost_fused(const LseJob &j) { return !j.cmat_cols && j.S == 1; }
+bool pcost_fused(const LseJob &j) { return j.cmat && !j.cmat_cols && j.S == 1; }
 
 hipError_t launch_pcost_merge(const LseJob &j, hipStream_t s) {
     hipLaunchKernelGGL(pcost_merge, dim3((unsigned)j.mblocks), dim3(256), 0, s, j);
@@ -591,7 +701,8 @@ hipError_t launch_pcost_merge(const LseJob &j, hipStream_t s) {
 }
 
 hipError_t launch_pcost_partial(const LseJob &j, hipStream_t s) {
-    if (j.blocks > 0x7fffffff || !j.cmat || j.ldc % 4) return hipErrorInvalidValue;
+    if (!j.cmat) return is_p15(j.cost_p) ? fly_launch_pk<1>(j, s) : fly_launch_pk<0>(j, s);
+    if (j.blocks > 0x7fffffff || j.ldc % 4) return hipErrorInvalidValue;
     if (pcost_fused(j))
         timed_launch(0, pcost_lse_rows<true>, dim3((unsigned)j.blocks), dim3(256), 0, s, j);
     else if (!j.cmat_cols)

@@ -110,7 +110,7 @@ struct PSchedLayout {
 
 PSchedLayout psched_plan(int64_t m, int64_t mt, int32_t d, float p) {
     PSchedLayout S{};
-    S.cy = plan(m, m, d, POT_PREC_FP32, p);
+    S.cy = plan(m, m, d, POT_PREC_FP32, p, pcost_keep(m, m, POT_PCOST_AUTO) == 1);
     size_t off = a256(S.cy.total);
     S.ty = off;
     off = a256(off + (size_t)mt * d * 4);
@@ -121,7 +121,7 @@ PSchedLayout psched_plan(int64_t m, int64_t mt, int32_t d, float p) {
 
 bool valid_pcost_pair(int64_t m, int32_t d, float p) {
     return p != 0.f && valid_cost_p(p) && valid_sizes(m, m, d, POT_PREC_FP32) &&
-           (double)m * (double)pot::pcost_ldc(m) <= (double)(int64_t(1) << 36);
+           pot::pcost_matrix_blocks(m, m) <= 0x7fffffff;
 }
 
 // Hold-out score err_p = sum |y~ - T_p(y~)|^2 of one grid solve (FP64 sum).
@@ -174,7 +174,8 @@ int schedule_pcost(const pot_clouds *c, const float *Y_test, int64_t mt, int32_t
     if (ws_bytes < S.total) return POT_ERR_NOMEM;
     char *base = static_cast<char *>(ws);
     pot_clouds cy;
-    bind_clouds(&cy, c->Y, m, c->Y, m, d, c->b, c->b, POT_PREC_FP32, ws, S.cy.total, S.cy, c->cost_p);
+    bind_clouds(&cy, c->Y, m, c->Y, m, d, c->b, c->b, POT_PREC_FP32, ws, S.cy.total, S.cy, c->cost_p,
+                pcost_keep(m, m, POT_PCOST_AUTO) == 1);
     std::vector<double> mom(moments_len(d));
     int st = enqueue_prepare(&cy, S.cy, mom.data(), s);
     if (st != POT_OK) return st;

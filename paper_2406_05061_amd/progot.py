@@ -80,9 +80,9 @@ _SIGS = {
     "pot_workspace_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32]),
     "pot_prepare_clouds": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _vp, _i64, _i32, _vp, _vp,
                                      _i32, _vp, C.c_size_t, _vp]),
-    "pot_workspace_bytes_pcost": (C.c_size_t, [_i64, _i64, _i32, _f32]),
+    "pot_workspace_bytes_pcost": (C.c_size_t, [_i64, _i64, _i32, _f32, _i32]),
     "pot_prepare_clouds_pcost": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _vp, _i64, _i32, _vp,
-                                           _vp, _f32, _vp, C.c_size_t, _vp]),
+                                           _vp, _f32, _i32, _vp, C.c_size_t, _vp]),
     "pot_sinkhorn_solve": (C.c_int, [C.POINTER(pot_clouds), _f32, _f32, _i32, _vp, _vp, _vp, _vp,
                                      C.POINTER(pot_sinkhorn_info), _vp]),
     "pot_entropic_map": (C.c_int, [C.POINTER(pot_clouds), _vp, _f32, _vp, _i64, _f32, _vp, _vp]),
@@ -153,11 +153,15 @@ def version() -> str:
     return lib().pot_version().decode()
 
 
-def workspace_bytes(n: int, m: int, d: int, precision: str = "fp32", cost_p: float = 0.0) -> int:
+PCOST_MODE = {"auto": 0, "on_the_fly": 1, "keep": 2}
+
+
+def workspace_bytes(n: int, m: int, d: int, precision: str = "fp32", cost_p: float = 0.0,
+                    cost_mode: str = "auto") -> int:
     if cost_p:
         if precision != "fp32":
             return 0
-        return int(lib().pot_workspace_bytes_pcost(n, m, d, float(cost_p)))
+        return int(lib().pot_workspace_bytes_pcost(n, m, d, float(cost_p), PCOST_MODE[cost_mode]))
     return int(lib().pot_workspace_bytes(n, m, d, PREC[precision]))
 
 
@@ -195,9 +199,12 @@ class Clouds:
     """A prepared pair of clouds: inputs, workspace and the pot_clouds POD.
     Keeps references to every tensor the library points into.  cost_p = 0
     selects the squared-Euclidean cost; cost_p > 1 the cost
-    h(z) = (1/p) sum_k |z_k|^p (FP32 only)."""
+    h(z) = (1/p) sum_k |z_k|^p (FP32 only), whose matrix is kept in the
+    workspace or formed on the fly per cost_mode ("auto", "keep",
+    "on_the_fly")."""
 
-    def __init__(self, X, Y, a=None, b=None, precision: str = "fp32", cost_p: float = 0.0):
+    def __init__(self, X, Y, a=None, b=None, precision: str = "fp32", cost_p: float = 0.0,
+                 cost_mode: str = "auto"):
         torch = _torch()
         _dev_f32(X, "X")
         _dev_f32(Y, "Y")
@@ -209,7 +216,7 @@ class Clouds:
             _dev_f32(a, "a", (n,))
         if b is not None:
             _dev_f32(b, "b", (m,))
-        nbytes = workspace_bytes(n, m, d, precision, cost_p)
+        nbytes = workspace_bytes(n, m, d, precision, cost_p, cost_mode)
         if nbytes == 0:
             raise PotError(POT_ERR_INVALID, "workspace_bytes")
         self.X, self.Y, self.a, self.b = X, Y, a, b
@@ -219,8 +226,9 @@ class Clouds:
         self.cost_p = float(cost_p)
         if cost_p:
             _check(lib().pot_prepare_clouds_pcost(C.byref(self.c), _ptr(X), n, _ptr(Y), m, d,
-                                                  _ptr(a), _ptr(b), float(cost_p), _ptr(self.ws),
-                                                  nbytes, C.c_void_p(_stream())),
+                                                  _ptr(a), _ptr(b), float(cost_p),
+                                                  PCOST_MODE[cost_mode], _ptr(self.ws), nbytes,
+                                                  C.c_void_p(_stream())),
                    "prepare_clouds_pcost", False)
         else:
             _check(lib().pot_prepare_clouds(C.byref(self.c), _ptr(X), n, _ptr(Y), m, d, _ptr(a),
@@ -234,8 +242,8 @@ class Clouds:
     def cost_matrix(self):
         """General costs: a copy of the resident cost matrix C_ij = h(x_i - y_j)
         of the current source iterate (n x m)."""
-        if not self.cost_p:
-            raise ValueError("the squared-Euclidean cost is never materialised")
+        if not self.cost_p or not self.c.cmat:
+            raise ValueError("these clouds do not keep their cost matrix")
         torch = _torch()
         off = self.c.cmat - self.ws.data_ptr()
         ldc = int(self.c.ldc)
@@ -251,8 +259,9 @@ class Clouds:
         return self.ws[off:off + nbytes].view(torch.float32).view(self.n, self.d).clone()
 
 
-def prepare_clouds(X, Y, a=None, b=None, precision: str = "fp32", cost_p: float = 0.0) -> Clouds:
-    return Clouds(X, Y, a, b, precision, cost_p)
+def prepare_clouds(X, Y, a=None, b=None, precision: str = "fp32", cost_p: float = 0.0,
+                   cost_mode: str = "auto") -> Clouds:
+    return Clouds(X, Y, a, b, precision, cost_p, cost_mode)
 
 
 @dataclass

@@ -202,22 +202,32 @@ def test_metrics_reject_invalid_before_launch():
 def test_pcost_workspace_and_prepare_reject_invalid():
     lib = P.lib()
     inv = B.POT_ERR_INVALID
+    AUTO, FLY, KEEP = 0, 1, 2
     for p in (0.0, 0.5, 1.0, float("nan"), float("inf"), 17.0):
-        assert lib.pot_workspace_bytes_pcost(100, 80, 8, p) == 0, p
-    assert lib.pot_workspace_bytes_pcost(0, 80, 8, 1.5) == 0
-    assert lib.pot_workspace_bytes_pcost(100, 80, 257, 1.5) == 0
-    assert lib.pot_workspace_bytes_pcost(1 << 20, 1 << 20, 8, 1.5) == 0   # n m > 2^36
-    nb = lib.pot_workspace_bytes_pcost(100, 80, 8, 1.5)
-    # the resident cost matrix (n x m rounded up to 4) is part of the workspace
+        assert lib.pot_workspace_bytes_pcost(100, 80, 8, p, AUTO) == 0, p
+    assert lib.pot_workspace_bytes_pcost(0, 80, 8, 1.5, AUTO) == 0
+    assert lib.pot_workspace_bytes_pcost(100, 80, 257, 1.5, AUTO) == 0
+    assert lib.pot_workspace_bytes_pcost(100, 80, 8, 1.5, 3) == 0          # unknown flags
+    # a kept matrix is limited to 2^36 entries; on the fly only the grid limits n m
+    assert lib.pot_workspace_bytes_pcost(1 << 20, 1 << 20, 8, 1.5, KEEP) == 0
+    big = lib.pot_workspace_bytes_pcost(1 << 20, 1 << 20, 8, 1.5, AUTO)
+    assert 0 < big < (1 << 36)                                              # > 16 GiB: not kept
+    assert lib.pot_workspace_bytes_pcost(1 << 22, 1 << 22, 8, 1.5, FLY) == 0  # grid limit
+    nb = lib.pot_workspace_bytes_pcost(100, 80, 8, 1.5, AUTO)
+    # the kept cost matrix (n x m rounded up to 4) is part of the workspace
     assert nb >= P.workspace_bytes(100, 80, 8) + 100 * 80 * 4 and nb % 256 == 0
-    assert lib.pot_workspace_bytes_pcost(100, 81, 8, 2.5) > nb
+    assert lib.pot_workspace_bytes_pcost(100, 80, 8, 1.5, KEEP) == nb
+    assert lib.pot_workspace_bytes_pcost(100, 80, 8, 1.5, FLY) <= nb - 100 * 80 * 4
+    assert lib.pot_workspace_bytes_pcost(100, 81, 8, 2.5, AUTO) > nb
     assert P.workspace_bytes(100, 80, 8, "bf16", cost_p=1.5) == 0
     c = B.pot_clouds()
     call = lambda **kw: lib.pot_prepare_clouds_pcost(
         C.byref(c), kw.get("X", 0x1000), kw.get("n", 100), kw.get("Y", 0x1000), kw.get("m", 80),
-        kw.get("d", 8), None, None, kw.get("p", 1.5), kw.get("ws", 0x2000), kw.get("wsb", nb), None)
+        kw.get("d", 8), None, None, kw.get("p", 1.5), kw.get("flags", AUTO), kw.get("ws", 0x2000),
+        kw.get("wsb", nb), None)
     assert call(X=None) == inv and call(Y=None) == inv and call(ws=None) == inv
     assert call(p=1.0) == inv and call(p=0.0) == inv and call(n=0) == inv and call(d=300) == inv
+    assert call(flags=7) == inv
     assert call(wsb=nb - 1) == B.POT_ERR_NOMEM
 
 
@@ -228,19 +238,20 @@ def test_pcost_clouds_validated():
     inv = B.POT_ERR_INVALID
     c = _fake_clouds(8, 8, 4)
     c.cost_p = 1.5
-    c.ws_bytes = lib.pot_workspace_bytes_pcost(8, 8, 4, 1.5)
+    c.ws_bytes = lib.pot_workspace_bytes_pcost(8, 8, 4, 1.5, 2)
     info = B.pot_sinkhorn_info()
-    # no cost matrix pointer
+    # a stride without a matrix, or a matrix with the wrong stride
+    c.cmat, c.ldc = 0, 8
     assert lib.pot_sinkhorn_solve(C.byref(c), 1.0, 1e-3, 10, None, None, 0x3000, 0x3000,
                                   C.byref(info), None) == inv
-    c.cmat, c.ldc = 0x5000, 7   # wrong stride
+    c.cmat, c.ldc = 0x5000, 7
     assert lib.pot_sinkhorn_solve(C.byref(c), 1.0, 1e-3, 10, None, None, 0x3000, 0x3000,
                                   C.byref(info), None) == inv
     c.ldc = 8
-    c.ws_bytes = P.workspace_bytes(8, 8, 4)   # too small for the cost matrix
+    c.ws_bytes = lib.pot_workspace_bytes_pcost(8, 8, 4, 1.5, 1)   # too small for the matrix
     assert lib.pot_sinkhorn_solve(C.byref(c), 1.0, 1e-3, 10, None, None, 0x3000, 0x3000,
                                   C.byref(info), None) == inv
-    c.ws_bytes = lib.pot_workspace_bytes_pcost(8, 8, 4, 1.5)
+    c.ws_bytes = lib.pot_workspace_bytes_pcost(8, 8, 4, 1.5, 2)
     c.precision = 1
     assert lib.pot_entropic_map(C.byref(c), 0x3000, 1.0, 0x3000, 4, 1.0, 0x3000, None) == inv
     c.precision = 0
@@ -248,7 +259,7 @@ def test_pcost_clouds_validated():
     grid = (C.c_double * 3)(0.5, 1.0, 2.0)
     eps = (C.c_double * 4)()
     wsb = lib.pot_eps_schedule_pcost_bytes(8, 5, 4, 3, 1.5)
-    assert wsb >= lib.pot_workspace_bytes_pcost(8, 8, 4, 1.5) and wsb % 256 == 0
+    assert wsb >= lib.pot_workspace_bytes_pcost(8, 8, 4, 1.5, 0) and wsb % 256 == 0
     assert lib.pot_eps_schedule_pcost_bytes(8, 5, 4, 3, 1.0) == 0
     assert lib.pot_eps_schedule(C.byref(c), 0x4000, 5, 4, 0, grid, 3, 5.0, 1e-3, 100, eps, None,
                                 None, 0x2000, wsb - 1, None) == B.POT_ERR_NOMEM
@@ -260,7 +271,7 @@ def test_pcost_divergence_rejects_invalid():
     assert lib.pot_sinkhorn_divergence_pcost_bytes(100, 80, 8, 1.0) == 0
     assert lib.pot_sinkhorn_divergence_pcost_bytes(0, 80, 8, 1.5) == 0
     nb = lib.pot_sinkhorn_divergence_pcost_bytes(100, 80, 8, 1.5)
-    assert nb >= lib.pot_workspace_bytes_pcost(100, 100, 8, 1.5) and nb % 256 == 0
+    assert nb >= lib.pot_workspace_bytes_pcost(100, 100, 8, 1.5, 0) and nb % 256 == 0
     out = (C.c_double * 5)()
     call = lambda **kw: lib.pot_sinkhorn_divergence_pcost(
         kw.get("X", 0x1000), 100, kw.get("Y", 0x1000), 80, 8, None, None, kw.get("p", 1.5),

@@ -291,3 +291,46 @@ def test_extreme_exponents(P, p):
     Q = workloads.gmm(seed=381, n=300, m=4, d=16, n_comp=3)[0]
     out = P.entropic_map(cl, g, eps, P.to_device(Q), alpha=0.5)
     assert map_err(out.cpu().numpy(), pcost.entropic_map_p(Q, Y, g32, eps, p, alpha=0.5), Y) < 1e-3
+
+
+FLY_SHAPES = [(700, 1300, 47), (300, 513, 100), (64, 2000, 256), (1, 5, 3), (7, 1, 3), (3000, 200, 16)]
+
+
+@pytest.mark.parametrize("n,m,d", FLY_SHAPES)
+@pytest.mark.parametrize("p", [1.5, 2.5])
+def test_on_the_fly_potentials(P, n, m, d, p):
+    """Potential updates that form h on the fly (no cost matrix in the
+    workspace) against the oracle, and against the kept-matrix path."""
+    X, Y = workloads.gmm(seed=390 + n + d, n=n, m=m, d=d, n_comp=3)
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    C = pcost.cost_matrix_p(X, Y, p)
+    eps = float(np.float32(0.05 * C.mean()))
+    print(f"case fly n={n} m={m} d={d} p={p}", flush=True)
+    clf = P.prepare_clouds(P.to_device(X), P.to_device(Y), cost_p=p, cost_mode="on_the_fly")
+    clk = P.prepare_clouds(P.to_device(X), P.to_device(Y), cost_p=p, cost_mode="keep")
+    assert not clf.c.cmat and clk.c.cmat
+    assert abs(clf.mean_cost / C.mean() - 1) < 1e-6 and clf.mean_cost == clk.mean_cost
+    f, g, info = P.sinkhorn_solve(clf, eps, tau=0.0, max_iter=13)
+    fk, gk, _ = P.sinkhorn_solve(clk, eps, tau=0.0, max_iter=13)
+    ref = oracle.sinkhorn(a, X, b, Y, eps, 0.0, n_iter=13, C=C)
+    assert pot_err(f.cpu().numpy(), ref.f, eps) < 1e-4 and pot_err(g.cpu().numpy(), ref.g, eps) < 1e-4
+    assert pot_err(f.cpu().numpy(), fk.cpu().numpy(), eps) < 1e-5
+    assert abs(info.err - ref.err) <= 1e-5 + 2e-3 * ref.err
+
+
+def test_on_the_fly_progot(P):
+    """ProgOT and T_Prog with the cost formed on the fly (the mean cost of each
+    step from a sum-only pass) against the oracle's trajectory."""
+    X, Y, _, _, _, _, _ = _progot_case(P, 1.0)
+    n, m = X.shape[0], Y.shape[0]
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), cost_p=1.5, cost_mode="on_the_fly")
+    f, G, TX, info = P.progot_solve(cl, 4, theta=1.0, tau_first=1e-3, tau_last=1e-3)
+    ref = pcost.progot_p(a, X, b, Y, 4, 1.5, theta=1.0, tau=1e-3)
+    print(f"case fly progot: gpu iters {info.iters} oracle {ref.iters}", flush=True)
+    assert info.converged
+    np.testing.assert_allclose(info.eps, ref.eps, rtol=1e-4)
+    assert all(abs(u - v) <= 2 for u, v in zip(info.iters, ref.iters))
+    assert map_err(TX.cpu().numpy(), ref.TX, Y) < 1e-3
+    chk = P.marginal_check(cl, f, G[-1], info.eps[-1])
+    assert chk[0] <= 1e-3 * 1.01 and chk[1] <= 1e-4

@@ -88,6 +88,19 @@ hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part);
 // to err_out[k] for the k-th such job.
 hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, float *err_out,
                                    hipStream_t s);
+
+// The two halves of launch_lse_update_group, for callers that upload the
+// tables of several grouped updates in one copy: plan_lse_update_group plans
+// the host array in place (block offsets included) and fills the totals;
+// enqueue_lse_update_group launches on a device copy of that planned array.
+struct GroupPlan {
+    int64_t blocks, mblocks;
+    int nerr;
+    int D;
+};
+hipError_t plan_lse_update_group(LseJob *jobs, int njobs, GroupPlan *gp);
+hipError_t enqueue_lse_update_group(const LseJob *jobs_dev, int njobs, const GroupPlan &gp,
+                                    float *err_out, hipStream_t s);
 int padded_dim_f32(int d);
 
 // Deterministic sum of n float partials into *out (device).

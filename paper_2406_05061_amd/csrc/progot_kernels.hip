@@ -632,12 +632,16 @@ void plan_lse_job(LseJob &j) {
     const int rows = j.precision == 0 ? lse_rows_per_block(j.d) : lse_bf16_rows_per_block(j.d, j.precision);
     const int64_t tiles = (j.nu + rows - 1) / rows;
     // Split the columns so that the grid holds >= target workgroups,
-    // keeping >= 256 columns per split.  S is a power of two, so with S >= 8
-    // the blocks an XCD receives (block b goes to XCD b mod 8, split b mod S)
-    // stream a fixed subset of the column splits through that XCD's L2.
+    // keeping >= one LDS column tile per split in FP32 (64 columns; small
+    // problems such as the 1024-point grid solves of the eps-scheduler need
+    // the splits to fill the chip) and >= 256 columns in BF16.  S is a power
+    // of two, so with S >= 8 the blocks an XCD receives (block b goes to XCD
+    // b mod 8, split b mod S) stream a fixed subset of the column splits
+    // through that XCD's L2.
     const int64_t target = j.precision == 0 ? kSplitTargetF32 : kSplitTargetBf16;
     int64_t S = tiles >= target ? 1 : (target + tiles - 1) / tiles;
-    const int64_t max_by_cols = (j.nv + 255) / 256;
+    const int64_t min_cols = j.precision == 0 ? 64 : 256;
+    const int64_t max_by_cols = (j.nv + min_cols - 1) / min_cols;
     if (S > max_by_cols) S = max_by_cols;
     if (S > 1) {
         int64_t q = 1;
@@ -684,9 +688,8 @@ hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
     return hipGetLastError();
 }
 
-hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, float *err_out,
-                                   hipStream_t s) {
-    if (njobs <= 0) return hipSuccess;
+hipError_t plan_lse_update_group(LseJob *jobs, int njobs, GroupPlan *gp) {
+    if (njobs <= 0) return hipErrorInvalidValue;
     int64_t blk = 0, mblk = 0;
     int nerr = 0;
     const int D = padded_dim(jobs[0].d);
@@ -700,20 +703,36 @@ hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, fl
         mblk += jobs[k].mblocks;
         if (jobs[k].pot_old) ++nerr;
     }
-    hipError_t e = hipMemcpyAsync(jobs_dev, jobs, sizeof(LseJob) * njobs, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    switch (D) {
-        case 16: e = lse_group_launch_t<16, lse_qb(16)>(jobs_dev, njobs, blk, s); break;
-        case 32: e = lse_group_launch_t<32, lse_qb(32)>(jobs_dev, njobs, blk, s); break;
-        case 64: e = lse_group_launch_t<64, lse_qb(64)>(jobs_dev, njobs, blk, s); break;
-        case 128: e = lse_group_launch_t<128, lse_qb(128)>(jobs_dev, njobs, blk, s); break;
-        default: e = lse_group_launch_t<256, lse_qb(256)>(jobs_dev, njobs, blk, s); break;
+    *gp = GroupPlan{blk, mblk, nerr, D};
+    return hipSuccess;
+}
+
+hipError_t enqueue_lse_update_group(const LseJob *jobs_dev, int njobs, const GroupPlan &gp,
+                                    float *err_out, hipStream_t s) {
+    hipError_t e;
+    switch (gp.D) {
+        case 16: e = lse_group_launch_t<16, lse_qb(16)>(jobs_dev, njobs, gp.blocks, s); break;
+        case 32: e = lse_group_launch_t<32, lse_qb(32)>(jobs_dev, njobs, gp.blocks, s); break;
+        case 64: e = lse_group_launch_t<64, lse_qb(64)>(jobs_dev, njobs, gp.blocks, s); break;
+        case 128: e = lse_group_launch_t<128, lse_qb(128)>(jobs_dev, njobs, gp.blocks, s); break;
+        default: e = lse_group_launch_t<256, lse_qb(256)>(jobs_dev, njobs, gp.blocks, s); break;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(lse_merge_group, dim3((unsigned)mblk), dim3(256), 0, s, jobs_dev, njobs);
-    if (nerr > 0)
-        hipLaunchKernelGGL(sum_group, dim3(nerr), dim3(256), 0, s, jobs_dev, njobs, err_out);
+    hipLaunchKernelGGL(lse_merge_group, dim3((unsigned)gp.mblocks), dim3(256), 0, s, jobs_dev, njobs);
+    if (gp.nerr > 0)
+        hipLaunchKernelGGL(sum_group, dim3(gp.nerr), dim3(256), 0, s, jobs_dev, njobs, err_out);
     return hipGetLastError();
+}
+
+hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, float *err_out,
+                                   hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    GroupPlan gp;
+    hipError_t e = plan_lse_update_group(jobs, njobs, &gp);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(jobs_dev, jobs, sizeof(LseJob) * njobs, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return enqueue_lse_update_group(jobs_dev, njobs, gp, err_out, s);
 }
 
 hipError_t launch_sum_f32(const float *part, int n, float *out, hipStream_t s) {

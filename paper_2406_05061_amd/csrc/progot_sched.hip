@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 using namespace pot::host;
@@ -56,8 +57,14 @@ size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
 struct SchedLayout {
     Layout cy;
     size_t f0, f1, g0, g1, pm, ps, errp, per_p;  // within one grid point's block
-    size_t grid, jobs, errs, ty, sq, total;
+    size_t grid, jobs, ctl, ty, sq, total;
 };
+
+// Sinkhorn iterations enqueued per host read-back of the stop words: the
+// first blocks are short (large-eps grid points stop within a few
+// iterations), later ones up to kMaxBlockIters.
+constexpr int kFirstBlockIters = 4;
+constexpr int kMaxBlockIters = 32;
 
 SchedLayout sched_plan(int64_t m, int64_t mt, int32_t d, int32_t G) {
     SchedLayout S{};
@@ -75,10 +82,10 @@ SchedLayout sched_plan(int64_t m, int64_t mt, int32_t d, int32_t G) {
     S.grid = a256(S.cy.total);
     size_t off = S.grid + (size_t)G * S.per_p;
     auto take2 = [&](size_t bytes) { size_t r = off; off = a256(off + bytes); return r; };
-    S.jobs = take2(sizeof(LseJob) * 2 * (size_t)G);
-    S.errs = take2(sizeof(float) * (size_t)G);
+    S.jobs = take2(sizeof(LseJob) * 2 * (size_t)G * kMaxBlockIters);
+    S.ctl = take2(sizeof(int) * 2 * (size_t)G);
     S.ty = take2((size_t)mt * d * 4);
-    S.sq = take2(kSqBlocks * sizeof(double));
+    S.sq = take2(kSqBlocks * sizeof(double) * (size_t)G);
     S.total = off;
     return S;
 }
@@ -124,22 +131,37 @@ bool valid_pcost_pair(int64_t m, int32_t d, float p) {
            pot::pcost_matrix_blocks(m, m) <= 0x7fffffff;
 }
 
-// Hold-out score err_p = sum |y~ - T_p(y~)|^2 of one grid solve (FP64 sum).
-int holdout_score(const pot_clouds *cy, const float *g, float eps, const float *Y_test, int64_t mt,
-                  float *ty, double *sq_dev, double *score, hipStream_t s) {
+// Hold-out score err_p = sum |y~ - T_p(y~)|^2 of one grid solve: the map of
+// the hold-out targets into ty and the FP64 partials of the squared distance
+// into sq_dev (kSqBlocks doubles), enqueued only.
+int enqueue_holdout(const pot_clouds *cy, const float *g, float eps, const float *Y_test, int64_t mt,
+                    float *ty, double *sq_dev, hipStream_t s) {
     int st = run_map(cy, g, eps, Y_test, mt, 1.f, ty, s);
     if (st != POT_OK) return st;
     hipLaunchKernelGGL(sqdist_partial, dim3(kSqBlocks), dim3(256), 0, s, Y_test, ty,
                        mt * (int64_t)cy->d, sq_dev);
     POT_TRY(hipGetLastError());
-    std::vector<double> sq(kSqBlocks);
-    POT_TRY(hipMemcpyAsync(sq.data(), sq_dev, sizeof(double) * kSqBlocks, hipMemcpyDeviceToHost, s));
-    POT_TRY(hipStreamSynchronize(s));
+    return POT_OK;
+}
+
+// Sum of the partials read back (in order, so the score does not depend on
+// how many grid points were scored together).
+int finish_holdout(const double *sq, double *score) {
     double tot = 0.0;
-    for (double v : sq) tot += v;
+    for (int i = 0; i < kSqBlocks; ++i) tot += sq[i];
     if (!std::isfinite(tot)) return POT_ERR_NUMERIC;
     *score = tot;
     return POT_OK;
+}
+
+int holdout_score(const pot_clouds *cy, const float *g, float eps, const float *Y_test, int64_t mt,
+                  float *ty, double *sq_dev, double *score, hipStream_t s) {
+    int st = enqueue_holdout(cy, g, eps, Y_test, mt, ty, sq_dev, s);
+    if (st != POT_OK) return st;
+    std::vector<double> sq(kSqBlocks);
+    POT_TRY(hipMemcpyAsync(sq.data(), sq_dev, sizeof(double) * kSqBlocks, hipMemcpyDeviceToHost, s));
+    POT_TRY(hipStreamSynchronize(s));
+    return finish_holdout(sq.data(), score);
 }
 
 // eps_k from the selected scale (the last lines of Alg. 4).
@@ -271,67 +293,97 @@ int pot_eps_schedule(const pot_clouds *c, const float *Y_test, int64_t m_test, i
         q.errp = reinterpret_cast<float *>(blk + S.errp);
     }
     LseJob *jobs_dev = reinterpret_cast<LseJob *>(base + S.jobs);
-    float *errs_dev = reinterpret_cast<float *>(base + S.errs);
+    int *ctl_dev = reinterpret_cast<int *>(base + S.ctl);
     const LseJob fbase = f_job(&cy, S.cy, 1.f), gbase = g_job(&cy, S.cy, 1.f);
 
     // Alg. 1 for every grid point, advanced together.  Iteration t: f_t
     // (whose error partials are the row-marginal error of iterate t-1), then
-    // g_t; after both, the errors of iterate t-1 are read back and a grid
-    // point that met tau stops there (its iterate t-1 is intact in the
-    // ping-pong buffers).  At t = max_iter one more f-update gives the error
-    // of the last iterate.
-    std::vector<LseJob> fj(n_grid), gj(n_grid);
-    std::vector<int> act, err_of(n_grid);
-    std::vector<float> errs(n_grid);
-    for (int t = 1;; ++t) {
+    // g_t; at t = max_iter + 1 only the f-update, for the error of the last
+    // iterate.  The stop rule runs on the device: the error sum of f_t sets
+    // the grid point's control word {stop iterate, error bits} once the error
+    // of iterate t-1 meets tau (or t-1 = max_iter), and every later update of
+    // that grid point is skipped, so its iterate t-1 stays intact in the
+    // ping-pong buffers (f_t writes the other one).  Blocks of iterations are
+    // enqueued between read-backs of the control words; each block's job
+    // tables go up in one copy.
+    POT_TRY(hipMemsetAsync(ctl_dev, 0, sizeof(int) * 2 * (size_t)n_grid, s));
+    std::vector<LseJob> tab((size_t)2 * n_grid * kMaxBlockIters);
+    std::vector<pot::GroupPlan> plans(2 * kMaxBlockIters);
+    std::vector<int> act, ctl(2 * (size_t)n_grid);
+    int t0 = 1, block = kFirstBlockIters;
+    while (true) {
         act.clear();
         for (int p = 0; p < n_grid; ++p)
             if (!pts[p].done) act.push_back(p);
         if (act.empty()) break;
+        if (t0 > max_iter + 1) return POT_ERR_DEVICE;   // every grid point stops by then
         const int na = (int)act.size();
-        const bool probe = t == max_iter + 1;   // error of iterate max_iter only
-        for (int k = 0; k < na; ++k) {
-            const GridPoint &q = pts[act[k]];
-            LseJob f = point_job(fbase, q);
-            f.vpot = t == 1 ? nullptr : q.gb[(t - 1) & 1];
-            f.pot_old = t == 1 ? nullptr : q.fb[(t - 1) & 1];
-            f.pot_out = q.fb[t & 1];
-            f.err_part = q.errp;
-            fj[k] = f;
-            LseJob g = point_job(gbase, q);
-            g.vpot = q.fb[t & 1];
-            g.pot_out = q.gb[t & 1];
-            g.err_part = nullptr;
-            gj[k] = g;
-        }
-        POT_TRY(pot::launch_lse_update_group(fj.data(), na, jobs_dev, errs_dev, s));
-        if (!probe) POT_TRY(pot::launch_lse_update_group(gj.data(), na, jobs_dev + n_grid, nullptr, s));
-        if (t > 1) POT_TRY(hipMemcpyAsync(errs.data(), errs_dev, sizeof(float) * na, hipMemcpyDeviceToHost, s));
-        // the job tables above are read by the copies just enqueued
-        POT_TRY(hipStreamSynchronize(s));
-        if (t == 1) continue;
-        for (int k = 0; k < na; ++k) {
-            GridPoint &q = pts[act[k]];
-            const float err = errs[k];
-            if (!std::isfinite(err)) return POT_ERR_NUMERIC;
-            if (err <= tau || probe) {
-                q.done = true;
-                q.converged = err <= tau;
-                q.iters = t - 1;
-                q.err = err;
-                q.g = q.gb[(t - 1) & 1];
+        const int nt = std::min<int64_t>(block, (int64_t)max_iter + 1 - t0 + 1);
+        for (int u = 0; u < nt; ++u) {
+            const int t = t0 + u;
+            LseJob *fj = tab.data() + (size_t)2 * na * u, *gj = fj + na;
+            for (int k = 0; k < na; ++k) {
+                const int p = act[k];
+                const GridPoint &q = pts[p];
+                LseJob f = point_job(fbase, q);
+                f.vpot = t == 1 ? nullptr : q.gb[(t - 1) & 1];
+                f.pot_old = t == 1 ? nullptr : q.fb[(t - 1) & 1];
+                f.pot_out = q.fb[t & 1];
+                f.err_part = q.errp;
+                f.ctl = ctl_dev + 2 * p;
+                f.iter = t - 1;
+                f.max_iter = max_iter;
+                f.tau = tau;
+                fj[k] = f;
+                LseJob g = point_job(gbase, q);
+                g.vpot = q.fb[t & 1];
+                g.pot_out = q.gb[t & 1];
+                g.err_part = nullptr;
+                g.ctl = f.ctl;
+                gj[k] = g;
             }
+            POT_TRY(pot::plan_lse_update_group(fj, na, &plans[2 * u]));
+            POT_TRY(pot::plan_lse_update_group(gj, na, &plans[2 * u + 1]));
         }
+        POT_TRY(hipMemcpyAsync(jobs_dev, tab.data(), sizeof(LseJob) * 2 * na * nt, hipMemcpyHostToDevice, s));
+        for (int u = 0; u < nt; ++u) {
+            const int t = t0 + u;
+            const LseJob *fd = jobs_dev + (size_t)2 * na * u;
+            POT_TRY(pot::enqueue_lse_update_group(fd, na, plans[2 * u], nullptr, s));
+            if (t <= max_iter) POT_TRY(pot::enqueue_lse_update_group(fd + na, na, plans[2 * u + 1], nullptr, s));
+        }
+        POT_TRY(hipMemcpyAsync(ctl.data(), ctl_dev, sizeof(int) * 2 * n_grid, hipMemcpyDeviceToHost, s));
+        // the host tables above stay untouched until the stream has read them
+        POT_TRY(hipStreamSynchronize(s));
+        for (int p : act) {
+            GridPoint &q = pts[p];
+            const int it = ctl[2 * p];
+            if (it == 0) continue;
+            float err;
+            std::memcpy(&err, &ctl[2 * p + 1], sizeof(float));
+            if (!std::isfinite(err)) return POT_ERR_NUMERIC;
+            q.done = true;
+            q.converged = err <= tau;
+            q.iters = it;
+            q.err = err;
+            q.g = q.gb[it & 1];
+        }
+        t0 += nt;
+        block = std::min(2 * block, kMaxBlockIters);
     }
 
-    // hold-out scores
-    std::vector<double> score(n_grid);
+    // hold-out scores: every grid point's map and partials, one read-back
     float *ty = reinterpret_cast<float *>(base + S.ty);
     double *sq_dev = reinterpret_cast<double *>(base + S.sq);
     for (int p = 0; p < n_grid; ++p)
-        if ((st = holdout_score(&cy, pts[p].g, pts[p].eps, Y_test, m_test, ty, sq_dev, &score[p], s)) !=
-            POT_OK)
+        if ((st = enqueue_holdout(&cy, pts[p].g, pts[p].eps, Y_test, m_test, ty,
+                                  sq_dev + (size_t)p * kSqBlocks, s)) != POT_OK)
             return st;
+    std::vector<double> sq((size_t)n_grid * kSqBlocks), score(n_grid);
+    POT_TRY(hipMemcpyAsync(sq.data(), sq_dev, sizeof(double) * sq.size(), hipMemcpyDeviceToHost, s));
+    POT_TRY(hipStreamSynchronize(s));
+    for (int p = 0; p < n_grid; ++p)
+        if ((st = finish_holdout(sq.data() + (size_t)p * kSqBlocks, &score[p])) != POT_OK) return st;
     int best = 0;
     for (int p = 1; p < n_grid; ++p)
         if (score[p] < score[best]) best = p;

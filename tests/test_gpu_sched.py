@@ -87,3 +87,34 @@ def test_eps_schedule_weighted_and_nonconverged(P):
     few = P.eps_schedule(cl, P.to_device(Yt), 3, tau=1e-9, max_iter=3)
     assert few.status == 1
     assert all(np.isfinite(few.eps))
+
+
+@pytest.mark.parametrize("tau,max_iter", [(1e-3, 10_000), (1e-9, 1), (1e-9, 3), (1e-9, 5),
+                                          (1e-6, 40)])
+def test_grid_solves_match_single_problem(P, tau, max_iter):
+    """Each grid solve of the scheduler (grid points advanced together, the
+    stop rule evaluated on the device, several iterations per read-back)
+    stops at the same iterate as the single-problem Sinkhorn solve with that
+    scale's eps, so its hold-out score equals the score of that solve's map
+    up to the order of one FP64 sum.  max_iter 1, 3, 5 cover the last-iterate
+    probe inside and right after the first block of iterations."""
+    X, Y = workloads.gmm(seed=31, n=400, m=300, d=8)
+    b = workloads.weights(300, seed=32)
+    Yt = workloads.gmm(seed=33, n=400, m=300, d=8)[1][:200]
+    Yd, bd, Ytd = P.to_device(Y), P.to_device(b), P.to_device(Yt)
+    cl = P.prepare_clouds(P.to_device(X), Yd, b=bd)
+    grid = [2.0 ** k for k in range(-3, 4)]
+    out = P.eps_schedule(cl, Ytd, 3, s_grid=grid, tau=tau, max_iter=max_iter)
+    cy = P.prepare_clouds(Yd, Yd, a=bd, b=bd)
+    sigma = cy.mean_cost / 20.0
+    ref, conv = [], []
+    for s in grid:
+        eps = float(np.float32(s * sigma))
+        _, g, info = P.sinkhorn_solve(cy, eps, tau=tau, max_iter=max_iter)
+        ty = P.entropic_map(cy, g, eps, Ytd).cpu().numpy().astype(np.float64)
+        ref.append(((Yt.astype(np.float32).astype(np.float64) - ty) ** 2).sum())
+        conv.append(info.converged)
+    print(f"case tau={tau} max_iter={max_iter}: scores {np.array(out.errors)} ref {np.array(ref)}",
+          flush=True)
+    np.testing.assert_allclose(out.errors, ref, rtol=1e-12)
+    assert out.status == (0 if all(conv) else 1)

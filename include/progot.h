@@ -363,14 +363,18 @@ POT_API int pot_server_poll(pot_server *srv, int64_t rid, pot_progot_info *info)
 /* Waits for the stream and frees the server's host state (not the arena). */
 POT_API int pot_server_destroy(pot_server *srv);
 
-/* Kernel timing, a tracing aid.  While enabled (process-wide), every launch
- * of the fused cost + log-sum-exp kernel (the f- and g-update) and of the
- * entropic-map kernel is bracketed by HIP timing events on the stream it is
- * launched on.  pot_timing_enable(1) clears the counters; pot_timing_read
- * waits for the recorded events and returns the summed kernel milliseconds
- * and launch counts (any pointer may be NULL).  Calls are serialised by a
- * mutex; timing adds two event records per launch. */
-POT_API int pot_timing_enable(int on);
+/* Kernel timing, a tracing aid.  While enabled (process-wide), launches of
+ * the potential-update kernel (the f- and g-update) and of the entropic-map
+ * kernel are bracketed by HIP timing events, recorded by the dispatch itself
+ * on the stream it is launched on.  pot_timing_enable(every), every >= 1,
+ * clears the counters and times launches 0, every, 2 every, ... of each of
+ * the two kernels (1: every launch; a larger stride samples, which keeps the
+ * cost of the events -- two per timed launch, and the host work to record
+ * them -- off short kernels); pot_timing_enable(0) stops; every < 0 is
+ * POT_ERR_INVALID.  pot_timing_read waits for the recorded events and
+ * returns the summed milliseconds and counts of the timed launches (any
+ * pointer may be NULL).  Calls are serialised by a mutex. */
+POT_API int pot_timing_enable(int every);
 POT_API int pot_timing_read(double *lse_ms, int64_t *lse_launches, double *map_ms,
                             int64_t *map_launches);
 

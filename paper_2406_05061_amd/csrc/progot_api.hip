@@ -46,7 +46,6 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p, bo
     // error partials: one per 256 rows from the merge kernel, or one per 4
     // rows from the fused row update of the general-cost path
     L.errp = take((cost_p != 0.f ? (nm + 3) / 4 : (nm + 255) / 256) * 4);
-    L.errd = take(64);
     L.xst = take((size_t)pot::cloud_stat_blocks(n) * (d + 1) * 8);
     L.yst = take((size_t)pot::cloud_stat_blocks(m) * (d + 1) * 8);
     L.chr = take((size_t)pot::fp64_check_blocks(n) * pot::kCheckParts * 8);
@@ -255,20 +254,32 @@ namespace {
 using namespace pot::host;
 using pot::LseJob;
 
-// Per-thread pinned landing zone for scalar read-backs.
+// Per-thread pinned landing zone for scalar read-backs: coherent host memory
+// mapped into the device's address space, so the kernel that forms a scalar
+// (an error sum) stores it there itself and the host reads it once an event
+// after that kernel has completed; no copy command per read-back.
 struct Pinned {
     float *buf = nullptr;
+    float *dev = nullptr;   // the same memory, as the device addresses it
     ~Pinned() { if (buf) (void)hipHostFree(buf); }
 };
 thread_local Pinned g_pinned;
 
-float *pinned_slot() {
+float *pinned_slot(float **dev) {
     if (!g_pinned.buf) {
         if (hipHostMalloc(reinterpret_cast<void **>(&g_pinned.buf), 64 * sizeof(float),
-                          hipHostMallocDefault) != hipSuccess) {
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
             g_pinned.buf = nullptr;
+            return nullptr;
+        }
+        if (hipHostGetDevicePointer(reinterpret_cast<void **>(&g_pinned.dev), g_pinned.buf, 0) !=
+            hipSuccess) {
+            (void)hipHostFree(g_pinned.buf);
+            g_pinned.buf = g_pinned.dev = nullptr;
+            return nullptr;
         }
     }
+    *dev = g_pinned.dev;
     return g_pinned.buf;
 }
 
@@ -290,12 +301,12 @@ struct SinkResult {
     const float *f = nullptr, *g = nullptr;
 };
 
-// Enqueue err = sum of the error partials and its copy to a pinned slot.
-int enqueue_err_readback(const pot_clouds *c, const Layout &L, int nparts, float *host,
-                         hipEvent_t ev, hipStream_t s) {
-    float *dev = at<float>(c, L.errd);
-    POT_TRY(pot::launch_sum_f32(at<float>(c, L.errp), nparts, dev, s));
-    POT_TRY(hipMemcpyAsync(host, dev, sizeof(float), hipMemcpyDeviceToHost, s));
+// Enqueue err = sum of the error partials into a pinned slot (`slot`, its
+// device address), unless a later update already carries it (summed = true),
+// and the event the host waits on before reading the slot.
+int enqueue_err_readback(const pot_clouds *c, const Layout &L, int nparts, float *slot,
+                         hipEvent_t ev, hipStream_t s, bool summed = false) {
+    if (!summed) POT_TRY(pot::launch_sum_f32(at<float>(c, L.errp), nparts, slot, s));
     POT_TRY(hipEventRecord(ev, s));
     return POT_OK;
 }
@@ -314,6 +325,10 @@ int enqueue_err_readback(const pot_clouds *c, const Layout &L, int nparts, float
 // The potentials live in a ring of three slots, so the iterate whose error
 // is being read is still intact when it is returned.  Errors are checked in
 // order and the first iterate with err <= tau is returned in every mode.
+// At lag 2, where the g-update's kernel can carry it (the general-cost
+// column kernel), the sum of f_t's error partials rides in g_t's first
+// workgroup instead of a launch of its own; the copy then follows g_t, which
+// the host does not wait for until two iterations later.
 constexpr int kRing = 3;
 
 int pick_lag(const pot_clouds *c) {
@@ -341,14 +356,16 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
                   const float *g_init, float gamma, SinkResult *out, hipStream_t s) {
     float *fb[kRing] = {at<float>(c, L.f0), at<float>(c, L.f1), at<float>(c, L.f2)};
     float *gb[kRing] = {at<float>(c, L.g0), at<float>(c, L.g1), at<float>(c, L.g2)};
-    float *host = pinned_slot();
+    float *hdev = nullptr;
+    float *host = pinned_slot(&hdev);
     if (!host) return POT_ERR_DEVICE;
     Events E;
     for (hipEvent_t &e : E.ev) POT_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     const int lag = pick_lag(c);
     LseJob fa = f_job(c, L, eps);
     LseJob ga = g_job(c, L, eps);
-    // read err_k (its copy was enqueued with f_{k+1}); true when the loop ends at k
+    const bool fold = lag == 2 && pot::lse_update_folds_sum(ga);
+    // read err_k (its sum was enqueued with f_{k+1}, or rides in g_{k+1}); true when the loop ends at k
     auto check = [&](int k, int *status) -> bool {
         if (hipEventSynchronize(E.ev[k % kRing]) != hipSuccess) { *status = POT_ERR_DEVICE; return true; }
         const float err = host[k % kRing];
@@ -368,13 +385,21 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
         fa.pot_out = fb[t % kRing];
         int nparts = 0;
         if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) return POT_ERR_DEVICE;
-        if (t > 1 && (status = enqueue_err_readback(c, L, nparts, host + (t - 1) % kRing,
-                                                    E.ev[(t - 1) % kRing], s)) != POT_OK)
+        if (t > 1 && !fold &&
+            (status = enqueue_err_readback(c, L, nparts, hdev + (t - 1) % kRing, E.ev[(t - 1) % kRing],
+                                           s)) != POT_OK)
             return status;
         if (lag == 0 && t > 1 && check(t - 1, &status)) return status;
         ga.vpot = fb[t % kRing];
         ga.pot_out = gb[t % kRing];
+        const bool carry = fold && t > 1;
+        ga.esum_in = carry ? at<float>(c, L.errp) : nullptr;
+        ga.esum_n = carry ? nparts : 0;
+        ga.esum_out = carry ? hdev + (t - 1) % kRing : nullptr;
         if (pot::launch_lse_update(ga, s, nullptr) != hipSuccess) return POT_ERR_DEVICE;
+        if (carry && (status = enqueue_err_readback(c, L, nparts, hdev + (t - 1) % kRing,
+                                                    E.ev[(t - 1) % kRing], s, true)) != POT_OK)
+            return status;
         // err_{t-lag}: its slots are not written before iteration t + 1
         if (lag > 0 && t - lag >= 1 && check(t - lag, &status)) return status;
         if (t == max_iter) {
@@ -384,7 +409,7 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
             fa.vpot = gb[t % kRing]; fa.gamma = 1.f;
             fa.pot_old = fb[t % kRing]; fa.pot_out = fb[(t + 1) % kRing];
             if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) return POT_ERR_DEVICE;
-            if ((status = enqueue_err_readback(c, L, nparts, host + t % kRing, E.ev[t % kRing], s)) !=
+            if ((status = enqueue_err_readback(c, L, nparts, hdev + t % kRing, E.ev[t % kRing], s)) !=
                 POT_OK)
                 return status;
             if (check(t, &status)) return status;

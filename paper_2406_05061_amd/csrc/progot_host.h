@@ -14,7 +14,7 @@ namespace host {
 
 // Workspace regions of one pair of clouds (byte offsets, 256-byte aligned).
 struct Layout {
-    size_t xk, xsq, ysq, la, lb, xlp, ylp, ytl, f0, f1, g0, g1, pm, ps, errp, errd, xst, yst, chr, chc,
+    size_t xk, xsq, ysq, la, lb, xlp, ylp, ytl, f0, f1, g0, g1, pm, ps, errp, xst, yst, chr, chc,
         n64;
     size_t f2, g2;         // third potential slots of the single-problem Sinkhorn loop
     size_t cm, cmp, mpa;   // general costs: cost matrix, its block sums, map partials

@@ -68,6 +68,13 @@ struct LseJob {
     const float *cmat;
     int64_t ldc;
     int cmat_cols;
+    // The previous f-update's error sum, folded into this update where
+    // lse_update_folds_sum(job) holds (esum_out NULL: none): workgroup 0 adds
+    // the esum_n partials at esum_in into *esum_out in the order of
+    // launch_sum_f32, so the value is the same bits as the separate sum.
+    const float *esum_in;
+    int esum_n;
+    float *esum_out;
 };
 typedef LseJob LseArgs;
 
@@ -105,6 +112,11 @@ int padded_dim_f32(int d);
 
 // Deterministic sum of n float partials into *out (device).
 hipError_t launch_sum_f32(const float *part, int n, float *out, hipStream_t s);
+
+// True when the update of `j` can carry the previous f-update's error sum
+// (the general-cost column kernel on a kept cost matrix), saving the launch
+// of launch_sum_f32.
+bool lse_update_folds_sum(const LseJob &j);
 
 // Per-point squared norms in FP64 (rounded to FP32), optional BF16 hi/lo
 // copies (lp != NULL), and FP64 partial sums of (sum_i x_i, sum_i |x_i|^2)

@@ -662,6 +662,7 @@ void plan_lse_job(LseJob &j) {
 }
 
 hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part) {
+    if (a.esum_out && !lse_update_folds_sum(a)) return hipErrorInvalidValue;
     LseJob j = a;
     if (j.cost_p != 0.f) plan_pcost_job(j);
     else plan_lse_job(j);
@@ -694,7 +695,7 @@ hipError_t plan_lse_update_group(LseJob *jobs, int njobs, GroupPlan *gp) {
     int nerr = 0;
     const int D = padded_dim(jobs[0].d);
     for (int k = 0; k < njobs; ++k) {
-        if (jobs[k].cost_p != 0.f) return hipErrorInvalidValue;
+        if (jobs[k].cost_p != 0.f || jobs[k].esum_out) return hipErrorInvalidValue;
         plan_lse_job(jobs[k]);
         if (jobs[k].precision != 0 || padded_dim(jobs[k].d) != D) return hipErrorInvalidValue;
         jobs[k].blk_begin = blk;

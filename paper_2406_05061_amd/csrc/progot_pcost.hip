@@ -20,8 +20,8 @@
 //     the 256 MB last-level cache, when C fits) serves faster for any d
 //     beyond a handful.
 //   * f-update: pcost_lse_rows, one wave per row of C and column split,
-//     float4 loads (8 in flight per lane), per-lane running (max, sum) in
-//     log2 units with one rescale per 32 values, then a wave reduction;
+//     float4 loads (12 in flight per lane), per-lane running (max, sum) in
+//     log2 units with one rescale per 48 values, then a wave reduction;
 //     with one split (n large enough to fill the chip) the wave writes the
 //     potential and its marginal-error term itself.
 //   * g-update: pcost_lse_cols, 256 columns per workgroup (4 per lane, so a
@@ -185,10 +185,13 @@ __global__ __launch_bounds__(256) void pcost_lse_rows(LseJob J) {
     // of a caller's K x m array need not be)
     const bool vp4 = vp && (reinterpret_cast<uintptr_t>(vp) & 15) == 0;
     float M = kNegBig, s = 0.f;
-    for (int64_t c = c_lo + 4 * lane; live && c < c_hi; c += 256 * 8) {
-        float t[32];
+    // 12 float4 per lane in flight: a row of up to 3072 columns in one round
+    // of loads (a second, short round cost 20-30 % at m = 2800; 16 per lane
+    // costs occupancy)
+    for (int64_t c = c_lo + 4 * lane; live && c < c_hi; c += 256 * 12) {
+        float t[48];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 12; ++u) {
             const int64_t cc = c + 256 * u;
             // cc and ldc are multiples of 4: the float4 stays inside the row
             const f4 cv = cc < c_hi ? *reinterpret_cast<const f4 *>(crow + cc) : f4{0.f, 0.f, 0.f, 0.f};
@@ -207,14 +210,14 @@ __global__ __launch_bounds__(256) void pcost_lse_rows(LseJob J) {
         }
         float cm = kNegBig;
 #pragma unroll
-        for (int e = 0; e < 32; ++e) cm = fmaxf(cm, t[e]);
+        for (int e = 0; e < 48; ++e) cm = fmaxf(cm, t[e]);
         if (cm > M) {
             s *= ex2(M - cm);
             M = cm;
         }
         float a0 = 0.f, a1 = 0.f;
 #pragma unroll
-        for (int e = 0; e < 32; e += 2) {
+        for (int e = 0; e < 48; e += 2) {
             a0 += ex2(t[e] - M);
             a1 += ex2(t[e + 1] - M);
         }
@@ -283,9 +286,34 @@ __global__ __launch_bounds__(256) void pcost_merge(LseJob J) {
 // 8-row chunks, so one split covers kColWaves x more rows per launch and the
 // merge has fewer splits to fold.
 constexpr int kColWaves = 8;
+
+// Sum of n floats in the order of the standalone error sum (thread t < 256
+// adds t, t + 256, ..., then a halving tree in LDS), by a workgroup of any
+// size >= 256; every thread of the workgroup calls it (it holds barriers).
+__device__ __forceinline__ float sum_in_order(const float *__restrict__ part, int n, float *red) {
+    const int tid = threadIdx.x;
+    if (tid < 256) {
+        float v = 0.f;
+        for (int i = tid; i < n; i += 256) v += part[i];
+        red[tid] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
 __global__ __launch_bounds__(64 * kColWaves) void pcost_lse_cols(LseJob J) {
     __shared__ float sm[kColWaves][256], ss[kColWaves][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (J.esum_out && blockIdx.x == 0) {   // uniform over the workgroup
+        const float tot = sum_in_order(J.esum_in, J.esum_n, sm[0]);
+        if (tid == 0) J.esum_out[0] = tot;
+        __syncthreads();   // sm[0] is reused below
+    }
     const int S = J.S;
     const int split = (int)(blockIdx.x % S);
     const int64_t jb = (int64_t)(blockIdx.x / S) * 256;
@@ -700,7 +728,10 @@ hipError_t launch_pcost_merge(const LseJob &j, hipStream_t s) {
     return hipGetLastError();
 }
 
+bool lse_update_folds_sum(const LseJob &j) { return j.cost_p != 0.f && j.cmat && j.cmat_cols; }
+
 hipError_t launch_pcost_partial(const LseJob &j, hipStream_t s) {
+    if (j.esum_out && (!lse_update_folds_sum(j) || !j.esum_in || j.esum_n < 1)) return hipErrorInvalidValue;
     if (!j.cmat) return is_p15(j.cost_p) ? fly_launch_pk<1>(j, s) : fly_launch_pk<0>(j, s);
     if (j.blocks > 0x7fffffff || j.ldc % 4) return hipErrorInvalidValue;
     if (pcost_fused(j))

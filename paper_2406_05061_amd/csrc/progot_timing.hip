@@ -18,6 +18,8 @@ struct Rec {
 struct Timing {
     std::mutex mu;
     bool on = false;
+    int every = 1;                          // time launch 0, every, 2 every, ... of each kind
+    int64_t seq[2] = {0, 0};
     std::vector<Rec> live;                  // both recorded, not yet resolved
     std::vector<hipEvent_t> pool;
     double ms[2] = {0.0, 0.0};
@@ -64,10 +66,10 @@ int resolve(Timing &t) {
 namespace pot {
 
 TimedEvents timing_events(int kind) {
-    (void)kind;
     Timing &t = T();
     std::lock_guard<std::mutex> lk(t.mu);
-    if (!t.on) return {nullptr, nullptr};
+    if (!t.on || kind < 0 || kind > 1) return {nullptr, nullptr};
+    if (t.seq[kind]++ % t.every != 0) return {nullptr, nullptr};
     TimedEvents e{take(t), take(t)};
     if (!e.start || !e.stop) {
         if (e.start) t.pool.push_back(e.start);
@@ -94,15 +96,18 @@ void timing_commit(int kind, TimedEvents e) {
 
 extern "C" {
 
-int pot_timing_enable(int on) {
+int pot_timing_enable(int every) {
+    if (every < 0) return POT_ERR_INVALID;
     Timing &t = T();
     std::lock_guard<std::mutex> lk(t.mu);
     int st = resolve(t);
-    if (on) {
+    if (every) {
         t.ms[0] = t.ms[1] = 0.0;
         t.count[0] = t.count[1] = 0;
+        t.seq[0] = t.seq[1] = 0;
+        t.every = every;
     }
-    t.on = on != 0;
+    t.on = every != 0;
     return st;
 }
 

@@ -557,9 +557,13 @@ class Server:
             pass
 
 
-def timing_enable(on: bool = True) -> None:
-    """Start (and clear) or stop the library's per-launch kernel timing."""
-    _check(lib().pot_timing_enable(1 if on else 0), "timing_enable", False)
+def timing_enable(on: bool = True, every: int = 1) -> None:
+    """Start (and clear) or stop the library's per-launch kernel timing;
+    while on, launches 0, every, 2 every, ... of each timed kernel are
+    timed."""
+    if on and every < 1:
+        raise ValueError("every must be >= 1")
+    _check(lib().pot_timing_enable(int(every) if on else 0), "timing_enable", False)
 
 
 def timing_read():

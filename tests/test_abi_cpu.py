@@ -280,3 +280,13 @@ def test_pcost_divergence_rejects_invalid():
     assert call(X=None) == inv and call(out=None) == inv and call(ws=None) == inv
     assert call(p=0.5) == inv and call(eps=-1.0) == inv and call(tau=0.0) == inv and call(it=0) == inv
     assert call(wsb=nb - 1) == B.POT_ERR_NOMEM
+
+
+def test_timing_enable_rejects_negative_stride():
+    """pot_timing_enable(every): 0 stops, every >= 1 samples, every < 0 is
+    invalid (no device work either way while nothing was timed)."""
+    lib = P.lib()
+    assert lib.pot_timing_enable(-1) == B.POT_ERR_INVALID
+    assert lib.pot_timing_enable(0) == 0
+    with pytest.raises(ValueError):
+        P.timing_enable(True, every=0)

@@ -220,3 +220,25 @@ def test_progot_variants(P, K, alpha_sched, warm, weighted, taus):
     assert map_err(TX.cpu().numpy(), ref.TX, Y) < 1e-3
     chk = P.marginal_check(cl, f, G[-1], info.eps[-1])
     assert chk[0] <= taus[1] * 1.01
+
+
+@pytest.mark.parametrize("cost_p", [0.0, 1.5])
+def test_timing_samples_launches(P, cost_p):
+    """pot_timing_enable(every): a fixed-iteration solve makes 2N + 1
+    potential-update launches (N f- and N g-updates, and the f-update that
+    measures the last iterate's error); stride 1 times all of them, stride 3
+    launches 0, 3, 6, ..."""
+    X, Y = workloads.gmm(seed=11, n=700, m=500, d=16)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), cost_p=cost_p)
+    eps = 0.05 * cl.mean_cost
+    N = 10
+    for every in (1, 3):
+        torch.cuda.synchronize()
+        P.timing_enable(True, every=every)
+        P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=N)
+        torch.cuda.synchronize()
+        ms, count, _, _ = P.timing_read()
+        P.timing_enable(False)
+        print(f"case cost_p={cost_p} every={every}: {count} timed launches, {ms:.3f} ms", flush=True)
+        assert count == -(-(2 * N + 1) // every)
+        assert ms > 0.0

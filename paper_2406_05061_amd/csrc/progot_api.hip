@@ -258,12 +258,45 @@ using pot::LseJob;
 // mapped into the device's address space, so the kernel that forms a scalar
 // (an error sum) stores it there itself and the host reads it once an event
 // after that kernel has completed; no copy command per read-back.
+// The Sinkhorn loop returns while up to two iterations past the returned one
+// may still be queued (the entry points synchronise their stream before they
+// return, but an error return or an internal caller need not), and their
+// error sums land in these slots; `tail` marks the end of the last solve's
+// work on `tail_stream`, and a solve on another stream waits for it before it
+// reuses the slots.
 struct Pinned {
     float *buf = nullptr;
     float *dev = nullptr;   // the same memory, as the device addresses it
-    ~Pinned() { if (buf) (void)hipHostFree(buf); }
+    hipEvent_t tail = nullptr;
+    hipStream_t tail_stream = nullptr;
+    bool tail_set = false;
+    ~Pinned() {
+        if (tail) (void)hipEventDestroy(tail);
+        if (buf) (void)hipHostFree(buf);
+    }
 };
 thread_local Pinned g_pinned;
+
+// Claims the pinned slots for a solve on stream s (see Pinned) and, on
+// destruction, marks the end of the work it enqueued.
+struct SlotClaim {
+    hipStream_t s;
+    bool ok = false;
+    explicit SlotClaim(hipStream_t st) : s(st) {
+        if (!g_pinned.tail && hipEventCreateWithFlags(&g_pinned.tail, hipEventDisableTiming) != hipSuccess) {
+            g_pinned.tail = nullptr;
+            return;
+        }
+        if (g_pinned.tail_set && g_pinned.tail_stream != s && hipEventSynchronize(g_pinned.tail) != hipSuccess)
+            return;
+        ok = true;
+    }
+    ~SlotClaim() {
+        if (!ok) return;
+        g_pinned.tail_set = hipEventRecord(g_pinned.tail, s) == hipSuccess;
+        g_pinned.tail_stream = s;
+    }
+};
 
 float *pinned_slot(float **dev) {
     if (!g_pinned.buf) {
@@ -359,6 +392,8 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
     float *hdev = nullptr;
     float *host = pinned_slot(&hdev);
     if (!host) return POT_ERR_DEVICE;
+    SlotClaim claim(s);
+    if (!claim.ok) return POT_ERR_DEVICE;
     Events E;
     for (hipEvent_t &e : E.ev) POT_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     const int lag = pick_lag(c);

@@ -242,3 +242,26 @@ def test_timing_samples_launches(P, cost_p):
         print(f"case cost_p={cost_p} every={every}: {count} timed launches, {ms:.3f} ms", flush=True)
         assert count == -(-(2 * N + 1) // every)
         assert ms > 0.0
+
+
+def test_solves_alternating_streams(P):
+    """Back-to-back solves of one pair on two streams, with no host
+    synchronisation between them: a solve can return while the iterations
+    queued past its result still run, and the next solve on another stream
+    waits for that tail before it reuses the thread's read-back slots (and
+    the pair's potential buffers), so every result equals the solve on the
+    default stream, bit for bit."""
+    X, Y = workloads.gmm(seed=12, n=2000, m=1500, d=16)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y))
+    eps = 0.05 * cl.mean_cost
+    f0, g0, i0 = P.sinkhorn_solve(cl, eps, tau=1e-3)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    for k in range(6):
+        with torch.cuda.stream(streams[k % 2]):
+            outs.append(P.sinkhorn_solve(cl, eps, tau=1e-3))
+    torch.cuda.synchronize()
+    for f, g, info in outs:
+        assert info.iters == i0.iters
+        assert torch.equal(f, f0) and torch.equal(g, g0)

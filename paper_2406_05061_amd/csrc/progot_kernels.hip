@@ -366,27 +366,40 @@ __global__ __launch_bounds__(256) void cloud_norms(const float *__restrict__ X, 
     sqn[i] = (float)s;
 }
 
-// Per-block FP64 sums of every feature and of |x|^2 over a contiguous row range.
+// Per-block FP64 sums of every feature and of |x|^2 over a contiguous row
+// range.  The 256 threads form G = 256/d groups of d threads (1 <= d <= 256):
+// thread f of group g adds feature f of rows r0 + g, r0 + g + G, ... (a group
+// reads whole rows, so the loads are contiguous), and the G group sums are
+// folded in LDS in group order, so the result is deterministic.
 __global__ __launch_bounds__(256) void cloud_stats(const float *__restrict__ X, int64_t n, int d,
                                                    const float *__restrict__ sqn, int64_t rows_per_blk,
                                                    double *__restrict__ part) {
     __shared__ double red[256];
+    const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
     const int64_t r1 = r0 + rows_per_blk < n ? r0 + rows_per_blk : n;
-    for (int f = threadIdx.x; f < d; f += 256) {
-        double s = 0.0;
-        for (int64_t r = r0; r < r1; ++r) s += X[r * d + f];
-        part[(int64_t)blockIdx.x * (d + 1) + f] = s;
+    const int G = 256 / d;
+    const int g = tid / d, f = tid - g * d;
+    double s = 0.0;
+    if (g < G)
+        for (int64_t r = r0 + g; r < r1; r += G) s += X[r * d + f];
+    red[tid] = s;
+    __syncthreads();
+    if (tid < d) {
+        double t = 0.0;
+        for (int k = 0; k < G; ++k) t += red[k * d + tid];
+        part[(int64_t)blockIdx.x * (d + 1) + tid] = t;
     }
+    __syncthreads();
     double q = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) q += sqn[r];
-    red[threadIdx.x] = q;
+    for (int64_t r = r0 + tid; r < r1; r += 256) q += sqn[r];
+    red[tid] = q;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (d + 1) + d] = red[0];
+    if (tid == 0) part[(int64_t)blockIdx.x * (d + 1) + d] = red[0];
 }
 
 // Fold nblk x (d+1) partials into the first row, fixed order.
@@ -741,8 +754,10 @@ hipError_t launch_sum_f32(const float *part, int n, float *out, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Workgroups of the moments pass: >= 64 rows each, at most 256 (the fold
+// reads nblk x (d + 1) partials in one workgroup).
 int cloud_stat_blocks(int64_t n) {
-    const int64_t b = (n + 1023) / 1024;
+    const int64_t b = (n + 63) / 64;
     return (int)(b < 256 ? (b < 1 ? 1 : b) : 256);
 }
 

@@ -619,7 +619,10 @@ int padded_dim(int d) {
     return 256;
 }
 
-int qb_for(int D) { return D >= 256 ? 1 : 2; }
+// Row blocks of 16 per wave in the FP32 map: one from D = 128 up (two at
+// D = 128 took 256 VGPRs + 164 AGPRs, one wave per SIMD, and ran 3.5 %
+// slower than one block at two waves per SIMD).
+int qb_for(int D) { return D >= 128 ? 1 : 2; }
 // Row blocks per wave of the potential kernel: four for D <= 64 (each column
 // fragment read from LDS feeds four MFMA chains; measured 5 % faster on the
 // benchmark workload than two, at two waves per SIMD instead of three).
@@ -794,7 +797,7 @@ hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s) {
         case 16: e = map_launch_t<16, 2>(a, scale2, bscale, s); break;
         case 32: e = map_launch_t<32, 2>(a, scale2, bscale, s); break;
         case 64: e = map_launch_t<64, 2>(a, scale2, bscale, s); break;
-        case 128: e = map_launch_t<128, 2>(a, scale2, bscale, s); break;
+        case 128: e = map_launch_t<128, 1>(a, scale2, bscale, s); break;
         default: e = map_launch_t<256, 1>(a, scale2, bscale, s); break;
     }
     return e;

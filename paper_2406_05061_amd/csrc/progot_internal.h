@@ -8,9 +8,8 @@
 
 namespace pot {
 
-// Rows handled by one workgroup of the log-sum-exp kernel and the map kernel.
+// Rows handled by one workgroup of the log-sum-exp kernel.
 int lse_rows_per_block(int d);
-int map_rows_per_block(int d);
 constexpr int kMaxSplit = 32;       // column splits of the log-sum-exp kernel
 constexpr int kReduceBlock = 256;   // threads of the per-row kernels
 

@@ -619,10 +619,6 @@ int padded_dim(int d) {
     return 256;
 }
 
-// Row blocks of 16 per wave in the FP32 map: one from D = 128 up (two at
-// D = 128 took 256 VGPRs + 164 AGPRs, one wave per SIMD, and ran 3.5 %
-// slower than one block at two waves per SIMD).
-int qb_for(int D) { return D >= 128 ? 1 : 2; }
 // Row blocks per wave of the potential kernel: four for D <= 64 (each column
 // fragment read from LDS feeds four MFMA chains; measured 5 % faster on the
 // benchmark workload than two, at two waves per SIMD instead of three).
@@ -631,7 +627,6 @@ constexpr int lse_qb(int D) { return D <= 64 ? 4 : (D >= 256 ? 1 : 2); }
 }  // namespace
 
 int lse_rows_per_block(int d) { return 64 * lse_qb(padded_dim(d)); }
-int map_rows_per_block(int d) { return 64 * qb_for(padded_dim(d)); }
 
 int padded_dim_f32(int d) { return padded_dim(d); }
 
@@ -794,9 +789,12 @@ hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s) {
     if (a.precision != 0) {
         e = launch_map_bf16(a, scale2, bscale, s);
     } else switch (padded_dim(a.d)) {
-        case 16: e = map_launch_t<16, 2>(a, scale2, bscale, s); break;
-        case 32: e = map_launch_t<32, 2>(a, scale2, bscale, s); break;
-        case 64: e = map_launch_t<64, 2>(a, scale2, bscale, s); break;
+        // one 16-row block per wave at every width: two (at D <= 64, and
+        // at D = 128 with 164 AGPRs spilled over) measured 32-35 % slower at
+        // D = 16, 32, 64 and 3.5 % at D = 128, for the lower occupancy
+        case 16: e = map_launch_t<16, 1>(a, scale2, bscale, s); break;
+        case 32: e = map_launch_t<32, 1>(a, scale2, bscale, s); break;
+        case 64: e = map_launch_t<64, 1>(a, scale2, bscale, s); break;
         case 128: e = map_launch_t<128, 1>(a, scale2, bscale, s); break;
         default: e = map_launch_t<256, 1>(a, scale2, bscale, s); break;
     }

@@ -826,8 +826,12 @@ hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s) {
 hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     const bool x3 = a.precision == 2;
     switch (bf16_dim(a.d)) {
-        case 32: return x3 ? map_bf16_t<32, 4, 2>(a, scale2, bscale, s) : map_bf16_t<32, 4, 1>(a, scale2, bscale, s);
-        case 64: return x3 ? map_bf16_t<64, 4, 2>(a, scale2, bscale, s) : map_bf16_t<64, 4, 1>(a, scale2, bscale, s);
+        // two 16-row blocks per wave up to D = 128: four at D = 32 and 64
+        // measured 23-27 % slower (two waves per SIMD instead of three or
+        // four), one at D = 128 35-53 % slower (each LDS fragment then feeds
+        // half the MFMAs)
+        case 32: return x3 ? map_bf16_t<32, 2, 2>(a, scale2, bscale, s) : map_bf16_t<32, 2, 1>(a, scale2, bscale, s);
+        case 64: return x3 ? map_bf16_t<64, 2, 2>(a, scale2, bscale, s) : map_bf16_t<64, 2, 1>(a, scale2, bscale, s);
         case 128: return x3 ? map_bf16_t<128, 2, 2>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1>(a, scale2, bscale, s);
         default:
             if (!a.out_sqn)

@@ -402,13 +402,20 @@ __global__ __launch_bounds__(256) void cloud_stats(const float *__restrict__ X, 
     if (tid == 0) part[(int64_t)blockIdx.x * (d + 1) + d] = red[0];
 }
 
-// Fold nblk x (d+1) partials into the first row, fixed order.
+// Fold nblk x (d+1) partials (nblk <= 256) into the first row: workgroup f
+// folds column f, thread t taking partial t, then a halving tree in LDS, so
+// the order is fixed.  Each workgroup writes only the element of the first
+// row that it alone reads.
 __global__ __launch_bounds__(256) void stats_fold(double *__restrict__ part, int nblk, int d) {
-    for (int f = threadIdx.x; f <= d; f += 256) {
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * (d + 1) + f];
-        part[f] = s;
+    __shared__ double red[256];
+    const int f = blockIdx.x, tid = threadIdx.x;
+    red[tid] = tid < nblk ? part[(int64_t)tid * (d + 1) + f] : 0.0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
     }
+    if (tid == 0) part[f] = red[0];
 }
 
 __global__ __launch_bounds__(256) void log_weights(const float *__restrict__ w, int64_t n, float *__restrict__ out) {
@@ -767,7 +774,8 @@ hipError_t launch_cloud_prep(const float *X, int64_t n, int d, float *sqn, void 
     if (e != hipSuccess || !stats_part) return e;
     const int64_t rpb = (n + nblk - 1) / nblk;
     hipLaunchKernelGGL(cloud_stats, dim3(nblk), dim3(256), 0, s, X, n, d, sqn, rpb, stats_part);
-    hipLaunchKernelGGL(stats_fold, dim3(1), dim3(256), 0, s, stats_part, nblk, d);
+    if (nblk > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stats_fold, dim3(d + 1), dim3(256), 0, s, stats_part, nblk, d);
     return hipGetLastError();
 }
 

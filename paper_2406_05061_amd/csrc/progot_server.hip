@@ -300,14 +300,22 @@ int pot_server_step(pot_server *S, int32_t *n_active, int32_t *n_finished) {
         q[head] = (int)std::min<double>(kMaxSub, std::max<double>(q[head], need));
         Q = std::max(Q, q[head]);
     }
+    // Every sub-step's job tables go into the pinned mirror back to back (f
+    // then g per sub-step, each in runs of one dimension class), planned on
+    // the host, uploaded in one copy, then launched in order.
     const int A = S->max_active;
+    struct Group {
+        int off, n;
+        pot::GroupPlan plan;
+    };
+    std::vector<Group> groups;
+    int used = 0;   // entries of the mirror written this tick (<= kMaxSub x 2 x A)
     for (int sub = 0; sub < Q; ++sub) {
-        pot::LseJob *fj = S->jobs_host + (size_t)sub * 2 * A, *gj = fj + A;
-        pot::LseJob *fd = S->jobs_dev + (size_t)sub * 2 * A, *gd = fd + A;
         std::vector<int> idx;   // requests iterating in this sub-step, by dimension class
         for (int i = 0; i < ns; ++i)
             if (sub < q[i]) idx.push_back(i);
         const int nj = (int)idx.size();
+        pot::LseJob *fj = S->jobs_host + used, *gj = fj + nj;
         for (int k = 0; k < nj; ++k) {
             Req *r = solving[idx[k]];
             const int it = r->t + sub + 1;   // iteration run by this sub-step
@@ -328,18 +336,25 @@ int pot_server_step(pot_server *S, int32_t *n_active, int32_t *n_finished) {
             gj[k] = g;
         }
         for (int pass = 0; pass < 2; ++pass) {
-            pot::LseJob *jh = pass == 0 ? fj : gj;
-            pot::LseJob *jd = pass == 0 ? fd : gd;
+            const int base = used + pass * nj;
             int i = 0;
             while (i < nj) {
                 int j = i;
                 const int D = pot::padded_dim_f32(solving[idx[i]]->c.d);
                 while (j < nj && pot::padded_dim_f32(solving[idx[j]]->c.d) == D) ++j;
-                POT_TRY(pot::launch_lse_update_group(jh + i, j - i, jd + i, nullptr, S->s));
+                Group grp{base + i, j - i, {}};
+                POT_TRY(pot::plan_lse_update_group(S->jobs_host + grp.off, grp.n, &grp.plan));
+                groups.push_back(grp);
                 i = j;
             }
         }
+        used += 2 * nj;
     }
+    if (used > 0)
+        POT_TRY(hipMemcpyAsync(S->jobs_dev, S->jobs_host, sizeof(pot::LseJob) * used, hipMemcpyHostToDevice,
+                               S->s));
+    for (const Group &grp : groups)
+        POT_TRY(pot::enqueue_lse_update_group(S->jobs_dev + grp.off, grp.n, grp.plan, nullptr, S->s));
     POT_TRY(hipMemcpyAsync(S->ctl_host, S->ctl_dev, sizeof(int) * 2 * A, hipMemcpyDeviceToHost, S->s));
     POT_TRY(hipStreamSynchronize(S->s));
 

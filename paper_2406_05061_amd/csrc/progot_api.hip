@@ -1,8 +1,9 @@
 // C ABI and host driver of the progressive entropic OT hot path (gfx950).
 //
-// The driver owns no device memory: every buffer is a view into the caller's
+// The host code owns no device memory: every buffer is a view into the caller's
 // workspace, laid out by plan() from (n, m, d, precision).  Host-side state is
-// limited to a small per-thread pinned buffer for scalar read-backs.
+// limited to a small per-thread pinned buffer for scalar read-backs (with the
+// event that marks the end of the last solve's work on it).
 
 #include "progot.h"
 #include "progot_host.h"

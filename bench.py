@@ -422,7 +422,7 @@ def main():
                     help="pcost_4i_d47: keep the cost matrix or form it in every update")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16384)
-    ap.add_argument("--cpu-iters", type=int, default=24,
+    ap.add_argument("--cpu-iters", type=int, default=48,
                     help="oracle iterations of the CPU baseline sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to scale "

@@ -679,11 +679,15 @@ void plan_pcost_job(LseJob &j) {
     int64_t tiles, S, per;
     if (!j.cmat) {
         // on the fly: QB rows per workgroup, columns split so that the grid
-        // holds >= 1024 workgroups, in whole tiles of kMapTJ columns
+        // holds >= 2048 workgroups as far as the split partials allow
+        // (kMaxSplit x max(n, m) floats: kMaxSplit max(n, m) / nu splits of
+        // nu outputs), in whole tiles of kMapTJ columns.  The g-update of a
+        // pair with m << n has few row tiles and needs the extra splits: at
+        // 11000 x 2800 a cap of 32 left it 352 workgroups, ~1.4 waves per SIMD
         const int QBr = 256 / (pmap_dim(j.d) <= 48 ? 1 : pmap_dim(j.d) / 32);
         tiles = (j.nu + QBr - 1) / QBr;
-        S = 1;
-        while (S * tiles < 1024 && S < kMaxSplit) S <<= 1;
+        const int64_t cap = kMaxSplit * std::max(j.nu, j.nv) / j.nu;
+        S = std::min<int64_t>(cap, std::max<int64_t>(1, (2048 + tiles - 1) / tiles));
         per = (j.nv + S - 1) / S;
         per = std::max<int64_t>(2 * kMapTJ, (per + kMapTJ - 1) / kMapTJ * kMapTJ);
         S = (j.nv + per - 1) / per;

@@ -28,6 +28,8 @@ def main() -> None:
     ap.add_argument("--m", type=int, default=0, help="target points (default n)")
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--cost-p", type=float, default=0.0)
+    ap.add_argument("--cost-mode", default="auto", choices=["auto", "keep", "on_the_fly"],
+                    help="general cost: keep the cost matrix or form it in every update")
     ap.add_argument("--theta", type=float, default=1.0)
     ap.add_argument("--prec", default="bf16", choices=["fp32", "bf16", "bf16x3"])
     ap.add_argument("--iters", type=int, default=1)
@@ -44,7 +46,8 @@ def main() -> None:
         X, Y = workloads.gmm(seed=args.seed, n=args.n, m=m, d=args.d, n_comp=10)
     else:
         X, Y = workloads.sphere(seed=args.seed, n=args.n, m=m, d=args.d, n_clusters=64)
-    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=args.prec, cost_p=args.cost_p)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=args.prec, cost_p=args.cost_p,
+                          cost_mode=args.cost_mode)
     eps = args.theta * cl.mean_cost / 20.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()

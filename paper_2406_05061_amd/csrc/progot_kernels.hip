@@ -667,7 +667,11 @@ void plan_lse_job(LseJob &j) {
         S = q;
         if (S > max_by_cols) S = max_by_cols;
     }
-    if (S > kMaxSplit) S = kMaxSplit;
+    // the split partials hold kMaxSplit x max(n, m) floats: up to
+    // kMaxSplit max(nu, nv) / nu splits of nu rows (a flat cap of kMaxSplit
+    // left the update of a pair with nu << nv a fraction of the chip)
+    const int64_t cap = kMaxSplit * std::max(j.nu, j.nv) / std::max<int64_t>(j.nu, 1);
+    if (S > cap) S = cap;
     if (S < 1) S = 1;
     j.S = (int)S;
     j.cps = (j.nv + S - 1) / S;

@@ -25,7 +25,9 @@ def P():
 
 
 @pytest.mark.parametrize("n,m,d", [(256, 256, 4), (1000, 777, 64), (300, 513, 100), (200, 700, 256),
-                                   (1, 9, 7)])
+                                   (1, 9, 7),
+                                   # n << m: > 32 column splits, the last ones empty
+                                   (130, 40000, 64)])
 def test_bf16x3_fixed_iterations(P, n, m, d):
     X, Y = workloads.sphere(seed=200 + d, n=n, m=m, d=d, n_clusters=6)
     a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)

@@ -36,6 +36,8 @@ SHAPES = [
     (2048, 1500, 64),   # several tiles, ragged tail
     (300, 513, 100),    # d padded to 128
     (64, 2000, 256),    # largest d, few rows (split columns)
+    (257, 9000, 16),    # n << m: the f-update takes more than 32 column splits
+    (9000, 200, 64),    # n >> m: so does the g-update
     (1, 5, 3),          # degenerate sizes
     (7, 1, 3),
 ]

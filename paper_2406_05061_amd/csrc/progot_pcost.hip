@@ -698,11 +698,13 @@ void plan_pcost_job(LseJob &j) {
         return;
     }
     if (!j.cmat_cols) {
-        // rows of C: 4 rows (one per wave) per workgroup, >= 256 columns per split
+        // rows of C: 4 rows (one per wave) per workgroup, >= 256 columns per
+        // split, as many splits as the split partials hold (kMaxSplit max(n,
+        // m) / nu), so a pair with few rows still fills the chip
         tiles = (j.nu + 3) / 4;
         S = tiles >= 2048 ? 1 : (2048 + tiles - 1) / tiles;
         S = std::min<int64_t>(S, std::max<int64_t>(1, j.nv / 256));
-        S = std::min<int64_t>(S, kMaxSplit);
+        S = std::min<int64_t>(S, kMaxSplit * std::max(j.nu, j.nv) / j.nu);
         per = (j.nv + S - 1) / S;
         per = (per + 3) / 4 * 4;
     } else {

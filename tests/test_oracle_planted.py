@@ -1,0 +1,88 @@
+"""Planted mistakes in the oracle (CPU only).  Each plausible slip -- the
+Euclidean instead of the squared distance, a cross term counted once, a
+dropped 1/eps or a flipped sign in the log-sum-exp, the wrong exponent of
+the conjugate gradient, a missing 1/p, a flipped McCann step -- is patched
+into the oracle module for one test, and a committed pin must then fail.
+This is what makes the pins a check of the oracle rather than of itself."""
+import importlib
+
+import numpy as np
+import pytest
+
+from oracle import pcost
+import tests.test_oracle_sinkhorn as pins
+import tests.test_oracle_pcost as ppins
+
+# the module (the package re-exports its sinkhorn function under that name)
+osk = importlib.import_module("oracle.sinkhorn")
+
+_cost = osk.cost_matrix
+_softmin_rows = osk.softmin_rows
+_grad_h_star = pcost.grad_h_star
+_h_p = pcost.h_p
+_map_p = pcost.entropic_map_p
+
+
+def _cross_term_once(X, Y):
+    X, Y = np.asarray(X, np.float64), np.asarray(Y, np.float64)
+    return (X ** 2).sum(1)[:, None] + (Y ** 2).sum(1)[None, :] - X @ Y.T
+
+
+COST_MISTAKES = {
+    "euclidean": lambda X, Y: np.sqrt(_cost(X, Y)),
+    "cross_term_once": _cross_term_once,
+    "half": lambda X, Y: 0.5 * _cost(X, Y),
+}
+
+SOFTMIN_MISTAKES = {
+    "no_1_over_eps": lambda C, v, eps: _softmin_rows(C, v, 1.0),
+    "cost_sign": lambda C, v, eps: _softmin_rows(-C, v, eps),
+}
+
+
+@pytest.mark.parametrize("name", sorted(COST_MISTAKES))
+def test_cost_mistakes_fail_a_pin(monkeypatch, name):
+    """The textbook-scaling pin builds its kernel from the correct cost, the
+    oracle's Sinkhorn from the planted one."""
+    monkeypatch.setattr(osk, "cost_matrix", COST_MISTAKES[name])
+    with pytest.raises(AssertionError):
+        pins.test_matches_textbook_scaling_iterations()
+
+
+@pytest.mark.parametrize("name", sorted(SOFTMIN_MISTAKES))
+def test_update_mistakes_fail_a_pin(monkeypatch, name):
+    monkeypatch.setattr(osk, "softmin_rows", SOFTMIN_MISTAKES[name])
+    with pytest.raises(AssertionError):
+        pins.test_matches_textbook_scaling_iterations()
+
+
+def test_conjugate_exponent_mistake_fails_a_pin(monkeypatch):
+    # grad h*(w) = sign(w)|w|^(p-1) instead of |w|^(1/(p-1))
+    monkeypatch.setattr(pcost, "grad_h_star",
+                        lambda W, p: np.sign(W) * np.abs(np.asarray(W, np.float64)) ** (p - 1.0))
+    with pytest.raises(AssertionError):
+        ppins.test_conjugate_identities(1.5)
+
+
+def test_missing_one_over_p_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(pcost, "h_p", lambda Z, p: _h_p(Z, p) * p)
+    with pytest.raises(AssertionError):
+        ppins.test_h_exact_values()
+
+
+def test_flipped_mccann_step_fails_a_pin(monkeypatch):
+    # x + grad h*(...) instead of x - grad h*(...)
+    monkeypatch.setattr(pcost, "entropic_map_p",
+                        lambda Xq, Y, g, eps, p, alpha=1.0: 2 * np.asarray(Xq, np.float64)
+                        - _map_p(Xq, Y, g, eps, p, alpha))
+    with pytest.raises(AssertionError):
+        ppins.test_map_is_x_minus_grad_h_star_of_potential_gradient(1.5)
+
+
+def test_pins_pass_on_the_unpatched_oracle():
+    """The same pins, unpatched, pass (so the failures above come from the
+    planted mistakes)."""
+    pins.test_matches_textbook_scaling_iterations()
+    ppins.test_conjugate_identities(1.5)
+    ppins.test_h_exact_values()
+    ppins.test_map_is_x_minus_grad_h_star_of_potential_gradient(1.5)

@@ -2,16 +2,19 @@
 Euclidean instead of the squared distance, a cross term counted once, a
 dropped 1/eps or a flipped sign in the log-sum-exp, the wrong exponent of
 the conjugate gradient, a missing 1/p, a flipped McCann step -- is patched
-into the oracle module for one test, and a committed pin must then fail.
+into the oracle module for one test, and a committed pin must then fail;
+so are the schedule slips (alpha_k as a share of the whole path, progress
+as a plain sum of the alpha_k, eps without its 1/20).
 This is what makes the pins a check of the oracle rather than of itself."""
 import importlib
 
 import numpy as np
 import pytest
 
-from oracle import pcost
-import tests.test_oracle_sinkhorn as pins
+from oracle import pcost, schedules
 import tests.test_oracle_pcost as ppins
+import tests.test_oracle_progot as spins
+import tests.test_oracle_sinkhorn as pins
 
 # the module (the package re-exports its sinkhorn function under that name)
 osk = importlib.import_module("oracle.sinkhorn")
@@ -86,3 +89,40 @@ def test_pins_pass_on_the_unpatched_oracle():
     ppins.test_conjugate_identities(1.5)
     ppins.test_h_exact_values()
     ppins.test_map_is_x_minus_grad_h_star_of_potential_gradient(1.5)
+
+
+_alpha = schedules.alpha_schedule
+
+
+def _alpha_unnormalised(K, kind="constant"):
+    # alpha_k = t_k - t_{k-1}: the step as a share of the whole path rather
+    # than of the rest of it
+    t = schedules.progress(_alpha(K, kind))
+    a = np.diff(np.concatenate([[0.0], t]))
+    a[-1] = 1.0
+    return a
+
+
+def test_unnormalised_alpha_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(schedules, "alpha_schedule", _alpha_unnormalised)
+    with pytest.raises(AssertionError):
+        spins.test_alpha_schedule_golden("accelerated")
+
+
+def test_progress_as_cumulative_sum_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(schedules, "progress", lambda alpha: np.cumsum(np.asarray(alpha, np.float64)))
+    with pytest.raises(AssertionError):
+        spins.test_alpha_schedule_golden("constant")
+
+
+def test_eps_without_the_twentieth_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(schedules, "eps_mean_cost",
+                        lambda X, Y, theta=1.0: float(theta * _cost(X, Y).mean()))
+    with pytest.raises(AssertionError):
+        spins.test_eps_mean_cost_closed_form()
+
+
+def test_schedule_pins_pass_unpatched():
+    spins.test_alpha_schedule_golden("accelerated")
+    spins.test_alpha_schedule_golden("constant")
+    spins.test_eps_mean_cost_closed_form()

@@ -4,14 +4,17 @@ dropped 1/eps or a flipped sign in the log-sum-exp, the wrong exponent of
 the conjugate gradient, a missing 1/p, a flipped McCann step -- is patched
 into the oracle module for one test, and a committed pin must then fail;
 so are the schedule slips (alpha_k as a share of the whole path, progress
-as a plain sum of the alpha_k, eps without its 1/20).
+as a plain sum of the alpha_k, eps without its 1/20) and the metrics slips
+(the divergence without its 1/2, a flipped entropy sign, <P, C> as a
+product of sums).
 This is what makes the pins a check of the oracle rather than of itself."""
 import importlib
 
 import numpy as np
 import pytest
 
-from oracle import pcost, schedules
+from oracle import metrics, pcost, schedules
+import tests.test_oracle_metrics as mpins
 import tests.test_oracle_pcost as ppins
 import tests.test_oracle_progot as spins
 import tests.test_oracle_sinkhorn as pins
@@ -126,3 +129,40 @@ def test_schedule_pins_pass_unpatched():
     spins.test_alpha_schedule_golden("accelerated")
     spins.test_alpha_schedule_golden("constant")
     spins.test_eps_mean_cost_closed_form()
+
+
+_ot_value = metrics.ot_value
+_p_log_p = metrics.p_log_p
+
+
+def _divergence_without_half(a, X, b, Y, eps=None, tau=1e-6, max_iter=100_000, cost_p=None):
+    if eps is None:
+        eps = metrics.eps_divergence_default(Y, cost_p)
+    oxy = _ot_value(a, X, b, Y, eps, tau, max_iter, cost_p)
+    oxx = _ot_value(a, X, a, X, eps, tau, max_iter, cost_p)
+    oyy = _ot_value(b, Y, b, Y, eps, tau, max_iter, cost_p)
+    return oxy - (oxx + oyy), oxy, oxx, oyy, eps
+
+
+def test_divergence_without_half_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(metrics, "sinkhorn_divergence", _divergence_without_half)
+    with pytest.raises(AssertionError):
+        mpins.test_divergence_translation_identity()
+
+
+def test_entropy_sign_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(metrics, "p_log_p", lambda P: -_p_log_p(P))
+    with pytest.raises(AssertionError):
+        mpins.test_primal_parts_match_the_dual()
+
+
+def test_transport_cost_as_product_of_sums_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(metrics, "transport_cost",
+                        lambda P, C: float(np.asarray(P, np.float64).sum() * np.asarray(C).mean()))
+    with pytest.raises(AssertionError):
+        mpins.test_primal_parts_match_the_dual()
+
+
+def test_metrics_pins_pass_unpatched():
+    mpins.test_divergence_translation_identity()
+    mpins.test_primal_parts_match_the_dual()

@@ -64,6 +64,19 @@ def tau_schedule(K: int, first: float, last: float) -> np.ndarray:
     return np.linspace(first, last, K)
 
 
+def eps_zero(C) -> float:
+    """eps_0 of Alg. 4 (its first set line): the mean of the source-target
+    cost matrix C over all pairs, divided by 20."""
+    return float(np.asarray(C, dtype=np.float64).mean() / 20.0)
+
+
+def holdout_score(Y_test, TY) -> float:
+    """error_p of Alg. 4: sum over the hold-out targets of the squared
+    distance |y~ - T(y~)|^2 between each point and its image."""
+    D = np.asarray(Y_test, dtype=np.float64) - np.asarray(TY, dtype=np.float64)
+    return float((D ** 2).sum())
+
+
 def eps_scheduler(a, X, b, Y, alpha, Y_test, s_grid=None, beta0: float = 5.0,
                   tau: float = 1e-3, max_iter: int = 10_000, cost_p=None):
     """Alg. 4 (eps-scheduler).
@@ -91,7 +104,7 @@ def eps_scheduler(a, X, b, Y, alpha, Y_test, s_grid=None, beta0: float = 5.0,
         from . import pcost
         cost = lambda U, V: pcost.cost_matrix_p(U, V, cost_p)
         tmap = lambda Q, V, g, eps, alpha: pcost.entropic_map_p(Q, V, g, eps, cost_p, alpha=alpha)
-    eps0 = float(cost(X, Y).mean() / 20.0)
+    eps0 = eps_zero(cost(X, Y))
     Cyy = cost(Y, Y)
     sigma = float(Cyy.mean() / 20.0)
     errors = []
@@ -99,7 +112,7 @@ def eps_scheduler(a, X, b, Y, alpha, Y_test, s_grid=None, beta0: float = 5.0,
         eps = s * sigma
         res = sinkhorn(b, Y, b, Y, eps, tau, max_iter=max_iter, C=Cyy)
         Ty = tmap(Y_test, Y, res.g, eps, alpha=1.0)
-        errors.append(float(((np.asarray(Y_test, np.float64) - Ty) ** 2).sum()))
+        errors.append(holdout_score(Y_test, Ty))
     p_star = int(np.argmin(errors))
     eps_final = float(s_grid[p_star] * sigma)
     if K == 1:

@@ -4,7 +4,9 @@ dropped 1/eps or a flipped sign in the log-sum-exp, the wrong exponent of
 the conjugate gradient, a missing 1/p, a flipped McCann step -- is patched
 into the oracle module for one test, and a committed pin must then fail;
 so are the schedule slips (alpha_k as a share of the whole path, progress
-as a plain sum of the alpha_k, eps without its 1/20) and the metrics slips
+as a plain sum of the alpha_k, eps without its 1/20, Alg. 4's eps_0 without
+its 1/20, its hold-out score unsquared or averaged, the warm start scaled by
+the previous step's alpha) and the metrics slips
 (the divergence without its 1/2, a flipped entropy sign, <P, C> as a
 product of sums).
 This is what makes the pins a check of the oracle rather than of itself."""
@@ -13,6 +15,7 @@ import importlib
 import numpy as np
 import pytest
 
+import oracle as oracle_pkg
 from oracle import metrics, pcost, schedules
 import tests.test_oracle_metrics as mpins
 import tests.test_oracle_pcost as ppins
@@ -125,10 +128,74 @@ def test_eps_without_the_twentieth_fails_a_pin(monkeypatch):
         spins.test_eps_mean_cost_closed_form()
 
 
+def test_alg4_eps0_without_the_twentieth_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(schedules, "eps_zero", lambda C: float(np.asarray(C).mean()))
+    with pytest.raises(AssertionError):
+        spins.test_eps_scheduler_eps0_closed_form()
+
+
+_score = schedules.holdout_score
+
+
+def test_alg4_unsquared_score_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(schedules, "holdout_score",
+                        lambda Yt, TY: float(np.linalg.norm(np.asarray(Yt, np.float64)
+                                                            - np.asarray(TY), axis=1).sum()))
+    with pytest.raises(AssertionError):
+        spins.test_eps_scheduler_score_large_eps_limit()
+
+
+def test_alg4_mean_score_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(schedules, "holdout_score",
+                        lambda Yt, TY: _score(Yt, TY) / np.asarray(Yt).shape[0])
+    with pytest.raises(AssertionError):
+        spins.test_eps_scheduler_score_large_eps_limit()
+
+
+_progot = importlib.import_module("oracle.progot").progot
+
+
+def test_warm_start_from_previous_alpha_fails_a_pin(monkeypatch):
+    # (1 - alpha_{k-1}) instead of the printed (1 - alpha_k)
+    monkeypatch.setattr(oracle_pkg, "progot",
+                        lambda *a, **k: _progot(*a, **{**k, "warm_start": "alpha_prev"}))
+    with pytest.raises(AssertionError):
+        spins.test_last_step_starts_cold()
+
+
+def _progot_unscaled_warm_start(a, X, b, Y, K, n_iter=None, **_):
+    """Alg. 2 with the previous potentials reused unscaled (no (1 - alpha_k)
+    factor), built from the oracle's own steps."""
+    al = schedules.alpha_schedule(K)
+    Xk = np.asarray(X, np.float64).copy()
+    f, g = np.zeros(Xk.shape[0]), np.zeros(np.asarray(Y).shape[0])
+    G, eps = np.zeros((K, g.shape[0])), np.zeros(K)
+    X_last = Xk
+    for k in range(K):
+        C = _cost(Xk, Y)
+        eps[k] = C.mean() / 20.0
+        r = osk.sinkhorn(a, Xk, b, Y, eps[k], 0.0, f, g, n_iter=n_iter, C=C)
+        f, g = r.f, r.g
+        G[k] = g
+        X_last = Xk
+        Xk = oracle_pkg.entropic_map(Xk, Y, g, eps[k], alpha=al[k])
+    return importlib.import_module("oracle.progot").ProgOTResult(
+        f=f, G=G, eps=eps, alpha=al, X_last=X_last, TX=Xk)
+
+
+def test_warm_start_unscaled_fails_a_pin(monkeypatch):
+    monkeypatch.setattr(oracle_pkg, "progot", _progot_unscaled_warm_start)
+    with pytest.raises(AssertionError):
+        spins.test_last_step_starts_cold()
+
+
 def test_schedule_pins_pass_unpatched():
     spins.test_alpha_schedule_golden("accelerated")
     spins.test_alpha_schedule_golden("constant")
     spins.test_eps_mean_cost_closed_form()
+    spins.test_eps_scheduler_eps0_closed_form()
+    spins.test_eps_scheduler_score_large_eps_limit()
+    spins.test_last_step_starts_cold()
 
 
 _ot_value = metrics.ot_value

@@ -104,6 +104,61 @@ def test_eps_scheduler_structure():
     np.testing.assert_allclose(sched, lin, rtol=1e-12)
 
 
+def test_eps_scheduler_eps0_closed_form():
+    """Alg. 4's eps_0 is the source-target mean cost / 20; the mean cost has
+    the moments closed form mean |x|^2 + mean |y|^2 - 2 xbar . ybar, formed
+    here from the clouds (not read from the scheduler), and the first step of
+    a constant-speed schedule is beta0 eps_0."""
+    X, Y = workloads.c1(seed=1, n=180, m=150)
+    Yt = workloads.c1_holdout(seed=1, n=180, m_test=120, test_seed=101)
+    a = np.full(X.shape[0], 1.0 / X.shape[0])
+    b = np.full(Y.shape[0], 1.0 / Y.shape[0])
+    Xd, Yd = X.astype(np.float64), Y.astype(np.float64)
+    cbar = (Xd ** 2).sum(1).mean() + (Yd ** 2).sum(1).mean() - 2 * Xd.mean(0) @ Yd.mean(0)
+    for beta0 in (5.0, 2.0):
+        sched, info = schedules.eps_scheduler(a, X, b, Y, schedules.alpha_schedule(4), Yt,
+                                              beta0=beta0)
+        assert abs(sched[0] - beta0 * cbar / 20) < 1e-12 * sched[0]
+        assert abs(info["eps0"] - cbar / 20) < 1e-12 * cbar
+
+
+def _weighted_target(seed=1, m=160, m_test=150):
+    X, Y = workloads.c1(seed=seed, n=200, m=m)
+    Yt = workloads.c1_holdout(seed=seed, n=200, m_test=m_test, test_seed=101)
+    rng = np.random.default_rng(7)
+    b = rng.uniform(0.5, 1.5, m)
+    return X, Y, b / b.sum(), Yt
+
+
+def test_eps_scheduler_score_large_eps_limit():
+    """The hold-out score sum |y~ - T(y~)|^2 at grid scale eps = s sigma.  As
+    eps grows the Y -> Y potentials carry the weights b and the map tends to
+    T(y~) = ybar_b + (2/eps) Cov_b(Y)(y~ - ybar_b) + O(1/eps^2) (the
+    large-eps expansion pinned for Sinkhorn itself), so the score tends to
+    sum |y~ - ybar_b|^2 with the first-order gap
+    -(4/eps) sum (y~ - ybar_b)^T Cov_b(Y) (y~ - ybar_b); the relative error
+    of that gap shrinks ~10x per decade of eps."""
+    X, Y, b, Yt = _weighted_target()
+    a = np.full(X.shape[0], 1.0 / X.shape[0])
+    Yd = Y.astype(np.float64)
+    ybar = b @ Yd
+    Z = Yd - ybar
+    cov = (Z * b[:, None]).T @ Z
+    D = Yt.astype(np.float64) - ybar
+    limit = (D ** 2).sum()
+    quad = np.einsum("ij,jk,ik->", D, cov, D)
+    grid = [1e3, 1e4]
+    _, info = schedules.eps_scheduler(a, X, b, Y, schedules.alpha_schedule(4), Yt,
+                                      s_grid=grid, tau=1e-10)
+    rel = []
+    for s, score in zip(grid, info["errors"]):
+        first_order = -4.0 / (s * info["sigma"]) * quad
+        assert abs(score - limit) < 0.02 * limit
+        rel.append(abs((score - limit) / first_order - 1.0))
+    assert rel[0] < 5e-3 and rel[1] < 5e-4
+    assert 5.0 < rel[0] / rel[1] < 20.0
+
+
 def _problem(seed=21, n=150, m=120, d=3):
     X, Y = workloads.gmm(seed=seed, n=n, m=m, d=d, n_comp=3)
     a = np.full(n, 1.0 / n)
@@ -145,6 +200,19 @@ def test_progot_step_marginals_and_eps():
     np.testing.assert_allclose(r.eps[0], schedules.eps_mean_cost(X, Y), rtol=1e-12)
     np.testing.assert_allclose(r.eps[-1], schedules.eps_mean_cost(r.X_last, Y), rtol=1e-12)
     assert r.eps[-1] < r.eps[0]
+
+
+def test_last_step_starts_cold():
+    """Alg. 2 warm-starts solve k from (1 - alpha_k) times the previous
+    potentials; the last step has alpha = 1, so in fixed-iteration mode the
+    last solve is exactly a cold Sinkhorn run (zero initial potentials) on
+    the moved cloud X^(K-1), whatever the earlier steps left behind."""
+    a, X, b, Y = _problem(seed=25)
+    for K in (2, 3):
+        r = oracle.progot(a, X, b, Y, K=K, n_iter=6)
+        s = oracle.sinkhorn(a, r.X_last, b, Y, r.eps[-1], 0.0, n_iter=6)
+        np.testing.assert_allclose(r.G[-1], s.g, rtol=0, atol=1e-12 * np.abs(s.g).max())
+        np.testing.assert_allclose(r.f, s.f, rtol=0, atol=1e-12 * np.abs(s.f).max())
 
 
 def test_warm_start_variants_agree():

@@ -21,7 +21,9 @@
  *
  * Memory and ownership.  Every pointer named "device" is device memory owned
  * by the caller.  The library never allocates device memory: all scratch
- * lives in a caller-provided workspace of pot_workspace_bytes() bytes.  The
+ * lives in a caller-provided workspace of pot_workspace_bytes() bytes (the
+ * one exception, pot_sinkhorn_divergence_noalloc, uses a static array of
+ * POT_STATIC_SCRATCH_BYTES per GPU that comes with the library).  The
  * pot_clouds struct is a host POD owned by the caller, valid while its
  * workspace lives.  X, Y, a, b are never written.  Layouts are row-major:
  * a cloud of n points in R^d is n*d floats, point i at [i*d, (i+1)*d).
@@ -272,6 +274,28 @@ POT_API int pot_sinkhorn_divergence_pcost(const float *X, int64_t n, const float
                                           int32_t d, const float *a, const float *b, float p,
                                           float eps, float tau, int32_t max_iter, double *out,
                                           void *ws, size_t ws_bytes, void *stream);
+
+/* The same divergence for callers that cannot allocate memory (code under
+ * HIP graph capture set-up, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument; the call calls no hipMalloc, hipFree,
+ * hipHostMalloc or event creation.  Its workspace is a static device array of
+ * POT_STATIC_SCRATCH_BYTES per GPU, part of the library's code object, held
+ * from the first call on a device until the process ends; its device address
+ * is looked up once per device (the device current at the call, which must
+ * own `stream`).  Pairs whose pot_sinkhorn_divergence_bytes(n, m, d) exceeds
+ * that size return POT_ERR_NOMEM before any work (e.g. n = m = 32768 at
+ * d = 64 fit).  Every call on one GPU shares the array and leaves its
+ * contents behind; each call writes every region before reading it, so
+ * nothing needs clearing, but calls that overlap on one GPU (two host threads,
+ * or two streams in flight) race and must be serialised by the caller.  The
+ * error sums of the Sinkhorn loop are copied back and checked after every
+ * iteration (one stream synchronisation each), so the call returns exactly
+ * what pot_sinkhorn_divergence returns, a little more slowly for short
+ * iterations.  Arguments, results and errors otherwise as above.  Blocks. */
+#define POT_STATIC_SCRATCH_BYTES (32u << 20)
+POT_API int pot_sinkhorn_divergence_noalloc(const float *X, int64_t n, const float *Y, int64_t m,
+                                            int32_t d, const float *a, const float *b, float eps,
+                                            float tau, int32_t max_iter, double *out, void *stream);
 
 /* ---- Alg. 4 (eps-scheduler) ------------------------------------------------
  *

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace pot {
@@ -52,6 +53,7 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p, bo
     L.chr = take((size_t)pot::fp64_check_blocks(n) * pot::kCheckParts * 8);
     L.chc = take((size_t)pot::fp64_check_blocks(m) * pot::kCheckParts * 8);
     L.n64 = take(std::max<size_t>((size_t)n + (size_t)m, 512) * 8);   // FP64 norms / partials
+    L.eslot = take(4 * sizeof(float));
     // general costs: the cost matrix of (xk, Y), its block sums (+ the
     // total), and the accumulator partials of the split map kernel
     const bool pc = cost_p != 0.f;
@@ -283,7 +285,9 @@ thread_local Pinned g_pinned;
 struct SlotClaim {
     hipStream_t s;
     bool ok = false;
-    explicit SlotClaim(hipStream_t st) : s(st) {
+    bool inert = false;   // the solve does not use the pinned slots
+    explicit SlotClaim(hipStream_t st, bool unused = false) : s(st), inert(unused) {
+        if (inert) { ok = true; return; }
         if (!g_pinned.tail && hipEventCreateWithFlags(&g_pinned.tail, hipEventDisableTiming) != hipSuccess) {
             g_pinned.tail = nullptr;
             return;
@@ -293,7 +297,7 @@ struct SlotClaim {
         ok = true;
     }
     ~SlotClaim() {
-        if (!ok) return;
+        if (!ok || inert) return;
         g_pinned.tail_set = hipEventRecord(g_pinned.tail, s) == hipSuccess;
         g_pinned.tail_stream = s;
     }
@@ -341,7 +345,7 @@ struct SinkResult {
 int enqueue_err_readback(const pot_clouds *c, const Layout &L, int nparts, float *slot,
                          hipEvent_t ev, hipStream_t s, bool summed = false) {
     if (!summed) POT_TRY(pot::launch_sum_f32(at<float>(c, L.errp), nparts, slot, s));
-    POT_TRY(hipEventRecord(ev, s));
+    if (ev) POT_TRY(hipEventRecord(ev, s));
     return POT_OK;
 }
 
@@ -386,25 +390,46 @@ struct Events {
     }
 };
 
+// copy_rb: the error sums go to device slots in the workspace and each check
+// copies one back and synchronises the stream (lag 0); no pinned host memory
+// and no events are created, for the entry points that allocate nothing.
+// The iterates and the returned one are the same as with the mapped slots.
 int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, int max_iter,
-                  const float *g_init, float gamma, SinkResult *out, hipStream_t s) {
+                  const float *g_init, float gamma, SinkResult *out, hipStream_t s,
+                  bool copy_rb = false) {
     float *fb[kRing] = {at<float>(c, L.f0), at<float>(c, L.f1), at<float>(c, L.f2)};
     float *gb[kRing] = {at<float>(c, L.g0), at<float>(c, L.g1), at<float>(c, L.g2)};
     float *hdev = nullptr;
-    float *host = pinned_slot(&hdev);
-    if (!host) return POT_ERR_DEVICE;
-    SlotClaim claim(s);
+    float *host = nullptr;
+    if (copy_rb) {
+        hdev = at<float>(c, L.eslot);
+    } else {
+        host = pinned_slot(&hdev);
+        if (!host) return POT_ERR_DEVICE;
+    }
+    SlotClaim claim(copy_rb ? nullptr : s, copy_rb);
     if (!claim.ok) return POT_ERR_DEVICE;
     Events E;
-    for (hipEvent_t &e : E.ev) POT_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    const int lag = pick_lag(c);
+    if (!copy_rb)
+        for (hipEvent_t &e : E.ev) POT_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const int lag = copy_rb ? 0 : pick_lag(c);
     LseJob fa = f_job(c, L, eps);
     LseJob ga = g_job(c, L, eps);
     const bool fold = lag == 2 && pot::lse_update_folds_sum(ga);
     // read err_k (its sum was enqueued with f_{k+1}, or rides in g_{k+1}); true when the loop ends at k
+    float copied = 0.f;
+    auto read_err = [&](int k) -> bool {
+        if (copy_rb)
+            return hipMemcpyAsync(&copied, hdev + k % kRing, sizeof(float), hipMemcpyDeviceToHost, s) ==
+                       hipSuccess &&
+                   hipStreamSynchronize(s) == hipSuccess;
+        if (hipEventSynchronize(E.ev[k % kRing]) != hipSuccess) return false;
+        copied = host[k % kRing];
+        return true;
+    };
     auto check = [&](int k, int *status) -> bool {
-        if (hipEventSynchronize(E.ev[k % kRing]) != hipSuccess) { *status = POT_ERR_DEVICE; return true; }
-        const float err = host[k % kRing];
+        if (!read_err(k)) { *status = POT_ERR_DEVICE; return true; }
+        const float err = copied;
         if (!std::isfinite(err)) { *status = POT_ERR_NUMERIC; return true; }
         if (tau > 0.f && err <= tau) {
             out->iters = k; out->err = err; out->converged = true;
@@ -449,7 +474,7 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
                 POT_OK)
                 return status;
             if (check(t, &status)) return status;
-            out->iters = t; out->err = host[t % kRing];
+            out->iters = t; out->err = copied;
             out->converged = tau > 0.f ? out->err <= tau : true;
             out->f = fb[t % kRing]; out->g = gb[t % kRing];
             return POT_OK;
@@ -500,19 +525,24 @@ size_t pot_workspace_bytes(int64_t n, int64_t m, int32_t d, int32_t precision) {
 
 namespace {
 
-// Weights, when given, must be positive and sum to 1 within 1e-5.
+// Weights, when given, must be positive and sum to 1 within 1e-5.  They are
+// read back in chunks through a buffer on the stack (no host allocation).
 int check_weights(const float *a, int64_t n, const float *b, int64_t m, hipStream_t s) {
+    constexpr int64_t kChunk = 8192;
+    float h[kChunk];
     for (int side = 0; side < 2; ++side) {
         const float *w = side ? b : a;
         const int64_t len = side ? m : n;
         if (!w) continue;
-        std::vector<float> h(len);
-        POT_TRY(hipMemcpyAsync(h.data(), w, len * sizeof(float), hipMemcpyDeviceToHost, s));
-        POT_TRY(hipStreamSynchronize(s));
         double tot = 0.0;
-        for (float v : h) {
-            if (!(v > 0.f) || !std::isfinite(v)) return POT_ERR_INVALID;
-            tot += v;
+        for (int64_t i0 = 0; i0 < len; i0 += kChunk) {
+            const int64_t cnt = std::min(kChunk, len - i0);
+            POT_TRY(hipMemcpyAsync(h, w + i0, cnt * sizeof(float), hipMemcpyDeviceToHost, s));
+            POT_TRY(hipStreamSynchronize(s));
+            for (int64_t i = 0; i < cnt; ++i) {
+                if (!(h[i] > 0.f) || !std::isfinite(h[i])) return POT_ERR_INVALID;
+                tot += h[i];
+            }
         }
         if (std::fabs(tot - 1.0) > 1e-5) return POT_ERR_INVALID;
     }
@@ -527,10 +557,10 @@ int prepare(pot_clouds *c, const float *X, int64_t n, const float *Y, int64_t m,
     int st = check_weights(a, n, b, m, s);
     if (st != POT_OK) return st;
     bind_clouds(c, X, n, Y, m, d, a, b, precision, ws, ws_bytes, L, cost_p, keep);
-    std::vector<double> host(moments_len(d));
-    if ((st = enqueue_prepare(c, L, host.data(), s)) != POT_OK) return st;
+    double host[2 * (POT_MAX_D + 1)];   // moments_len(d) <= this
+    if ((st = enqueue_prepare(c, L, host, s)) != POT_OK) return st;
     POT_TRY(hipStreamSynchronize(s));
-    if ((st = finish_moments(c, host.data())) != POT_OK) return st;
+    if ((st = finish_moments(c, host)) != POT_OK) return st;
     return cost_p != 0.f ? refresh_pcost(c, L, s) : POT_OK;
 }
 
@@ -731,7 +761,7 @@ namespace {
 // eps_D = 5 % of the mean cost within Y.
 int divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d, const float *a,
                const float *b, float cost_p, float eps, float tau, int32_t max_iter, double *out,
-               void *ws, size_t ws_bytes, hipStream_t s) {
+               void *ws, size_t ws_bytes, hipStream_t s, bool noalloc = false) {
     struct Pair { const float *U; int64_t nu; const float *wu; const float *V; int64_t nv; const float *wv; };
     const Pair pairs[3] = {{Y, m, b, Y, m, b}, {X, n, a, Y, m, b}, {X, n, a, X, n, a}};
     double ot[3];
@@ -747,7 +777,8 @@ int divergence(const float *X, int64_t n, const float *Y, int64_t m, int32_t d, 
         if (k == 0 && eps == 0.f) eps = (float)(0.05 * c.mean_cost);
         if (!finite_pos(eps)) return POT_ERR_NUMERIC;
         SinkResult r;
-        if ((st = sinkhorn_core(&c, L, eps, tau, max_iter, nullptr, 1.f, &r, s)) != POT_OK) return st;
+        if ((st = sinkhorn_core(&c, L, eps, tau, max_iter, nullptr, 1.f, &r, s, noalloc)) != POT_OK)
+            return st;
         all = all && r.converged;
         // The returned iterate ends with a g-update, so its coupling's column
         // sums are b and its mass sum_ij P_ij is 1: the objective of eq.
@@ -800,6 +831,52 @@ int pot_sinkhorn_divergence_pcost(const float *X, int64_t n, const float *Y, int
     if (ws_bytes < need) return POT_ERR_NOMEM;
     return divergence(X, n, Y, m, d, a, b, p, eps, tau, max_iter, out, ws, ws_bytes,
                       static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of pot_sinkhorn_divergence_noalloc: one array per GPU, loaded with
+// the library's code object and kept until the process ends.  Host code never
+// uses the array's name as an address (on the host it is only a stand-in for
+// the symbol): the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+static __device__ __align__(256) unsigned char scratch[POT_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (nullptr on failure).
+void *scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int pot_sinkhorn_divergence_noalloc(const float *X, int64_t n, const float *Y, int64_t m, int32_t d,
+                                    const float *a, const float *b, float eps, float tau,
+                                    int32_t max_iter, double *out, void *stream) {
+    if (!X || !Y || !out || !valid_sizes(n, m, d, POT_PREC_FP32) || !std::isfinite(eps) ||
+        eps < 0.f || !finite_pos(tau) || max_iter < 1)
+        return POT_ERR_INVALID;
+    const size_t need = pot_sinkhorn_divergence_bytes(n, m, d);
+    if (need > (size_t)POT_STATIC_SCRATCH_BYTES) return POT_ERR_NOMEM;
+    void *ws = scratch_on_current_device();
+    if (!ws) return POT_ERR_DEVICE;
+    return divergence(X, n, Y, m, d, a, b, 0.f, eps, tau, max_iter, out, ws, need,
+                      static_cast<hipStream_t>(stream), true);
 }
 
 int pot_diag_metrics(const pot_clouds *c, const float *f, const float *g, float eps, double *out,

@@ -101,6 +101,8 @@ _SIGS = {
                                                 _i32, C.POINTER(C.c_double), _vp, C.c_size_t, _vp]),
     "pot_sinkhorn_divergence": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _f32, _f32, _i32,
                                           C.POINTER(C.c_double), _vp, C.c_size_t, _vp]),
+    "pot_sinkhorn_divergence_noalloc": (C.c_int, [_vp, _i64, _vp, _i64, _i32, _vp, _vp, _f32, _f32,
+                                                  _i32, C.POINTER(C.c_double), _vp]),
     "pot_eps_schedule_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32]),
     "pot_eps_schedule_pcost_bytes": (C.c_size_t, [_i64, _i64, _i32, _i32, _f32]),
     "pot_eps_schedule": (C.c_int, [C.POINTER(pot_clouds), _vp, _i64, _i32, _i32,
@@ -469,6 +471,33 @@ def sinkhorn_divergence(X, Y, a=None, b=None, eps: float = 0.0, tau: float = 1e-
                                                   float(eps), float(tau), int(max_iter), out,
                                                   _ptr(ws), nb, C.c_void_p(_stream())),
                     "sinkhorn_divergence")
+    return {"D": out[0], "ot_xy": out[1], "ot_xx": out[2], "ot_yy": out[3], "eps": out[4],
+            "status": st}
+
+
+STATIC_SCRATCH_BYTES = 32 << 20
+
+
+def sinkhorn_divergence_noalloc(X, Y, a=None, b=None, eps: float = 0.0, tau: float = 1e-3,
+                                max_iter: int = 10_000) -> dict:
+    """The squared-Euclidean Sinkhorn divergence of ``sinkhorn_divergence``
+    computed in the library's static per-GPU scratch array: no workspace
+    tensor is allocated, here or in the library."""
+    for t, nm in ((X, "X"), (Y, "Y")):
+        _dev_f32(t, nm)
+    n, d = X.shape
+    m = Y.shape[0]
+    if Y.shape[1] != d:
+        raise ValueError("X and Y must have the same dimension")
+    if a is not None:
+        _dev_f32(a, "a", (n,))
+    if b is not None:
+        _dev_f32(b, "b", (m,))
+    out = (C.c_double * 5)()
+    st = _check(lib().pot_sinkhorn_divergence_noalloc(_ptr(X), n, _ptr(Y), m, d, _ptr(a), _ptr(b),
+                                                      float(eps), float(tau), int(max_iter), out,
+                                                      C.c_void_p(_stream())),
+                "sinkhorn_divergence_noalloc")
     return {"D": out[0], "ot_xy": out[1], "ot_xx": out[2], "ot_yy": out[3], "eps": out[4],
             "status": st}
 

@@ -290,3 +290,35 @@ def test_timing_enable_rejects_negative_stride():
     assert lib.pot_timing_enable(0) == 0
     with pytest.raises(ValueError):
         P.timing_enable(True, every=0)
+
+
+def test_static_scratch_size_matches_header():
+    """The binding's size of the allocation-free entry point's scratch array is
+    the header's POT_STATIC_SCRATCH_BYTES, and pairs up to 32768^2 at d = 64
+    fit in it."""
+    import re
+    txt = B.HEADER.read_text()
+    m = re.search(r"#define POT_STATIC_SCRATCH_BYTES \((\d+)u << (\d+)\)", txt)
+    assert m and int(m.group(1)) << int(m.group(2)) == B.STATIC_SCRATCH_BYTES
+    assert P.lib().pot_sinkhorn_divergence_bytes(32768, 32768, 64) <= B.STATIC_SCRATCH_BYTES
+    assert P.lib().pot_sinkhorn_divergence_bytes(70000, 70000, 64) > B.STATIC_SCRATCH_BYTES
+
+
+def test_noalloc_divergence_rejects_invalid_arguments_on_the_host():
+    out = (C.c_double * 5)()
+    L = P.lib()
+    # null inputs, d out of range, negative eps, tau <= 0, max_iter < 1: all before any HIP call
+    assert L.pot_sinkhorn_divergence_noalloc(None, 10, None, 10, 4, None, None, 0.0, 1e-3, 10, out,
+                                             None) == B.POT_ERR_INVALID
+    fake = C.c_void_p(0x1000)
+    assert L.pot_sinkhorn_divergence_noalloc(fake, 10, fake, 10, 300, None, None, 0.0, 1e-3, 10,
+                                             out, None) == B.POT_ERR_INVALID
+    assert L.pot_sinkhorn_divergence_noalloc(fake, 10, fake, 10, 4, None, None, -1.0, 1e-3, 10,
+                                             out, None) == B.POT_ERR_INVALID
+    assert L.pot_sinkhorn_divergence_noalloc(fake, 10, fake, 10, 4, None, None, 0.0, 0.0, 10,
+                                             out, None) == B.POT_ERR_INVALID
+    assert L.pot_sinkhorn_divergence_noalloc(fake, 10, fake, 10, 4, None, None, 0.0, 1e-3, 0,
+                                             out, None) == B.POT_ERR_INVALID
+    # too large for the scratch: refused before any HIP call
+    assert L.pot_sinkhorn_divergence_noalloc(fake, 70000, fake, 70000, 64, None, None, 0.0, 1e-3,
+                                             10, out, None) == B.POT_ERR_NOMEM

@@ -376,7 +376,10 @@ POT_API int pot_server_submit(pot_server *srv, const float *X, int64_t n, const 
 
 /* One tick (blocks on the stream).  n_active: requests still in flight;
  * n_finished: requests that finished in this tick (their outputs are in
- * place).  A request that fails (non-finite error) finishes with its status. */
+ * place).  A request that fails (a non-finite mean cost or marginal error,
+ * e.g. from a NaN in its clouds) finishes with its status, which
+ * pot_server_poll reports; the tick itself still returns POT_OK and the other
+ * requests are unaffected.  POT_ERR_DEVICE when a HIP call fails. */
 POT_API int pot_server_step(pot_server *srv, int32_t *n_active, int32_t *n_finished);
 
 /* POT_BUSY while request rid is in flight; once finished, fills info (may be

@@ -383,9 +383,12 @@ int pot_server_step(pot_server *S, int32_t *n_active, int32_t *n_finished) {
             }
         }
         if (st != POT_OK) {
+            // the failure belongs to this request: it finishes with its
+            // status (reported by pot_server_poll) and the others go on; only
+            // a failing HIP call is the whole server's error
             r->status = st;
             done = true;
-            status = st;
+            if (st == POT_ERR_DEVICE) status = st;
         }
         (done ? done_now : keep).push_back(r);
     }

@@ -565,13 +565,17 @@ class Server:
         return a.value, fin.value
 
     def poll(self, rid: int):
-        """None while in flight, else (f, G, TX, ProgOTInfo)."""
+        """None while in flight, else (f, G, TX, ProgOTInfo); raises PotError
+        with the request's status when it failed."""
         info = pot_progot_info()
         st = lib().pot_server_poll(self.h, int(rid), C.byref(info))
         if st == POT_BUSY:
             return None
+        # the request is finished (or unknown): drop its tensors before a
+        # failure status raises
+        entry = self.live.pop(rid, None)
         _check(st, "server_poll")
-        _, _, f, G, TX, _ = self.live.pop(rid)
+        _, _, f, G, TX, _ = entry
         return f, G, TX, _info(info, st)
 
     def close(self):

@@ -104,6 +104,18 @@ def recorded_traffic(kernel: str, workload: str, sources=None):
     return float(rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"])
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first processor of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(X, Y, n_sample: int, n_iter: int):
     """FP64 oracle (as it stands) on the first n_sample points of a seeded
     permutation of each cloud: the first n_iter iterations of a Sinkhorn
@@ -121,7 +133,7 @@ def cpu_baseline(X, Y, n_sample: int, n_iter: int):
     r = oracle.sinkhorn(a, Xs, a, Ys, eps, 0.0, n_iter=n_iter)
     dt = time.perf_counter() - t0
     return {"value": n_sample * n_sample * r.iters / dt, "unit": "n·m·iters/s",
-            "cores": osk.THREADS, "kind": "oracle",
+            "cores": osk.THREADS, "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"FP64 oracle Sinkhorn on a {n_sample}x{n_sample} seeded subsample of the "
                       f"same clouds, eps = mean cost/20, {r.iters} fixed iterations, cost matrix "
                       f"build included, {dt:.1f} s"}
@@ -298,7 +310,7 @@ def next_bench(args):
                     "eps": sched.eps, "potential_launches": lse_n,
                     "potential_kernel_ms": lse_ms,
                     "cpu_baseline": {"value": t_cpu * 1e3, "unit": "ms per schedule",
-                                     "cores": osk.THREADS, "kind": "oracle",
+                                     "cores": osk.THREADS, "cpu_model": cpu_model(), "kind": "oracle",
                                      "sample": "the full problem (FP64 oracle Alg. 4, 7 grid solves "
                                                "of 1024 x 1024, hold-out maps)"}})
     else:
@@ -324,7 +336,7 @@ def next_bench(args):
                                  "frac": flops / (lse_ms * 1e-3) / 1e12 / PEAK["fp32"],
                                  "traffic": None, "kernel": "lse_partial (fused cost + log-sum-exp)"},
                     "cpu_baseline": {"value": t_cpu * 1e3, "unit": "ms per divergence",
-                                     "cores": osk.THREADS, "kind": "oracle",
+                                     "cores": osk.THREADS, "cpu_model": cpu_model(), "kind": "oracle",
                                      "sample": f"FP64 oracle divergence on a 2048 x 2048 seeded "
                                                f"subsample (D = {refD[0]:.6g}), same eps_D and tau"}})
     print(json.dumps(out), flush=True)
@@ -406,14 +418,104 @@ def pcost_bench(args, out):
     print(json.dumps(out), flush=True)
 
 
+FORMS = ("fp32", "bf16", "bf16x3")
+
+
+def forms_bench(args) -> dict:
+    """The precision workload (n = m = 65536, d = 256, 32 unit-norm clusters +
+    N(0, 0.01 I), K = 4, eps_k = mean cost/20, tau) solved by ProgOT in each
+    arithmetic form of the cross term, timed the same way as the main line:
+    solve time, Sinkhorn iterations, the FP64 row/column marginal L1 of the
+    returned coupling (the equal-error condition of the speed-ups) and the
+    potential kernel's fraction of its MFMA peak (every launch timed; they
+    last milliseconds)."""
+    import torch
+    import paper_2406_05061_amd as P
+    spec, K = _SPHERE64K, 4
+    X, Y = make_clouds(spec)
+    n, d = X.shape
+    m = Y.shape[0]
+    log(f"bench: forms: precision workload n={n} m={m} d={d} K={K}")
+    Xd, Yd = P.to_device(X), P.to_device(Y)
+    res = {"workload": "sphere64k_d256", "n": n, "m": m, "d": d, "K": K, "tau": args.tau,
+           "steps": args.forms_steps, "warmup": 1}
+    for prec in FORMS:
+        cl = P.prepare_clouds(Xd, Yd, precision=prec)
+
+        def step():
+            return P.progot_solve(cl, K, tau_first=args.tau, tau_last=args.tau)
+
+        step()
+        torch.cuda.synchronize()
+        P.timing_enable(True, every=1)
+        t0 = time.perf_counter()
+        for _ in range(args.forms_steps):
+            f, G, TX, info = step()
+        torch.cuda.synchronize()
+        solve_s = (time.perf_counter() - t0) / args.forms_steps
+        lse_ms, lse_n, _, _ = P.timing_read()
+        P.timing_enable(False)
+        row, col, _ = P.marginal_check(cl, f, G[-1], info.eps[-1])
+        avg = lse_ms * 1e-3 / max(lse_n, 1)
+        achieved = 2.0 * n * m * d / avg / 1e12
+        res[prec] = {"solve_s": solve_s, "sinkhorn_iters_per_solve": info.iters,
+                     "final_marginal_l1_fp64": {"row": row, "col": col},
+                     "meets_tau": bool(row <= args.tau * 1.01 and col <= args.tau * 1.01),
+                     "roofline": {"kernel": "lse_partial", "bound": "mfma",
+                                  "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
+                                  "frac": achieved / PEAK[prec], "avg_launch_us": avg * 1e6,
+                                  "timed_launches": lse_n}}
+        log(f"bench: forms: {prec}: {solve_s * 1e3:.1f} ms per solve, iters {info.iters}, "
+            f"FP64 marginal {row:.2e}/{col:.2e}, lse_partial {achieved:.1f} TFLOP/s "
+            f"({achieved / PEAK[prec]:.2f} of peak)")
+        del cl, f, G, TX
+        torch.cuda.empty_cache()
+    for prec in FORMS[1:]:
+        res[prec]["speedup_vs_fp32"] = res["fp32"]["solve_s"] / res[prec]["solve_s"]
+    return res
+
+
+def probe_bench(args):
+    """One short run of the hot kernels at a chosen shape, for profilers:
+    seeded clouds (clustered unit-norm, or Gaussian mixtures with
+    --gen gmm), --iters Sinkhorn iterations in fixed-iteration mode at
+    eps = theta * mean cost / 20 (each one f- and one g-update), then --maps
+    launches of the entropic map on the source cloud; --cost-p selects the
+    cost (1/p)|.|_p^p.  Prints the wall times as one JSON line."""
+    import torch
+    import paper_2406_05061_amd as P
+    m = args.m or args.n
+    if args.gen == "gmm":
+        X, Y = workloads.gmm(seed=args.seed, n=args.n, m=m, d=args.d, n_comp=10)
+    else:
+        X, Y = workloads.sphere(seed=args.seed, n=args.n, m=m, d=args.d, n_clusters=64)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=args.prec, cost_p=args.cost_p,
+                          cost_mode=args.cost_mode)
+    eps = args.theta * cl.mean_cost / 20.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, g, _ = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=args.iters)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Xq = cl.xk()
+    for _ in range(args.maps):
+        P.entropic_map(cl, g, eps, Xq)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    print(json.dumps({"workload": "probe", "gen": args.gen, "n": args.n, "m": m, "d": args.d,
+                      "precision": args.prec, "cost_p": args.cost_p, "theta": args.theta,
+                      "iters": args.iters, "sinkhorn_s": t1 - t0, "maps": args.maps,
+                      "maps_s": t2 - t1}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gmm16k_d64_fp32",
-                    choices=sorted(WORKLOADS) + ["serve", *NEXT_WORKLOADS])
-    ap.add_argument("--requests", type=int, default=128, help="serve: number of requests")
+                    choices=sorted(WORKLOADS) + ["serve", "probe", *NEXT_WORKLOADS])
+    ap.add_argument("--requests", type=int, default=2048, help="serve: number of requests")
     ap.add_argument("--max-active", type=int, default=128, help="serve: server slots")
     ap.add_argument("--arena-gib", type=int, default=16, help="serve: HBM budget of the server")
     ap.add_argument("--tau", type=float, default=1e-3)
@@ -421,6 +523,20 @@ def main():
     ap.add_argument("--cost-mode", default="auto", choices=["auto", "keep", "on_the_fly"],
                     help="pcost_4i_d47: keep the cost matrix or form it in every update")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="default workload: skip the precision forms of the 65536^2 workload")
+    ap.add_argument("--forms-steps", type=int, default=3, help="timed solves per precision form")
+    g = ap.add_argument_group("probe workload (profiling driver)")
+    g.add_argument("--gen", default="sphere", choices=["sphere", "gmm"])
+    g.add_argument("--n", type=int, default=65536)
+    g.add_argument("--m", type=int, default=0, help="target points (default n)")
+    g.add_argument("--d", type=int, default=128)
+    g.add_argument("--prec", default="bf16", choices=list(FORMS))
+    g.add_argument("--cost-p", type=float, default=0.0)
+    g.add_argument("--theta", type=float, default=1.0)
+    g.add_argument("--iters", type=int, default=1)
+    g.add_argument("--maps", type=int, default=1)
+    g.add_argument("--seed", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--cpu-iters", type=int, default=48,
                     help="oracle iterations of the CPU baseline sample")
@@ -444,6 +560,9 @@ def main():
         return
     if args.workload in NEXT_WORKLOADS:
         next_bench(args)
+        return
+    if args.workload == "probe":
+        probe_bench(args)
         return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -548,6 +667,10 @@ def main():
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline (oracle, {args.cpu_sample}^2 sample) ...")
         out["cpu_baseline"] = cpu_baseline(X, Y, args.cpu_sample, args.cpu_iters)
+    if args.workload == "gmm16k_d64_fp32" and not args.no_forms:
+        del cl, Xd, Yd, f, G, TX
+        torch.cuda.empty_cache()
+        out["forms"] = forms_bench(args)
     print(json.dumps(out), flush=True)
 
 

@@ -28,17 +28,37 @@
 namespace pot {
 namespace {
 
+// LDS tile layout.  A tile of BN columns x D features is stored as 16-byte
+// chunks (4 features): chunk c of tile row j sits at chunk index
+//   ((j / 16) * C + c) * 16 + ((j % 16) ^ (c % 4)),   C = D / 4,
+// i.e. 16 rows per chunk column with the rows of chunk column c permuted by
+// an XOR with c % 4.  On gfx950 a ds_read_b128 is conflict-free when each
+// group of 16 consecutive lanes reads 16 chunks of one 256-byte block (padded
+// row strides measured 2-way conflicted): the cross-term operand read -- lane
+// (li, lq) takes chunk c of row 16 s + li -- is one such block per lane group.
+// The XOR makes the map's projection read conflict-free as well: there lane
+// (li, lq) takes feature 16 db + li of row 16 s + 4 lq + r (a ds_read_b32),
+// and the permuted row 4 lq + (r ^ (li / 4)) puts the 64 lanes on 64
+// distinct banks.  Thread t fills LDS chunk t (+ 256 k), so the stores are
+// contiguous too; its global load is chunk c of one row of a 16-row block.
 template <int D, int BN_ = (D >= 256 ? 32 : 64)> struct Tile {
     static constexpr int BN = BN_;                 // columns per LDS tile
     static constexpr int NSUB = BN / 16;           // 16-column subtiles
     static constexpr int KD = D / 4;               // features per lane group
-    static constexpr int STRIDE = D + 4;           // padded LDS row (floats)
-    static constexpr int NV4 = BN * D / 4;         // float4 per tile
-    static constexpr int PER_T = (NV4 + 255) / 256;
+    static constexpr int C = D / 4;                // 16-byte chunks per row
+    static constexpr int NCH = BN * C;             // chunks per tile
+    static constexpr int FLOATS = BN * D;          // LDS floats per tile
+    static constexpr int PER_T = (NCH + 255) / 256;
 };
 
+// Float offset of chunk c of tile row j (layout above).
+template <int D>
+__device__ __forceinline__ int tchunk(int j, int c) {
+    return (((j >> 4) * (D / 4) + c) * 16 + ((j & 15) ^ (c & 3))) * 4;
+}
+
 // Load one BN x D column tile (rows j0.., zero-padded beyond nv and beyond
-// feature d) into registers; thread t takes float4 slots t, t+256, ...
+// feature d) into registers: thread t takes LDS chunks t, t + 256, ...
 template <int D, int BN>
 __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t nv, int d,
                                            int64_t j0, f4 (&pre)[Tile<D, BN>::PER_T]) {
@@ -47,9 +67,10 @@ __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t 
     for (int r = 0; r < T::PER_T; ++r) {
         const int e = threadIdx.x + 256 * r;
         f4 v = {0.f, 0.f, 0.f, 0.f};
-        if (e < T::NV4) {
-            const int row = e / (D / 4);
-            const int c = (e % (D / 4)) * 4;
+        if (T::NCH % 256 == 0 || e < T::NCH) {
+            const int cc = (e >> 4) % T::C;
+            const int row = (e / (16 * T::C)) * 16 + ((e & 15) ^ (cc & 3));
+            const int c = cc * 4;
             const int64_t j = j0 + row;
             if (j < nv) {
                 if (d == D) {
@@ -73,11 +94,7 @@ __device__ __forceinline__ void tile_store(float *__restrict__ lds, const f4 (&p
 #pragma unroll
     for (int r = 0; r < T::PER_T; ++r) {
         const int e = threadIdx.x + 256 * r;
-        if (e < T::NV4) {
-            const int row = e / (D / 4);
-            const int c = (e % (D / 4)) * 4;
-            *reinterpret_cast<f4 *>(lds + row * T::STRIDE + c) = pre[r];
-        }
+        if (T::NCH % 256 == 0 || e < T::NCH) *reinterpret_cast<f4 *>(lds + 4 * e) = pre[r];
     }
 }
 
@@ -91,7 +108,7 @@ template <int D> using LseTile = Tile<D, lse_bn(D)>;
 
 template <int D, int QB>
 __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, int split,
-                                                 float (&vt)[2][LseTile<D>::BN * LseTile<D>::STRIDE],
+                                                 float (&vt)[2][LseTile<D>::FLOATS],
                                                  float (&bt)[2][LseTile<D>::BN]) {
     using T = LseTile<D>;
     constexpr int ROWS = 64 * QB;
@@ -163,10 +180,9 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
         for (int sub = 0; sub < T::NSUB; ++sub) {
             const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
             float a[T::KD];
-            const f4 *ap = reinterpret_cast<const f4 *>(vb + (sub * 16 + li) * T::STRIDE + lq * T::KD);
 #pragma unroll
             for (int k = 0; k < T::KD / 4; ++k) {
-                f4 v = ap[k];
+                const f4 v = *reinterpret_cast<const f4 *>(vb + tchunk<D>(sub * 16 + li, lq * (T::KD / 4) + k));
                 a[4 * k + 0] = v.x; a[4 * k + 1] = v.y; a[4 * k + 2] = v.z; a[4 * k + 3] = v.w;
             }
 #pragma unroll
@@ -223,7 +239,7 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
 // b mod 8, so with S = 8 each XCD streams one eighth of the columns).
 template <int D, int QB>
 __global__ __launch_bounds__(256) void lse_partial_f32(LseJob J) {
-    __shared__ float vt[2][LseTile<D>::BN * LseTile<D>::STRIDE];
+    __shared__ float vt[2][LseTile<D>::FLOATS];
     __shared__ float bt[2][LseTile<D>::BN];
     lse_partial_body<D, QB>(J, blockIdx.x / J.S, blockIdx.x % J.S, vt, bt);
 }
@@ -246,7 +262,7 @@ __device__ __forceinline__ int find_job(const LseJob *__restrict__ jobs, int njo
 // every problem gets the same bits as when it runs alone.
 template <int D, int QB>
 __global__ __launch_bounds__(256) void lse_partial_f32_group(const LseJob *__restrict__ jobs, int njobs) {
-    __shared__ float vt[2][LseTile<D>::BN * LseTile<D>::STRIDE];
+    __shared__ float vt[2][LseTile<D>::FLOATS];
     __shared__ float bt[2][LseTile<D>::BN];
     const LseJob &J = jobs[find_job<false>(jobs, njobs, blockIdx.x)];
     if (J.ctl && *(volatile const int *)J.ctl != 0) return;   // loop already stopped
@@ -430,25 +446,40 @@ __global__ __launch_bounds__(256) void scale_vec(const float *__restrict__ in, f
 }
 
 // Entropic map + McCann-type step for ROWS = 64*QB queries per workgroup.
+// As in the potential kernel the query rows are held already multiplied by
+// scale2 and the column bias beta_j is the accumulator's initial value, so
+// the score MFMA yields the log2-domain exponent t_ij itself.  The online
+// softmax keeps a running maximum per query (shared by the 4 lane groups);
+// the output accumulator is rescaled only in tiles where some query of the
+// wave raises its maximum (the factor is exactly 1 otherwise).
 template <int D, int QB>
-__global__ __launch_bounds__(256) void entropic_map_f32(
-    const float *Xq, int64_t nq, int d, const float *__restrict__ Y,
-    const float *__restrict__ ysq, const float *__restrict__ g, int64_t m, float scale2,
-    float bscale, float alpha, float *Xout, float *__restrict__ out_sqn) {
+__device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, int d,
+                                                  const float *__restrict__ Y,
+                                                  const float *__restrict__ ysq,
+                                                  const float *__restrict__ g, int64_t m,
+                                                  float scale2, float bscale, float alpha, float *Xout,
+                                                  float *__restrict__ out_sqn, int64_t tile,
+                                                  float (&vt)[2][Tile<D>::FLOATS],
+                                                  float (&bt)[2][Tile<D>::BN]) {
     using T = Tile<D>;
     constexpr int ROWS = 64 * QB;
     constexpr int NDB = D / 16;   // 16-feature blocks of the output
-    __shared__ float vt[2][T::BN * T::STRIDE];
-    __shared__ float bt[2][T::BN];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lq = lane >> 4;
-    const int64_t row0 = (int64_t)blockIdx.x * ROWS + wave * (QB * 16);
+    const int64_t row0 = tile * ROWS + wave * (QB * 16);
 
     float ub[QB][T::KD];
 #pragma unroll
-    for (int qb = 0; qb < QB; ++qb) row_fetch<D>(Xq, nq, d, row0 + qb * 16 + li, lq, ub[qb]);
+    for (int qb = 0; qb < QB; ++qb) {
+        row_fetch<D>(Xq, nq, d, row0 + qb * 16 + li, lq, ub[qb]);
+#pragma unroll
+        for (int k = 0; k < T::KD; ++k) {
+            ub[qb][k] *= scale2;
+            asm volatile("" : "+v"(ub[qb][k]));
+        }
+    }
 
     float run_m[QB], run_l[QB];
     f4 o[QB][NDB];
@@ -459,6 +490,12 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
 #pragma unroll
         for (int db = 0; db < NDB; ++db) o[qb][db] = f4{0.f, 0.f, 0.f, 0.f};
     }
+    // lane part of the projection read: row 4 lq + (r ^ (li / 4)) of a
+    // 16-row block, feature li of a 16-feature block (layout of tchunk)
+    int pv_off[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        pv_off[r] = ((li >> 2) * 16 + 4 * lq + (r ^ (li >> 2))) * 4 + (li & 3);
 
     const int ntiles = (int)((m + T::BN - 1) / T::BN);
     f4 pre[T::PER_T];
@@ -486,19 +523,21 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
             fetch_beta(jn);
         }
         const float *vb = vt[buf];
-        // k outer, (column subtile, row block) inner: NSUB x QB independent
-        // accumulation chains.
+        // accumulators start at beta_j; k outer, (column subtile, row block)
+        // inner: NSUB x QB independent accumulation chains
         f4 acc[QB][T::NSUB];
 #pragma unroll
-        for (int sub = 0; sub < T::NSUB; ++sub)
+        for (int sub = 0; sub < T::NSUB; ++sub) {
+            const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = beta;
+        }
 #pragma unroll
         for (int k4 = 0; k4 < T::KD / 4; ++k4) {
             f4 a[T::NSUB];
 #pragma unroll
             for (int sub = 0; sub < T::NSUB; ++sub)
-                a[sub] = *reinterpret_cast<const f4 *>(vb + (sub * 16 + li) * T::STRIDE + lq * T::KD + 4 * k4);
+                a[sub] = *reinterpret_cast<const f4 *>(vb + tchunk<D>(sub * 16 + li, lq * (T::KD / 4) + k4));
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
@@ -507,44 +546,41 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
                     for (int qb = 0; qb < QB; ++qb)
                         acc[qb][sub] = mfma4(a[sub][kk], ub[qb][4 * k4 + kk], acc[qb][sub]);
         }
-        f4 beta[T::NSUB];
-#pragma unroll
-        for (int sub = 0; sub < T::NSUB; ++sub)
-            beta[sub] = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
-            float p[T::NSUB * 4];
             float mx = kNegBig;
 #pragma unroll
             for (int sub = 0; sub < T::NSUB; ++sub)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float x = fmaf(acc[qb][sub][r], scale2, beta[sub][r]);
-                    p[sub * 4 + r] = x;
-                    mx = fmaxf(mx, x);
-                }
+                for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
             mx = fmaxf(mx, __shfl_xor(mx, 16));
             mx = fmaxf(mx, __shfl_xor(mx, 32));
             const float mn = fmaxf(run_m[qb], mx);
-            const float c = ex2(run_m[qb] - mn);
-            run_m[qb] = mn;
-            float s = 0.f;
+            if (__any(mn > run_m[qb])) {
+                const float c = ex2(run_m[qb] - mn);
+                run_l[qb] *= c;
 #pragma unroll
-            for (int e = 0; e < T::NSUB * 4; ++e) {
-                p[e] = ex2(p[e] - mn);
-                s += p[e];
+                for (int db = 0; db < NDB; ++db) o[qb][db] *= c;
+                run_m[qb] = mn;
             }
-            run_l[qb] = fmaf(run_l[qb], c, s);
-#pragma unroll
-            for (int db = 0; db < NDB; ++db) o[qb][db] *= c;
+            float p[T::NSUB * 4];
+            float s = 0.f;
 #pragma unroll
             for (int sub = 0; sub < T::NSUB; ++sub)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float *yrow = vb + (sub * 16 + 4 * lq + r) * T::STRIDE + li;
+                    p[sub * 4 + r] = ex2(acc[qb][sub][r] - mn);
+                    s += p[sub * 4 + r];
+                }
+            run_l[qb] += s;
+#pragma unroll
+            for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float *yb = vb + sub * 16 * D + pv_off[r];
 #pragma unroll
                     for (int db = 0; db < NDB; ++db)
-                        o[qb][db] = mfma4(yrow[db * 16], p[sub * 4 + r], o[qb][db]);
+                        o[qb][db] = mfma4(yb[db * 256], p[sub * 4 + r], o[qb][db]);
                 }
         }
         if (more) {
@@ -593,6 +629,17 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
         sq += __shfl_xor(sq, 32);
         if (out_sqn && lq == 0 && row < nq) out_sqn[row] = (float)sq;
     }
+}
+
+template <int D, int QB>
+__global__ __launch_bounds__(256) void entropic_map_f32(
+    const float *Xq, int64_t nq, int d, const float *__restrict__ Y,
+    const float *__restrict__ ysq, const float *__restrict__ g, int64_t m, float scale2,
+    float bscale, float alpha, float *Xout, float *__restrict__ out_sqn) {
+    __shared__ float vt[2][Tile<D>::FLOATS];
+    __shared__ float bt[2][Tile<D>::BN];
+    entropic_map_body<D, QB>(Xq, nq, d, Y, ysq, g, m, scale2, bscale, alpha, Xout, out_sqn,
+                             blockIdx.x, vt, bt);
 }
 
 template <int D, int QB>

@@ -111,3 +111,25 @@ def test_progot_bf16x3_c1(P):
     assert map_err(TX.cpu().numpy(), ref.TX, Y) < 1e-3
     row, col, _ = P.marginal_check(cl, f, G[-1], info.eps[-1])
     assert row <= 1e-3 * 1.01 and col <= 1e-4
+
+
+def test_bf16x3_small_eps_limit_is_a_warning(P):
+    """The form's limit at small eps, recorded: ProgOT (K = 4) on the small
+    workload's clouds at n = m = 4096, d = 16 with eps_k = 0.03 mean cost/20.
+    The late steps' potentials are ~1e4 eps, so BF16X3's ~2^-16 relative
+    cross-term error is an absolute exponent error near tau: its marginal
+    error stalls above tau = 1e-3 and the solve returns
+    POT_WARN_NOT_CONVERGED with finite outputs, where FP32 (2^-24) meets tau
+    in every step."""
+    X, Y = workloads.c1(seed=7, n=4096, m=4096, d=16)
+    res = {}
+    for prec in ("fp32", "bf16x3"):
+        print(f"case ProgOT {prec} c1 4096 d=16 theta=0.03", flush=True)
+        cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=prec)
+        f, G, TX, info = P.progot_solve(cl, 4, theta=0.03, max_iter=3000)
+        assert torch.isfinite(f).all() and torch.isfinite(G).all() and torch.isfinite(TX).all()
+        res[prec] = info
+        print(f"  status {info.status} iters {info.iters} err {info.err}", flush=True)
+    assert res["fp32"].status == 0 and res["fp32"].converged
+    assert res["bf16x3"].status == P.progot.POT_WARN_NOT_CONVERGED
+    assert max(res["bf16x3"].err) > 1e-3 and max(res["bf16x3"].err) < 1e-2

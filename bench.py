@@ -184,6 +184,8 @@ def serve_bench(args):
                         done[i] = now
                         infos[i] = res[3]
                         del rid_of[rid]
+                        if len(done) % 256 == 0:
+                            log(f"bench: serve: {len(done)} of {len(reqs)} done at {now:.1f} s")
             elif pending < len(order):
                 time.sleep(max(0.0, min(0.01, arrivals[order[pending]] - now)))
         wall = time.perf_counter() - t0
@@ -222,6 +224,8 @@ def serve_bench(args):
         cl = P.prepare_clouds(data[i][0], data[i][1])
         P.progot_solve(cl, K, tau_first=tau, tau_last=tau)
         done_seq[i] = time.perf_counter() - t0
+        if len(done_seq) % 256 == 0:
+            log(f"bench: FIFO: {len(done_seq)} of {len(reqs)} done at {done_seq[i]:.1f} s")
     wall_seq = time.perf_counter() - t0
     b50, b99 = lat_stats(done_seq, arrivals)
     log(f"bench: FIFO single solves: p50 {b50:.1f} ms p99 {b99:.1f} ms ({wall_seq:.1f} s)")

@@ -340,15 +340,21 @@ POT_API int pot_eps_schedule(const pot_clouds *c, const float *Y_test, int64_t m
  * together.  The caller gives it one device arena; each admitted request
  * takes a workspace of pot_server_request_bytes() from it (first fit), so
  * admission is by HBM footprint, bounded also by max_active slots.  Each
- * pot_server_step is one tick: one Sinkhorn iteration of every active
- * request, with all f-updates in one grouped kernel launch per padded
- * dimension and likewise all g-updates, then one read-back of all their
- * row-marginal errors; a request whose solve met its tau takes its McCann
- * step and starts the next ProgOT step at the following tick, and a request
- * submitted between ticks joins at the next one.  A request computes exactly
- * what pot_progot_solve computes for it alone (bit for bit): same kernels,
- * same column splits, same host arithmetic.  FP32 cross term, uniform
- * weights.  Calls on one server are not thread-safe. */
+ * pot_server_step is one tick: up to 16 Sinkhorn iterations of every
+ * active request, each sub-step with all f-updates in one grouped kernel
+ * launch per padded dimension and likewise all g-updates (the stop rule runs
+ * on the device), then one read-back of all their control words; a request
+ * whose solve met its tau takes its McCann step and starts the next ProgOT
+ * step at the following tick, and a request
+ * submitted between ticks joins at the next one.  The grouped launches are
+ * persistent kernels (a grid of the workgroups the chip holds at once, each
+ * walking the tick's work list of (request, row tile, column split) items),
+ * and the maps of every request whose solve ended in a tick (its McCann step
+ * or its final map) run in one grouped map launch per padded dimension.  A
+ * request computes exactly what pot_progot_solve computes for it alone (bit
+ * for bit): same device bodies, same column splits, same host arithmetic.
+ * FP32 cross term, uniform weights.  Calls on one server are not
+ * thread-safe. */
 typedef struct pot_server pot_server;
 
 #define POT_SERVER_MAX_ACTIVE 1024

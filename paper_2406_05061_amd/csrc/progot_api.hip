@@ -135,10 +135,14 @@ int refresh_pcost(pot_clouds *c, const Layout &L, hipStream_t s) {
     return std::isfinite(c->mean_cost) ? POT_OK : POT_ERR_NUMERIC;
 }
 
-int enqueue_moments(pot_clouds *c, const Layout &L, double *host, hipStream_t s) {
+bool map_writes_norms(const pot_clouds *c) {
+    return c->precision == POT_PREC_FP32 && c->cost_p == 0.f;
+}
+
+int enqueue_moments(pot_clouds *c, const Layout &L, double *host, hipStream_t s, bool norms_ready) {
     const int d = c->d;
     POT_TRY(pot::launch_cloud_prep(c->xk, c->n, d, c->x_sqn, c->x_lp, at<double>(c, L.xst),
-                                   pot::cloud_stat_blocks(c->n), s));
+                                   pot::cloud_stat_blocks(c->n), s, norms_ready));
     POT_TRY(hipMemcpyAsync(host, at<double>(c, L.xst), (d + 1) * 8, hipMemcpyDeviceToHost, s));
     POT_TRY(hipMemcpyAsync(host + d + 1, at<double>(c, L.yst), (d + 1) * 8, hipMemcpyDeviceToHost, s));
     return POT_OK;
@@ -229,7 +233,7 @@ int step_values(const pot_progot_params *p, const float *alpha, int k, double me
 }
 
 int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
-            float alpha, float *Xout, hipStream_t s) {
+            float alpha, float *Xout, hipStream_t s, float *out_sqn) {
     if (c->cost_p != 0.f) {
         const Layout L = plan_of(c);
         pot::PcostMapArgs a{};
@@ -244,7 +248,7 @@ int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int
     a.Xq = Xq; a.nq = nq; a.Y = c->Y; a.Y_lp = c->y_lp; a.m = c->m; a.ysq = c->y_sqn; a.g = g;
     a.eps = eps; a.alpha = alpha; a.d = c->d; a.precision = c->precision;
     a.YT_lp = c->yt_lp; a.mp = pot::bf16_mpad(c->m);
-    a.Xout = Xout; a.out_sqn = nullptr;
+    a.Xout = Xout; a.out_sqn = map_writes_norms(c) ? out_sqn : nullptr;
     POT_TRY(pot::launch_entropic_map(a, s));
     return POT_OK;
 }
@@ -322,11 +326,12 @@ float *pinned_slot(float **dev) {
 }
 
 // Synchronous mean-cost refresh of the source iterate (single-problem path);
-// for a general cost, the cost matrix is rebuilt with it.
-int refresh_mean_cost(pot_clouds *c, const Layout &L, hipStream_t s) {
+// for a general cost, the cost matrix is rebuilt with it.  norms_ready: the
+// map that moved the iterate wrote its squared norms.
+int refresh_mean_cost(pot_clouds *c, const Layout &L, hipStream_t s, bool norms_ready = false) {
     if (c->cost_p != 0.f) return refresh_pcost(c, L, s);
     std::vector<double> host(moments_len(c->d));
-    int st = enqueue_moments(c, L, host.data(), s);
+    int st = enqueue_moments(c, L, host.data(), s, norms_ready);
     if (st != POT_OK) return st;
     POT_TRY(hipStreamSynchronize(s));
     return finish_moments(c, host.data());
@@ -656,9 +661,10 @@ int pot_progot_solve(pot_clouds *c, const pot_progot_params *p, float *f, float 
         loc.iters[k] = r.iters; loc.err[k] = r.err; loc.eps[k] = eps; loc.alpha[k] = alpha[k];
         if (!r.converged) loc.converged = 0;
         if (k + 1 < K) {
-            st = run_map(c, G + (size_t)k * m, eps, c->xk, n, alpha[k], c->xk, s);
+            st = run_map(c, G + (size_t)k * m, eps, c->xk, n, alpha[k], c->xk, s, c->x_sqn);
             if (st != POT_OK) return st;
-            st = refresh_mean_cost(c, L, s);  // norms, BF16 copy and mean cost of X^(k+1)
+            // norms (unless the map wrote them), BF16 copy and mean cost of X^(k+1)
+            st = refresh_mean_cost(c, L, s, map_writes_norms(c));
             if (st != POT_OK) return st;
         } else {
             POT_TRY(hipMemcpyAsync(f, r.f, n * sizeof(float), hipMemcpyDeviceToDevice, s));

@@ -15,6 +15,20 @@ constexpr float kNegBig = -1.0e30f;  // finite "minus infinity" of running maxim
 
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// Loads and stores of global memory through pointers whose address space the
+// compiler cannot infer (fields of a job table in device memory).  Without the
+// cast they compile to flat instructions, which also count against the LDS
+// wait counter, so every LDS wait in a tile loop would also wait for the
+// next tile's prefetch.  T must be a scalar or an ext_vector_type.
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void stg(T *p, T v) {
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -29,13 +43,13 @@ __device__ __forceinline__ void row_fetch(const float *__restrict__ U, int64_t n
         const f4 *p = reinterpret_cast<const f4 *>(U + row * D + c0);
 #pragma unroll
         for (int k = 0; k < KD / 4; ++k) {
-            f4 v = p[k];
+            f4 v = ldg(p + k);
             u[4 * k + 0] = v.x; u[4 * k + 1] = v.y; u[4 * k + 2] = v.z; u[4 * k + 3] = v.w;
         }
     } else {
 #pragma unroll
         for (int k = 0; k < KD; ++k)
-            u[k] = (row < nu && c0 + k < d) ? U[row * d + c0 + k] : 0.f;
+            u[k] = (row < nu && c0 + k < d) ? ldg(U + row * d + c0 + k) : 0.f;
     }
 }
 

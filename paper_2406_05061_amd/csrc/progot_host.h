@@ -60,8 +60,15 @@ inline int moments_len(int d) { return 2 * (d + 1); }
 // source's, then the moments' copy into `host` (2 (d+1) doubles, pinned or
 // not: the caller synchronises before finish_moments).
 int enqueue_prepare(pot_clouds *c, const Layout &L, double *host, hipStream_t s);
-// Enqueue the source iterate's norms, BF16 copies and moments, and the copy.
-int enqueue_moments(pot_clouds *c, const Layout &L, double *host, hipStream_t s);
+// Enqueue the source iterate's norms (unless norms_ready), BF16 copies and
+// moments, and the copy.
+int enqueue_moments(pot_clouds *c, const Layout &L, double *host, hipStream_t s,
+                    bool norms_ready = false);
+// True when the McCann step's map writes the moved source's squared norms
+// itself (the FP32 squared-Euclidean form): then the moments pass after it
+// skips the norm kernel.  The single-problem loop and the server both
+// follow this, so a problem gets the same bits either way.
+bool map_writes_norms(const pot_clouds *c);
 // mean_ij |x_i - y_j|^2 = (1/n) sum |x|^2 + (1/m) sum |y|^2 - 2 xbar . ybar.
 int finish_moments(pot_clouds *c, const double *host);
 
@@ -75,8 +82,9 @@ int step_values(const pot_progot_params *p, const float *alpha, int k, double me
                 float *eps, float *tau, float *gamma);
 bool valid_params(const pot_progot_params *p);
 
+// out_sqn (FP32 squared-Euclidean form only, else ignored): |Xout_i|^2.
 int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int64_t nq,
-            float alpha, float *Xout, hipStream_t s);
+            float alpha, float *Xout, hipStream_t s, float *out_sqn = nullptr);
 
 // Alg. 1 on c->xk as pot_sinkhorn_solve runs it; f and g point into the
 // clouds' workspace and stay valid until the next solve on it.

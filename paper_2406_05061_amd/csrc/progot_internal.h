@@ -75,6 +75,7 @@ struct LseJob {
     int esum_n;
     float *esum_out;
 };
+
 typedef LseJob LseArgs;
 
 // Choose S, the scales and the workgroup counts of a job.  Depends only on
@@ -86,19 +87,16 @@ void plan_lse_job(LseJob &j);
 // error partials written to err_part (0 if pot_old is NULL).
 hipError_t launch_lse_update(const LseArgs &a, hipStream_t s, int *n_err_part);
 
-// Grouped form: every job of `jobs` (host array, planned, FP32, all of one
-// padded dimension) in one partial launch and one merge launch; jobs_dev is
-// device memory holding a copy of the planned jobs with blk_begin/mblk_begin
-// filled (done here, via an async copy from the host array, which must stay
-// alive until the stream reaches the copy).  err sums of jobs with pot_old go
-// to err_out[k] for the k-th such job.
-hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, float *err_out,
-                                   hipStream_t s);
-
-// The two halves of launch_lse_update_group, for callers that upload the
-// tables of several grouped updates in one copy: plan_lse_update_group plans
-// the host array in place (block offsets included) and fills the totals;
-// enqueue_lse_update_group launches on a device copy of that planned array.
+// Grouped potential updates: every job of a host array (FP32, all of one
+// padded dimension) in one partial launch and one merge launch, both
+// persistent kernels (a static walk of the jobs' work list), plus one
+// error-sum launch for the jobs that
+// carry pot_old.  plan_lse_update_group plans the host array in place --
+// reordering it, largest items first, and filling the work-list offsets --
+// and the totals; enqueue_lse_update_group launches on a device copy of that
+// planned array (callers upload the tables of several updates in one copy).
+// Error sums go to err_out[k] for the k-th job with pot_old in the planned
+// order (err_out may be NULL when the jobs carry control words).
 struct GroupPlan {
     int64_t blocks, mblocks;
     int nerr;
@@ -117,11 +115,12 @@ hipError_t launch_sum_f32(const float *part, int n, float *out, hipStream_t s);
 // of launch_sum_f32.
 bool lse_update_folds_sum(const LseJob &j);
 
-// Per-point squared norms in FP64 (rounded to FP32), optional BF16 hi/lo
-// copies (lp != NULL), and FP64 partial sums of (sum_i x_i, sum_i |x_i|^2)
-// into stats (nblk x (d+1)).
+// Per-point squared norms in FP64 (rounded to FP32; skipped when
+// norms_ready: the entropic map that produced X wrote them), optional BF16
+// hi/lo copies (lp != NULL), and FP64 partial sums of (sum_i x_i,
+// sum_i |x_i|^2) into stats (nblk x (d+1)).
 hipError_t launch_cloud_prep(const float *X, int64_t n, int d, float *sqn, void *lp,
-                             double *stats_part, int nblk, hipStream_t s);
+                             double *stats_part, int nblk, hipStream_t s, bool norms_ready = false);
 int cloud_stat_blocks(int64_t n);
 
 // log of probability weights (w == NULL: uniform).
@@ -146,6 +145,30 @@ struct MapArgs {
     float *out_sqn;        // |Xout_i|^2 (nullable)
 };
 hipError_t launch_entropic_map(const MapArgs &a, hipStream_t s);
+
+// Grouped FP32 maps (one launch for many maps of one padded dimension, each
+// computing exactly what launch_entropic_map computes for it).  plan_map_group
+// reorders the host array (largest first) and fills the work-list offsets;
+// enqueue_map_group launches on a device copy of the planned array.
+struct MapJob {
+    const float *Xq;
+    int64_t nq;
+    const float *Y;
+    int64_t m;
+    const float *ysq, *g;
+    float scale2, bscale, alpha;
+    int d;
+    float *Xout, *out_sqn;
+    int64_t blk_begin;
+};
+struct MapGroupPlan {
+    int64_t blocks;
+    int D;
+};
+MapJob map_job(const MapArgs &a);   // FP32 args, squared-Euclidean cost
+hipError_t plan_map_group(MapJob *jobs, int njobs, MapGroupPlan *gp);
+hipError_t enqueue_map_group(const MapJob *jobs_dev, int njobs, const MapGroupPlan &gp,
+                             hipStream_t s);
 
 // General costs h(z) = (1/p) sum_k |z_k|^p (FP32 on the VALU).
 int pcost_pad_dim(int d);                 // padded dimension of the map kernel

@@ -23,6 +23,7 @@
 #include "progot_internal.h"
 #include "progot_device.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace pot {
@@ -61,11 +62,11 @@ __device__ __forceinline__ int tchunk(int j, int c) {
 // feature d) into registers: thread t takes LDS chunks t, t + 256, ...
 template <int D, int BN>
 __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t nv, int d,
-                                           int64_t j0, f4 (&pre)[Tile<D, BN>::PER_T]) {
+                                           int64_t j0, int tid, f4 (&pre)[Tile<D, BN>::PER_T]) {
     using T = Tile<D, BN>;
 #pragma unroll
     for (int r = 0; r < T::PER_T; ++r) {
-        const int e = threadIdx.x + 256 * r;
+        const int e = tid + 256 * r;
         f4 v = {0.f, 0.f, 0.f, 0.f};
         if (T::NCH % 256 == 0 || e < T::NCH) {
             const int cc = (e >> 4) % T::C;
@@ -74,13 +75,13 @@ __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t 
             const int64_t j = j0 + row;
             if (j < nv) {
                 if (d == D) {
-                    v = *reinterpret_cast<const f4 *>(V + j * D + c);
+                    v = ldg(reinterpret_cast<const f4 *>(V + j * D + c));
                 } else {
                     const float *p = V + j * d;
-                    v.x = c + 0 < d ? p[c + 0] : 0.f;
-                    v.y = c + 1 < d ? p[c + 1] : 0.f;
-                    v.z = c + 2 < d ? p[c + 2] : 0.f;
-                    v.w = c + 3 < d ? p[c + 3] : 0.f;
+                    v.x = c + 0 < d ? ldg(p + c + 0) : 0.f;
+                    v.y = c + 1 < d ? ldg(p + c + 1) : 0.f;
+                    v.z = c + 2 < d ? ldg(p + c + 2) : 0.f;
+                    v.w = c + 3 < d ? ldg(p + c + 3) : 0.f;
                 }
             }
         }
@@ -89,13 +90,25 @@ __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t 
 }
 
 template <int D, int BN>
-__device__ __forceinline__ void tile_store(float *__restrict__ lds, const f4 (&pre)[Tile<D, BN>::PER_T]) {
+__device__ __forceinline__ void tile_store(float *__restrict__ lds, int tid,
+                                           const f4 (&pre)[Tile<D, BN>::PER_T]) {
     using T = Tile<D, BN>;
 #pragma unroll
     for (int r = 0; r < T::PER_T; ++r) {
-        const int e = threadIdx.x + 256 * r;
+        const int e = tid + 256 * r;
         if (T::NCH % 256 == 0 || e < T::NCH) *reinterpret_cast<f4 *>(lds + 4 * e) = pre[r];
     }
+}
+
+// The thread id, hidden from loop-invariant code motion: in the persistent
+// kernels the bodies run once per work item, and without this the compiler
+// hoists every lane-dependent address out of the item loop and keeps it live
+// across items, which pushed the D = 128 kernels into register spills.
+__device__ __forceinline__ int item_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    __builtin_assume(t >= 0 && t < 256);
+    return t;
 }
 
 // Partial log-sum-exp of t_ij over one column split, for ROWS = 64*QB rows
@@ -123,7 +136,7 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
     float *__restrict__ part_m = J.part_m;
     float *__restrict__ part_s = J.part_s;
 
-    const int tid = threadIdx.x;
+    const int tid = item_tid();
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lq = lane >> 4;
     const int64_t row0 = tile * ROWS + wave * (QB * 16);
@@ -154,13 +167,13 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
     auto fetch_beta = [&](int64_t j0) {
         if (tid < T::BN) {
             const int64_t j = j0 + tid;
-            bpre = j < c1 ? ((vpot ? gamma * vpot[j] : 0.f) - vsq[j]) * bscale : -INFINITY;
+            bpre = j < c1 ? ((vpot ? gamma * ldg(vpot + j) : 0.f) - ldg(vsq + j)) * bscale : -INFINITY;
         }
     };
     if (ntiles > 0) {
-        tile_fetch<D, T::BN>(V, c1, d, c0, pre);
+        tile_fetch<D, T::BN>(V, c1, d, c0, tid, pre);
         fetch_beta(c0);
-        tile_store<D, T::BN>(vt[0], pre);
+        tile_store<D, T::BN>(vt[0], tid, pre);
         if (tid < T::BN) bt[0][tid] = bpre;
     }
     __syncthreads();
@@ -170,7 +183,7 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
         const bool more = t + 1 < ntiles;
         if (more) {
             const int64_t jn = c0 + (int64_t)(t + 1) * T::BN;
-            tile_fetch<D, T::BN>(V, c1, d, jn, pre);
+            tile_fetch<D, T::BN>(V, c1, d, jn, tid, pre);
             fetch_beta(jn);
         }
         const float *vb = vt[buf];
@@ -210,7 +223,7 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
             run_m[qb] = mn;
         }
         if (more) {
-            tile_store<D, T::BN>(vt[buf ^ 1], pre);
+            tile_store<D, T::BN>(vt[buf ^ 1], tid, pre);
             if (tid < T::BN) bt[buf ^ 1][tid] = bpre;
         }
         __syncthreads();
@@ -229,8 +242,8 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
         }
         const int64_t row = row0 + qb * 16 + li;
         if (lq == 0 && row < nu) {
-            part_m[split * nu + row] = m;
-            part_s[split * nu + row] = s;
+            stg(part_m + split * nu + row, m);
+            stg(part_s + split * nu + row, s);
         }
     }
 }
@@ -244,30 +257,41 @@ __global__ __launch_bounds__(256) void lse_partial_f32(LseJob J) {
     lse_partial_body<D, QB>(J, blockIdx.x / J.S, blockIdx.x % J.S, vt, bt);
 }
 
-// Index of the job owning flattened block `item` (jobs sorted by `begin`).
-template <bool MERGE>
-__device__ __forceinline__ int find_job(const LseJob *__restrict__ jobs, int njobs, int64_t item) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        const int64_t b = MERGE ? jobs[mid].mblk_begin : jobs[mid].blk_begin;
-        if (b <= item) lo = mid; else hi = mid - 1;
-    }
-    return lo;
+// Persistent grouped kernels.  A grouped launch covers the work list of many
+// jobs (problems of different sizes, or the grid points of Alg. 4): item i of
+// the list is workgroup-sized work of the job whose [begin, begin + blocks)
+// range holds i.  The grid is at most the number of workgroups the chip holds
+// at once, and workgroup w walks the items w, w + G, w + 2G, ... (G the grid
+// size), a static walk every workgroup finishes.  Workgroup w runs on XCD
+// w mod 8 and G is a multiple of 8, so an XCD always gets the items with one
+// residue mod 8; the potential kernel's jobs start on multiples of 8 in the
+// list and split their columns S ways (S a power of two), so with S >= 8 an
+// XCD streams a fixed subset of the column splits through its own L2, as a
+// flat launch of one job would.  Items run the same device body as the
+// single-problem kernels, so a problem gets the same bits alone or grouped,
+// whichever workgroup runs an item.
+
+// The control word of a problem's Sinkhorn loop is nonzero once it stopped
+// (written by an earlier launch on the stream; read as global memory).
+__device__ __forceinline__ bool stopped(const int *ctl) {
+    return *(volatile const __attribute__((address_space(1))) int *)ctl != 0;
 }
 
-// Grouped: one launch covers the flattened work list of many jobs (problems
-// of different sizes); block b finds its job by binary search over the jobs'
-// first-block offsets and runs the same body as the single-job kernel, so
-// every problem gets the same bits as when it runs alone.
 template <int D, int QB>
-__global__ __launch_bounds__(256) void lse_partial_f32_group(const LseJob *__restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(256) void lse_partial_f32_group(const LseJob *__restrict__ jobs, int njobs,
+                                                             int64_t total) {
     __shared__ float vt[2][LseTile<D>::FLOATS];
     __shared__ float bt[2][LseTile<D>::BN];
-    const LseJob &J = jobs[find_job<false>(jobs, njobs, blockIdx.x)];
-    if (J.ctl && *(volatile const int *)J.ctl != 0) return;   // loop already stopped
-    const int64_t local = (int64_t)blockIdx.x - J.blk_begin;
-    lse_partial_body<D, QB>(J, local / J.S, (int)(local % J.S), vt, bt);
+    int j = 0;   // the walk's items increase, so the owning job only advances
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        while (j + 1 < njobs && jobs[j + 1].blk_begin <= item) ++j;
+        const LseJob &J = jobs[j];
+        const int64_t local = item - J.blk_begin;
+        if (local >= J.blocks) continue;                 // alignment gap before the next job
+        if (J.ctl && stopped(J.ctl)) continue;           // loop already stopped
+        lse_partial_body<D, QB>(J, local / J.S, (int)(local % J.S), vt, bt);
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ float block_sum_256(float v, float *red) {
@@ -299,20 +323,20 @@ __device__ __forceinline__ void lse_merge_body(const LseJob &J, int64_t blk, flo
         float M = kNegBig, sum = 0.f;
 #pragma unroll 8
         for (int s = 0; s < S; ++s) {
-            const float m = part_m[s * nu + i], v = part_s[s * nu + i];
+            const float m = ldg(part_m + s * nu + i), v = ldg(part_s + s * nu + i);
             const float Mn = fmaxf(M, m);
             sum = sum * exp2f(M - Mn) + v * exp2f(m - Mn);
             M = Mn;
         }
         const float L = M + log2f(sum);
-        const float lw = J.logw[i];
-        const float pot = fmaf(eps, lw, J.usq ? J.usq[i] : 0.f) - eps * kLn2 * L;
-        if (J.pot_old) e = expf(lw) * fabsf(expm1f((J.pot_old[i] - pot) / eps));
-        J.pot_out[i] = pot;
+        const float lw = ldg(J.logw + i);
+        const float pot = fmaf(eps, lw, J.usq ? ldg(J.usq + i) : 0.f) - eps * kLn2 * L;
+        if (J.pot_old) e = expf(lw) * fabsf(expm1f((ldg(J.pot_old + i) - pot) / eps));
+        stg(J.pot_out + i, pot);
     }
     if (J.pot_old) {
         const float tot = block_sum_256(e, red);
-        if (threadIdx.x == 0) J.err_part[blk] = tot;
+        if (threadIdx.x == 0) stg(J.err_part + blk, tot);
     }
 }
 
@@ -321,11 +345,17 @@ __global__ __launch_bounds__(256) void lse_merge(LseJob J) {
     lse_merge_body(J, blockIdx.x, red);
 }
 
-__global__ __launch_bounds__(256) void lse_merge_group(const LseJob *__restrict__ jobs, int njobs) {
+__global__ __launch_bounds__(256) void lse_merge_group(const LseJob *__restrict__ jobs, int njobs,
+                                                      int64_t total) {
     __shared__ float red[256];
-    const LseJob J = jobs[find_job<true>(jobs, njobs, blockIdx.x)];
-    if (J.ctl && *(volatile const int *)J.ctl != 0) return;   // loop already stopped
-    lse_merge_body(J, blockIdx.x - J.mblk_begin, red);
+    int j = 0;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        while (j + 1 < njobs && jobs[j + 1].mblk_begin <= item) ++j;
+        const LseJob &J = jobs[j];
+        if (J.ctl && stopped(J.ctl)) continue;   // loop already stopped
+        lse_merge_body(J, item - J.mblk_begin, red);
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ void sum_body(const float *__restrict__ part, int n, float *out,
@@ -465,7 +495,7 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
     constexpr int ROWS = 64 * QB;
     constexpr int NDB = D / 16;   // 16-feature blocks of the output
 
-    const int tid = threadIdx.x;
+    const int tid = item_tid();
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lq = lane >> 4;
     const int64_t row0 = tile * ROWS + wave * (QB * 16);
@@ -503,13 +533,13 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
     auto fetch_beta = [&](int64_t j0) {
         if (tid < T::BN) {
             const int64_t j = j0 + tid;
-            bpre = j < m ? (g[j] - ysq[j]) * bscale : -INFINITY;
+            bpre = j < m ? (ldg(g + j) - ldg(ysq + j)) * bscale : -INFINITY;
         }
     };
     if (ntiles > 0) {
-        tile_fetch<D, T::BN>(Y, m, d, 0, pre);
+        tile_fetch<D, T::BN>(Y, m, d, 0, tid, pre);
         fetch_beta(0);
-        tile_store<D, T::BN>(vt[0], pre);
+        tile_store<D, T::BN>(vt[0], tid, pre);
         if (tid < T::BN) bt[0][tid] = bpre;
     }
     __syncthreads();
@@ -519,7 +549,7 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
         const bool more = t + 1 < ntiles;
         if (more) {
             const int64_t jn = (int64_t)(t + 1) * T::BN;
-            tile_fetch<D, T::BN>(Y, m, d, jn, pre);
+            tile_fetch<D, T::BN>(Y, m, d, jn, tid, pre);
             fetch_beta(jn);
         }
         const float *vb = vt[buf];
@@ -584,7 +614,7 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
                 }
         }
         if (more) {
-            tile_store<D, T::BN>(vt[buf ^ 1], pre);
+            tile_store<D, T::BN>(vt[buf ^ 1], tid, pre);
             if (tid < T::BN) bt[buf ^ 1][tid] = bpre;
         }
         __syncthreads();
@@ -605,11 +635,11 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
                 if (f0 >= d) continue;
                 float xo[4], xn[4];
                 if (f0 + 3 < d && (d & 3) == 0) {
-                    f4 v = *reinterpret_cast<const f4 *>(Xq + row * d + f0);
+                    f4 v = ldg(reinterpret_cast<const f4 *>(Xq + row * d + f0));
                     xo[0] = v.x; xo[1] = v.y; xo[2] = v.z; xo[3] = v.w;
                 } else {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) xo[r] = f0 + r < d ? Xq[row * d + f0 + r] : 0.f;
+                    for (int r = 0; r < 4; ++r) xo[r] = f0 + r < d ? ldg(Xq + row * d + f0 + r) : 0.f;
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -617,17 +647,17 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
                     if (f0 + r < d) sq += (double)xn[r] * xn[r];
                 }
                 if (f0 + 3 < d && (d & 3) == 0) {
-                    *reinterpret_cast<f4 *>(Xout + row * d + f0) = f4{xn[0], xn[1], xn[2], xn[3]};
+                    stg(reinterpret_cast<f4 *>(Xout + row * d + f0), f4{xn[0], xn[1], xn[2], xn[3]});
                 } else {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        if (f0 + r < d) Xout[row * d + f0 + r] = xn[r];
+                        if (f0 + r < d) stg(Xout + row * d + f0 + r, xn[r]);
                 }
             }
         }
         sq += __shfl_xor(sq, 16);
         sq += __shfl_xor(sq, 32);
-        if (out_sqn && lq == 0 && row < nq) out_sqn[row] = (float)sq;
+        if (out_sqn && lq == 0 && row < nq) stg(out_sqn + row, (float)sq);
     }
 }
 
@@ -642,6 +672,36 @@ __global__ __launch_bounds__(256) void entropic_map_f32(
                              blockIdx.x, vt, bt);
 }
 
+// Grouped map: the (job, 64-query tile) items of many maps in one launch
+// (the McCann steps and final maps of the serving form).
+template <int D>
+__global__ __launch_bounds__(256) void entropic_map_f32_group(const MapJob *__restrict__ jobs, int njobs,
+                                                              int64_t total) {
+    __shared__ float vt[2][Tile<D>::FLOATS];
+    __shared__ float bt[2][Tile<D>::BN];
+    int j = 0;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        while (j + 1 < njobs && jobs[j + 1].blk_begin <= item) ++j;
+        const MapJob &J = jobs[j];
+        entropic_map_body<D, 1>(J.Xq, J.nq, J.d, J.Y, J.ysq, J.g, J.m, J.scale2, J.bscale, J.alpha,
+                                J.Xout, J.out_sqn, item - J.blk_begin, vt, bt);
+        __syncthreads();
+    }
+}
+
+// Workgroups of `kernel` the chip holds at once (the grid of a persistent
+// launch), for the current device; computed once per kernel.
+template <typename K>
+int64_t resident_blocks(K kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        cus < 1 || per_cu < 1)
+        return 1024;   // a safe default; any grid size gives the same results
+    return (int64_t)cus * per_cu;
+}
+
 template <int D, int QB>
 hipError_t lse_launch_t(const LseJob &j, hipStream_t s) {
     // the plan must cover every row tile of this kernel variant
@@ -650,10 +710,23 @@ hipError_t lse_launch_t(const LseJob &j, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Grid of a persistent launch: the workgroups the chip holds at once, or
+// fewer when the list is short.
+inline unsigned group_grid(int64_t total, int64_t cap) { return (unsigned)std::min(total, cap); }
+
 template <int D, int QB>
 hipError_t lse_group_launch_t(const LseJob *jobs_dev, int njobs, int64_t total, hipStream_t s) {
-    timed_launch(0, lse_partial_f32_group<D, QB>, dim3((unsigned)total), dim3(256), 0, s, jobs_dev,
-                 njobs);
+    static const int64_t cap = resident_blocks(lse_partial_f32_group<D, QB>);
+    timed_launch(0, lse_partial_f32_group<D, QB>, dim3(group_grid(total, cap)), dim3(256), 0, s, jobs_dev,
+                 njobs, total);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t map_group_launch_t(const MapJob *jobs_dev, int njobs, int64_t total, hipStream_t s) {
+    static const int64_t cap = resident_blocks(entropic_map_f32_group<D>);
+    timed_launch(1, entropic_map_f32_group<D>, dim3(group_grid(total, cap)), dim3(256), 0, s, jobs_dev,
+                 njobs, total);
     return hipGetLastError();
 }
 
@@ -767,6 +840,13 @@ hipError_t plan_lse_update_group(LseJob *jobs, int njobs, GroupPlan *gp) {
         if (jobs[k].cost_p != 0.f || jobs[k].esum_out) return hipErrorInvalidValue;
         plan_lse_job(jobs[k]);
         if (jobs[k].precision != 0 || padded_dim(jobs[k].d) != D) return hipErrorInvalidValue;
+    }
+    // largest items first (an item is a row tile times cps columns): every
+    // workgroup's share of the static walk starts with the long items and
+    // the walk ends on short ones
+    std::stable_sort(jobs, jobs + njobs, [](const LseJob &a, const LseJob &b) { return a.cps > b.cps; });
+    for (int k = 0; k < njobs; ++k) {
+        blk = (blk + 7) / 8 * 8;   // jobs start on multiples of 8 (XCD affinity of the splits)
         jobs[k].blk_begin = blk;
         jobs[k].mblk_begin = mblk;
         blk += jobs[k].blocks;
@@ -788,21 +868,47 @@ hipError_t enqueue_lse_update_group(const LseJob *jobs_dev, int njobs, const Gro
         default: e = lse_group_launch_t<256, lse_qb(256)>(jobs_dev, njobs, gp.blocks, s); break;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(lse_merge_group, dim3((unsigned)gp.mblocks), dim3(256), 0, s, jobs_dev, njobs);
+    static const int64_t mcap = resident_blocks(lse_merge_group);
+    hipLaunchKernelGGL(lse_merge_group, dim3(group_grid(gp.mblocks, mcap)), dim3(256), 0, s, jobs_dev, njobs,
+                       gp.mblocks);
     if (gp.nerr > 0)
         hipLaunchKernelGGL(sum_group, dim3(gp.nerr), dim3(256), 0, s, jobs_dev, njobs, err_out);
     return hipGetLastError();
 }
 
-hipError_t launch_lse_update_group(LseJob *jobs, int njobs, LseJob *jobs_dev, float *err_out,
-                                   hipStream_t s) {
-    if (njobs <= 0) return hipSuccess;
-    GroupPlan gp;
-    hipError_t e = plan_lse_update_group(jobs, njobs, &gp);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(jobs_dev, jobs, sizeof(LseJob) * njobs, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    return enqueue_lse_update_group(jobs_dev, njobs, gp, err_out, s);
+MapJob map_job(const MapArgs &a) {
+    MapJob j{};
+    j.Xq = a.Xq; j.nq = a.nq; j.Y = a.Y; j.m = a.m; j.ysq = a.ysq; j.g = a.g;
+    j.scale2 = 2.f * kLog2e / a.eps;   // as launch_entropic_map
+    j.bscale = kLog2e / a.eps;
+    j.alpha = a.alpha; j.d = a.d; j.Xout = a.Xout; j.out_sqn = a.out_sqn;
+    return j;
+}
+
+hipError_t plan_map_group(MapJob *jobs, int njobs, MapGroupPlan *gp) {
+    if (njobs <= 0) return hipErrorInvalidValue;
+    const int D = padded_dim(jobs[0].d);
+    for (int k = 0; k < njobs; ++k)
+        if (padded_dim(jobs[k].d) != D || jobs[k].nq < 1) return hipErrorInvalidValue;
+    // largest items (most targets) first, as for the potential updates
+    std::stable_sort(jobs, jobs + njobs, [](const MapJob &a, const MapJob &b) { return a.m > b.m; });
+    int64_t blk = 0;
+    for (int k = 0; k < njobs; ++k) {
+        jobs[k].blk_begin = blk;
+        blk += (jobs[k].nq + 63) / 64;   // 64 queries per workgroup (one 16-row block per wave)
+    }
+    *gp = MapGroupPlan{blk, D};
+    return hipSuccess;
+}
+
+hipError_t enqueue_map_group(const MapJob *jobs_dev, int njobs, const MapGroupPlan &gp, hipStream_t s) {
+    switch (gp.D) {
+        case 16: return map_group_launch_t<16>(jobs_dev, njobs, gp.blocks, s);
+        case 32: return map_group_launch_t<32>(jobs_dev, njobs, gp.blocks, s);
+        case 64: return map_group_launch_t<64>(jobs_dev, njobs, gp.blocks, s);
+        case 128: return map_group_launch_t<128>(jobs_dev, njobs, gp.blocks, s);
+        default: return map_group_launch_t<256>(jobs_dev, njobs, gp.blocks, s);
+    }
 }
 
 hipError_t launch_sum_f32(const float *part, int n, float *out, hipStream_t s) {
@@ -818,8 +924,9 @@ int cloud_stat_blocks(int64_t n) {
 }
 
 hipError_t launch_cloud_prep(const float *X, int64_t n, int d, float *sqn, void *lp,
-                             double *stats_part, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL(cloud_norms, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, sqn);
+                             double *stats_part, int nblk, hipStream_t s, bool norms_ready) {
+    if (!norms_ready)
+        hipLaunchKernelGGL(cloud_norms, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, n, d, sqn);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && lp) e = launch_bf16_rows(X, n, d, lp, s);
     if (e != hipSuccess || !stats_part) return e;

@@ -3,14 +3,16 @@
 //
 // Requests are admitted while a slot and room in the caller's device arena
 // are free (first-fit by HBM footprint, the workspace of one solve).  A tick
-// advances every active request by one Sinkhorn iteration: all their
-// f-updates run in one grouped launch per padded dimension, then all their
-// g-updates, then one read-back of every request's row-marginal error.
-// Requests whose solve met its tau take their McCann step and move to the
-// next ProgOT step (or finish) between ticks; new requests join at the next
-// tick.  Each request runs the same kernels with the same splits and the same
-// host arithmetic as pot_progot_solve, so its result is bit-identical to a
-// solve on its own.
+// advances every active request by up to kMaxSub Sinkhorn iterations: each
+// sub-step runs all f-updates in one grouped, persistent launch per padded
+// dimension (a grid of resident workgroups walking the work list), then all
+// g-updates; the stop rule runs on the device, and one read-back of every
+// request's control word ends the tick.  The requests whose solve ended then
+// take their maps (McCann steps and final maps) in one grouped launch per
+// padded dimension and move to the next ProgOT step (or finish); new
+// requests join at the next tick.  Each request runs the same device bodies
+// with the same splits and the same host arithmetic as pot_progot_solve, so
+// its result is bit-identical to a solve on its own.
 
 #include "progot.h"
 #include "progot_host.h"
@@ -94,6 +96,8 @@ size_t jobs_bytes(int max_active) {
     return a256(sizeof(pot::LseJob) * 2 * (size_t)max_active * kMaxSub);
 }
 size_t ctl_bytes(int max_active) { return a256(sizeof(int) * 2 * (size_t)max_active); }
+// at most one map per request and tick (its McCann step or its final map)
+size_t maps_bytes(int max_active) { return a256(sizeof(pot::MapJob) * (size_t)max_active); }
 
 }  // namespace
 
@@ -106,7 +110,9 @@ struct pot_server {
     FirstFit fit;
     pot::LseJob *jobs_dev = nullptr;   // in the arena: kMaxSub x (f, g) x max_active
     int *ctl_dev = nullptr;            // in the arena: per slot {stop iterate, err bits}
+    pot::MapJob *maps_dev = nullptr;   // in the arena: the tick's grouped maps
     pot::LseJob *jobs_host = nullptr;  // pinned mirror of jobs_dev
+    pot::MapJob *maps_host = nullptr;  // pinned mirror of maps_dev
     int *ctl_host = nullptr;           // pinned
     double *mom_host = nullptr;        // pinned, max_active x moments_len(POT_MAX_D)
     std::vector<int> free_slots;
@@ -137,10 +143,13 @@ int start_step(pot_server *S, Req *r, const double *mom) {
     return POT_OK;
 }
 
-// Iterate s of step k met its tau (or hit max_iter): store g^(k), then either
-// move the source (next step) or write the outputs.  Returns true when the
-// request has finished (its final copies are enqueued).
-int finish_step(pot_server *S, Req *r, int s_it, float err, bool converged, bool *done) {
+// Iterate s of step k met its tau (or hit max_iter): store g^(k) and, for the
+// last step, f; then describe the map this step ends with -- the McCann step
+// of the source in place (next step, *moving) or the final map into TX --
+// in *mj (*has_map), for the tick's grouped map launch.  *done when the
+// request finishes with this step.
+int finish_step(pot_server *S, Req *r, int s_it, float err, bool converged, bool *done, bool *moving,
+                pot::MapJob *mj, bool *has_map) {
     pot_clouds *c = &r->c;
     const int64_t m = c->m, n = c->n;
     const int k = r->k;
@@ -151,21 +160,25 @@ int finish_step(pot_server *S, Req *r, int s_it, float err, bool converged, bool
     if (!converged) r->info.converged = 0;
     float *Gk = r->G + (size_t)k * m;
     POT_TRY(hipMemcpyAsync(Gk, r->gb[s_it & 1], m * sizeof(float), hipMemcpyDeviceToDevice, S->s));
+    // the arguments run_map would pass for this map
+    pot::MapArgs a{};
+    a.Xq = c->xk; a.nq = n; a.Y = c->Y; a.m = m; a.ysq = c->y_sqn; a.g = Gk; a.eps = r->eps;
+    a.d = c->d; a.precision = POT_PREC_FP32;
     if (k + 1 < r->p.K) {
-        int st = run_map(c, Gk, r->eps, c->xk, n, r->alpha[k], c->xk, S->s);
-        if (st != POT_OK) return st;
-        st = enqueue_moments(c, r->L, moments_slot(S, r->slot), S->s);
-        if (st != POT_OK) return st;
-        r->k = k + 1;
-        r->state = ST_PREP;
+        a.alpha = r->alpha[k]; a.Xout = c->xk; a.out_sqn = c->x_sqn;
+        *mj = pot::map_job(a);
+        *has_map = true;
+        *moving = true;
         *done = false;
     } else {
         POT_TRY(hipMemcpyAsync(r->f_out, r->fb[s_it & 1], n * sizeof(float), hipMemcpyDeviceToDevice,
                                S->s));
-        if (r->TX) {
-            const int st = run_map(c, Gk, r->eps, c->xk, n, 1.f, r->TX, S->s);
-            if (st != POT_OK) return st;
+        *has_map = r->TX != nullptr;
+        if (*has_map) {
+            a.alpha = 1.f; a.Xout = r->TX; a.out_sqn = nullptr;
+            *mj = pot::map_job(a);
         }
+        *moving = false;
         *done = true;
     }
     return POT_OK;
@@ -177,7 +190,7 @@ extern "C" {
 
 size_t pot_server_arena_overhead(int32_t max_active) {
     if (max_active < 1 || max_active > POT_SERVER_MAX_ACTIVE) return 0;
-    return jobs_bytes(max_active) + ctl_bytes(max_active);
+    return jobs_bytes(max_active) + ctl_bytes(max_active) + maps_bytes(max_active);
 }
 
 size_t pot_server_request_bytes(int64_t n, int64_t m, int32_t d) {
@@ -198,11 +211,14 @@ int pot_server_create(pot_server **out, void *arena, size_t arena_bytes, int32_t
     S->max_active = max_active;
     S->jobs_dev = reinterpret_cast<pot::LseJob *>(S->arena);
     S->ctl_dev = reinterpret_cast<int *>(S->arena + jobs_bytes(max_active));
+    S->maps_dev = reinterpret_cast<pot::MapJob *>(S->arena + jobs_bytes(max_active) + ctl_bytes(max_active));
     S->base = over;
     S->fit.init((arena_bytes - over) & ~size_t(255));
     if (hipHostMalloc(reinterpret_cast<void **>(&S->jobs_host), jobs_bytes(max_active),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&S->ctl_host), ctl_bytes(max_active),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&S->maps_host), maps_bytes(max_active),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&S->mom_host),
                       sizeof(double) * moments_len(POT_MAX_D) * max_active, hipHostMallocDefault) != hipSuccess) {
@@ -359,7 +375,8 @@ int pot_server_step(pot_server *S, int32_t *n_active, int32_t *n_finished) {
     POT_TRY(hipStreamSynchronize(S->s));
 
     int status = POT_OK;
-    std::vector<Req *> done_now, keep;
+    std::vector<Req *> done_now, keep, moving;
+    int nmap = 0;   // map jobs of this tick, in the pinned mirror
     for (Req *r : S->active) {
         bool done = false;
         int st = POT_OK;
@@ -375,7 +392,10 @@ int pot_server_step(pot_server *S, int32_t *n_active, int32_t *n_finished) {
                     st = POT_ERR_NUMERIC;
                 } else {
                     const bool conv = r->tau > 0.f ? err <= r->tau : true;
-                    st = finish_step(S, r, ctl[0], err, conv, &done);
+                    bool mv = false, has_map = false;
+                    st = finish_step(S, r, ctl[0], err, conv, &done, &mv, S->maps_host + nmap, &has_map);
+                    if (st == POT_OK && has_map) ++nmap;
+                    if (st == POT_OK && mv) moving.push_back(r);
                 }
             } else {
                 const auto pos = std::find(solving.begin(), solving.end(), r) - solving.begin();
@@ -392,6 +412,38 @@ int pot_server_step(pot_server *S, int32_t *n_active, int32_t *n_finished) {
         }
         (done ? done_now : keep).push_back(r);
     }
+    // The maps every step that ended in this tick finishes with (McCann steps
+    // and final maps): one grouped launch per padded dimension, all tables in
+    // one upload; then the moved sources' moments (the maps wrote their norms).
+    if (nmap > 0) {
+        pot::MapJob *mj = S->maps_host;
+        std::stable_sort(mj, mj + nmap, [](const pot::MapJob &a, const pot::MapJob &b) {
+            return pot::padded_dim_f32(a.d) < pot::padded_dim_f32(b.d);
+        });
+        std::vector<std::pair<int, int>> runs;   // (offset, count) per dimension class
+        std::vector<pot::MapGroupPlan> plans;
+        for (int i = 0; i < nmap;) {
+            int j = i;
+            while (j < nmap && pot::padded_dim_f32(mj[j].d) == pot::padded_dim_f32(mj[i].d)) ++j;
+            pot::MapGroupPlan gp;
+            POT_TRY(pot::plan_map_group(mj + i, j - i, &gp));
+            runs.push_back({i, j - i});
+            plans.push_back(gp);
+            i = j;
+        }
+        POT_TRY(hipMemcpyAsync(S->maps_dev, mj, sizeof(pot::MapJob) * nmap, hipMemcpyHostToDevice, S->s));
+        for (size_t g = 0; g < runs.size(); ++g)
+            POT_TRY(pot::enqueue_map_group(S->maps_dev + runs[g].first, runs[g].second, plans[g], S->s));
+    }
+    for (Req *r : moving) {
+        // fails only when a HIP call does: the whole server's error
+        const int st = enqueue_moments(&r->c, r->L, moments_slot(S, r->slot), S->s, true);
+        if (st != POT_OK) return st;
+        r->k += 1;
+        r->state = ST_PREP;
+    }
+    // (the map tables' upload is complete by the next tick's synchronisation,
+    // before the mirror is written again)
     if (!done_now.empty()) {
         POT_TRY(hipStreamSynchronize(S->s));   // final copies and maps are in place
         const double now = now_s();
@@ -431,6 +483,7 @@ int pot_server_destroy(pot_server *S) {
     for (auto &kv : S->finished) delete kv.second;
     if (S->jobs_host) (void)hipHostFree(S->jobs_host);
     if (S->ctl_host) (void)hipHostFree(S->ctl_host);
+    if (S->maps_host) (void)hipHostFree(S->maps_host);
     if (S->mom_host) (void)hipHostFree(S->mom_host);
     delete S;
     return POT_OK;

@@ -37,6 +37,7 @@ Layout plan(int64_t n, int64_t m, int32_t d, int32_t precision, float cost_p, bo
     L.xlp = take(lp ? 2 * (size_t)pot::bf16_mpad(n) * Dp * 2 : 0);
     L.ylp = take(lp ? 2 * (size_t)pot::bf16_mpad(m) * Dp * 2 : 0);
     L.ytl = take(lp ? 2 * Dp * (size_t)pot::bf16_mpad(m) * 2 : 0);
+    L.yts = take(precision == POT_PREC_BF16 ? 2 * sizeof(float) : 0);
     L.f0 = take((size_t)n * 4);
     L.f1 = take((size_t)n * 4);
     L.g0 = take((size_t)m * 4);
@@ -154,7 +155,12 @@ int enqueue_prepare(pot_clouds *c, const Layout &L, double *host, hipStream_t s)
     POT_TRY(pot::launch_log_weights(c->b, c->m, c->log_b, s));
     POT_TRY(pot::launch_cloud_prep(c->Y, c->m, c->d, c->y_sqn, c->y_lp, at<double>(c, L.yst),
                                    pot::cloud_stat_blocks(c->m), s));
-    if (c->yt_lp) POT_TRY(pot::launch_bf16_transpose(c->Y, c->m, c->d, c->yt_lp, s));
+    if (c->yt_lp) {
+        if (c->precision == POT_PREC_BF16)
+            POT_TRY(pot::launch_f16_transpose(c->Y, c->m, c->d, c->yt_lp, at<float>(c, L.yts), s));
+        else
+            POT_TRY(pot::launch_bf16_transpose(c->Y, c->m, c->d, c->yt_lp, s));
+    }
     return enqueue_moments(c, L, host, s);
 }
 
@@ -248,6 +254,7 @@ int run_map(const pot_clouds *c, const float *g, float eps, const float *Xq, int
     a.Xq = Xq; a.nq = nq; a.Y = c->Y; a.Y_lp = c->y_lp; a.m = c->m; a.ysq = c->y_sqn; a.g = g;
     a.eps = eps; a.alpha = alpha; a.d = c->d; a.precision = c->precision;
     a.YT_lp = c->yt_lp; a.mp = pot::bf16_mpad(c->m);
+    a.yt_unscale = c->precision == POT_PREC_BF16 ? at<float>(c, plan_of(c).yts) + 1 : nullptr;
     a.Xout = Xout; a.out_sqn = map_writes_norms(c) ? out_sqn : nullptr;
     POT_TRY(pot::launch_entropic_map(a, s));
     return POT_OK;

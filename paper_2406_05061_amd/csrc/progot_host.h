@@ -17,6 +17,7 @@ struct Layout {
     size_t xk, xsq, ysq, la, lb, xlp, ylp, ytl, f0, f1, g0, g1, pm, ps, errp, xst, yst, chr, chc,
         n64;
     size_t f2, g2;         // third potential slots of the single-problem Sinkhorn loop
+    size_t yts;            // plain BF16 form: max |y| and the unscale of the FP16 copy
     size_t eslot;          // device slots of the error sums when they are copied back
                            // (entry points that allocate no pinned host memory)
     size_t cm, cmp, mpa;   // general costs: cost matrix, its block sums, map partials

@@ -141,6 +141,7 @@ struct MapArgs {
     int d, precision;
     const void *YT_lp;     // transposed BF16 copy of Y (BF16 forms)
     int64_t mp;            // bf16_mpad(m): rows of Y_lp per part, row stride of YT_lp
+    const float *yt_unscale;  // plain BF16 form: 2^-k of the FP16 copy YT_lp = Y 2^k
     float *Xout;           // may alias Xq
     float *out_sqn;        // |Xout_i|^2 (nullable)
 };
@@ -224,6 +225,10 @@ hipError_t launch_bf16_rows(const float *X, int64_t n, int d, void *lp, hipStrea
 // [hi^T | lo^T] of Y, each bf16_dim(d) x bf16_mpad(m) in blocks of 32
 // columns (permuted into the projection product's order, tile layout).
 hipError_t launch_bf16_transpose(const float *Y, int64_t m, int d, void *yt, hipStream_t s);
+// The plain BF16 form's projection copy: one FP16 part of the same layout
+// holding Y 2^k (k from max |y|, so max |y| 2^k <= 2^14); scale2 is two
+// floats of device scratch: [0] max |y| (bits), [1] receives 2^-k.
+hipError_t launch_f16_transpose(const float *Y, int64_t m, int d, void *yt, float *scale2, hipStream_t s);
 
 // FP64 check: FP64 norms of X and Y into xsq64/ysq64 (n and m doubles),
 // then row sums and column sums of P in FP64 reduced to per-block partials

@@ -38,6 +38,8 @@
 // both operands).
 
 #include "progot_internal.h"
+
+#include <algorithm>
 #include "progot_device.h"
 
 namespace pot {
@@ -51,6 +53,39 @@ __device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
 }
 
 __device__ __forceinline__ bf8 bf8_zero() { return __builtin_bit_cast(bf8, u4{0u, 0u, 0u, 0u}); }
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f4 mfma_h(h8 a, h8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// Projection product of the plain BF16 form: FP16 weights times an FP16
+// transposed copy of Y (one product instead of BF16 weights times Y_hi +
+// Y_lo).  The weights are formed as 2^(t - (m - kF16Shift)), i.e. scaled by
+// 2^14, so the largest (exactly 2^14) and those down to ~4e-9 of it stay in
+// FP16's normal range with 11 significant bits (FP16 subnormals start at
+// 6.1e-5); the normaliser sums the same scaled weights, so the scale cancels.
+constexpr float kF16Shift = 14.f;
+
+// The weights 2^(t - shift) of one lane's 8 scores, rounded to FP16 (nearest
+// even), in the B-operand order of the projection product.
+__device__ __forceinline__ h8 weights_f16(const f4 (&acc)[2], float shift) {
+    h8 w;
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+        const f2 v = {ex2(acc[e >> 2][e & 3] - shift), ex2(acc[(e + 1) >> 2][(e + 1) & 3] - shift)};
+        const h2 h = __builtin_convertvector(v, h2);
+        w[e] = h[0];
+        w[e + 1] = h[1];
+    }
+    return w;
+}
+
+__device__ __forceinline__ h8 as_h8(bf8 x) { return __builtin_bit_cast(h8, x); }
+__device__ __forceinline__ bf8 as_bf8(h8 x) { return __builtin_bit_cast(bf8, x); }
 
 // Keeps an operand computed before the tile loop in its registers: without
 // this the compiler re-derives the BF16 row operands from the FP32 rows in
@@ -292,16 +327,17 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     const float *Xq, int64_t nq, int d, const __bf16 *__restrict__ Ylp,
     const __bf16 *__restrict__ YTlp, int64_t m, int64_t mp, const float *__restrict__ ysq,
     const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout,
-    float *__restrict__ out_sqn) {
+    float *__restrict__ out_sqn, const float *__restrict__ yt_unscale) {
     constexpr int BN = kMapBN;
     constexpr int KS = D / 32, C = D / 8;
     constexpr int NDB = D / 16;
     constexpr int ROWS = 64 * QB;
     constexpr int NCH = BN * D / 8;            // 16-byte chunks per part (both copies)
     constexpr int PER_T = (NCH + 255) / 256;
+    constexpr int NYT = NPART == 2 ? 2 : 1;    // parts of the transposed copy (FP16: one)
     // row tile: BN columns x C chunks; transposed tile: D dims x 4 chunks
     __shared__ __bf16 yr[2][NPART][BN * D];
-    __shared__ __bf16 ytr[2][2][D * BN];
+    __shared__ __bf16 ytr[2][NYT][D * BN];
     __shared__ float bt[2][BN];
 
     const int tid = threadIdx.x;
@@ -316,9 +352,13 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 
     // A operand of the normaliser: a row of ones (output row 0)
     bf8 ones = bf8_zero();
+    h8 ones16 = as_h8(bf8_zero());
     if (li == 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
+        for (int e = 0; e < 8; ++e) {
+            ones[e] = (__bf16)1.f;
+            ones16[e] = (_Float16)1.f;
+        }
     }
 
     float m_used[QB];
@@ -333,7 +373,7 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 
     const int ntiles = (int)((m + BN - 1) / BN);
     u4 pre[NPART][PER_T];
-    u4 pret[2][PER_T];
+    u4 pret[NYT][PER_T];
     float bpre = 0.f;
     auto fetch = [&](int t) {
         const int64_t j0 = (int64_t)t * BN;
@@ -345,7 +385,7 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
                 for (int p = 0; p < NPART; ++p)
                     pre[p][r] = *reinterpret_cast<const u4 *>(Ylp + (p * mp + j0) * D + c * 8);
 #pragma unroll
-                for (int p = 0; p < 2; ++p)
+                for (int p = 0; p < NYT; ++p)
                     pret[p][r] = *reinterpret_cast<const u4 *>(YTlp + (p * mp + j0) * D + c * 8);
             }
         }
@@ -362,7 +402,7 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 #pragma unroll
                 for (int p = 0; p < NPART; ++p) *reinterpret_cast<u4 *>(&yr[buf][p][c * 8]) = pre[p][r];
 #pragma unroll
-                for (int p = 0; p < 2; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
+                for (int p = 0; p < NYT; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
             }
         }
         if (tid < BN) bt[buf][tid] = bpre;
@@ -420,6 +460,7 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
             }
         }
         bf8 pb[QB], pl[NPART == 2 ? QB : 1];
+        h8 p16[QB];
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
             float mx = kNegBig;
@@ -438,35 +479,51 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 #pragma unroll
                 for (int db = 0; db < NDB; ++db) o[qb][db] *= cs;
             }
+            if constexpr (NPART == 1) {
+                p16[qb] = weights_f16(acc[qb], m_used[qb] - kF16Shift);
+            } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float v = ex2(acc[qb][e >> 2][e & 3] - m_used[qb]);
-                const __bf16 h = (__bf16)v;
-                pb[qb][e] = h;
-                if constexpr (NPART == 2) pl[qb][e] = (__bf16)(v - (float)h);
+                for (int e = 0; e < 8; ++e) {
+                    const float v = ex2(acc[qb][e >> 2][e & 3] - m_used[qb]);
+                    const __bf16 h = (__bf16)v;
+                    pb[qb][e] = h;
+                    pl[qb][e] = (__bf16)(v - (float)h);
+                }
             }
         }
         // O^T += Y^T P^T: each Y^T fragment (16 dims x 32 columns) is read
         // once and feeds the QB row blocks; the hi part of every dimension
         // block is applied before the lo part, so an accumulator is not
         // touched by consecutive MFMAs
-#pragma unroll
-        for (int p2 = 0; p2 < 2; ++p2)
+        if constexpr (NPART == 1) {
+            // one FP16 product against the scaled FP16 copy
 #pragma unroll
             for (int db = 0; db < NDB; ++db) {
-                const bf8 av =
-                    *reinterpret_cast<const bf8 *>(&ytr[buf][p2][tile_chunk(db, 4, lq, li) * 8]);
+                const h8 av =
+                    as_h8(*reinterpret_cast<const bf8 *>(&ytr[buf][0][tile_chunk(db, 4, lq, li) * 8]));
 #pragma unroll
-                for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pb[qb], o[qb][db]);
-                if constexpr (NPART == 2)
+                for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_h(av, p16[qb], o[qb][db]);
+            }
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) on[qb] = mfma_h(ones16, p16[qb], on[qb]);
+        } else {
+#pragma unroll
+            for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+                for (int db = 0; db < NDB; ++db) {
+                    const bf8 av =
+                        *reinterpret_cast<const bf8 *>(&ytr[buf][p2][tile_chunk(db, 4, lq, li) * 8]);
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pb[qb], o[qb][db]);
                     if (p2 == 0)
 #pragma unroll
                         for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pl[qb], o[qb][db]);
-            }
+                }
 #pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-            on[qb] = mfma_bf(ones, pb[qb], on[qb]);
-            if constexpr (NPART == 2) on[qb] = mfma_bf(ones, pl[qb], on[qb]);
+            for (int qb = 0; qb < QB; ++qb) {
+                on[qb] = mfma_bf(ones, pb[qb], on[qb]);
+                on[qb] = mfma_bf(ones, pl[qb], on[qb]);
+            }
         }
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -476,7 +533,8 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     for (int qb = 0; qb < QB; ++qb) {
         // the normaliser of row li sits in output row 0: lane li, register 0
         const float l = __shfl(on[qb][0], li);
-        const float inv = 1.f / l;
+        // the FP16 copy holds Y scaled by a power of two: undo it exactly
+        const float inv = (NPART == 1 ? *yt_unscale : 1.f) / l;
         const int64_t row = row0 + qb * 16 + li;
         double sq = 0.0;
         if (row < nq) {
@@ -518,7 +576,8 @@ template <int D, int NPART>
 __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
     const float *Xq, int64_t nq, int d, const __bf16 *__restrict__ Ylp,
     const __bf16 *__restrict__ YTlp, int64_t m, int64_t mp, const float *__restrict__ ysq,
-    const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout) {
+    const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout,
+    const float *__restrict__ yt_unscale) {
     constexpr int BN = kMapBN;
     constexpr int KS = D / 32, C = D / 8;
     constexpr int NW = 8;                  // waves = query blocks of 16
@@ -526,9 +585,10 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
     constexpr int NDBW = D / NW / 16;      // output dimension blocks per wave
     constexpr int NCH = BN * C;            // 16-byte chunks per part of a tile
     constexpr int PER_T = NCH / 512;
+    constexpr int NYT = NPART == 2 ? 2 : 1;  // parts of the transposed copy (FP16: one)
     static_assert(NDBW >= 1 && NCH % 512 == 0, "wide map needs D >= 128");
     __shared__ __bf16 yr[2][NPART][BN * D];
-    __shared__ __bf16 ytr[2][2][D * BN];
+    __shared__ __bf16 ytr[2][NYT][D * BN];
     __shared__ float bt[2][BN];
     __shared__ bf8 pw[NPART][NW][64];      // B operands (weights) of the 8 blocks
     __shared__ float csw[NW][16];          // rescale factor of each query this tile
@@ -544,9 +604,13 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
     bf8 ub[NPART][KS];
     scaled_row_operand<D, NPART>(Xq, nq, d, row, lq, scale2, ub);
     bf8 ones = bf8_zero();
+    h8 ones16 = as_h8(bf8_zero());
     if (li == 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
+        for (int e = 0; e < 8; ++e) {
+            ones[e] = (__bf16)1.f;
+            ones16[e] = (_Float16)1.f;
+        }
     }
 
     float m_used = kNegBig;
@@ -558,7 +622,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
         for (int db = 0; db < NDBW; ++db) o[qb][db] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int ntiles = (int)((m + BN - 1) / BN);
-    u4 pre[NPART][PER_T], pret[2][PER_T];
+    u4 pre[NPART][PER_T], pret[NYT][PER_T];
     float bpre = 0.f;
     auto fetch = [&](int t) {
         const int64_t j0 = (int64_t)t * BN;
@@ -569,7 +633,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
             for (int p = 0; p < NPART; ++p)
                 pre[p][r] = *reinterpret_cast<const u4 *>(Ylp + (p * mp + j0) * D + c * 8);
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < NYT; ++p)
                 pret[p][r] = *reinterpret_cast<const u4 *>(YTlp + (p * mp + j0) * D + c * 8);
         }
         if (tid < BN) {
@@ -584,7 +648,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
 #pragma unroll
             for (int p = 0; p < NPART; ++p) *reinterpret_cast<u4 *>(&yr[buf][p][c * 8]) = pre[p][r];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
+            for (int p = 0; p < NYT; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
         }
         if (tid < BN) bt[buf][tid] = bpre;
     };
@@ -643,18 +707,24 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
             m_used = mn;
             on *= csf;
         }
-        bf8 pb, pl;
+        if constexpr (NPART == 1) {
+            const h8 w = weights_f16(acc, m_used - kF16Shift);
+            on = mfma_h(ones16, w, on);
+            pw[0][wave][lane] = as_bf8(w);
+        } else {
+            bf8 pb, pl;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float v = ex2(acc[e >> 2][e & 3] - m_used);
-            const __bf16 h = (__bf16)v;
-            pb[e] = h;
-            if constexpr (NPART == 2) pl[e] = (__bf16)(v - (float)h);
+            for (int e = 0; e < 8; ++e) {
+                const float v = ex2(acc[e >> 2][e & 3] - m_used);
+                const __bf16 h = (__bf16)v;
+                pb[e] = h;
+                pl[e] = (__bf16)(v - (float)h);
+            }
+            on = mfma_bf(ones, pb, on);
+            on = mfma_bf(ones, pl, on);
+            pw[0][wave][lane] = pb;
+            pw[1][wave][lane] = pl;
         }
-        on = mfma_bf(ones, pb, on);
-        if constexpr (NPART == 2) on = mfma_bf(ones, pl, on);
-        pw[0][wave][lane] = pb;
-        if constexpr (NPART == 2) pw[1][wave][lane] = pl;
         if (lq == 0) csw[wave][li] = csf;
         if (lane == 0) upw[wave] = any;
         __syncthreads();
@@ -670,15 +740,26 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
         bf8 pq[NW];
 #pragma unroll
         for (int qb = 0; qb < NW; ++qb) pq[qb] = pw[0][qb][lane];
-#pragma unroll
-        for (int p2 = 0; p2 < 2; ++p2)
+        if constexpr (NPART == 1) {
+            // one FP16 product against the scaled FP16 copy
 #pragma unroll
             for (int db = 0; db < NDBW; ++db) {
-                const bf8 av = *reinterpret_cast<const bf8 *>(
-                    &ytr[buf][p2][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]);
+                const h8 av = as_h8(*reinterpret_cast<const bf8 *>(
+                    &ytr[buf][0][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]));
 #pragma unroll
-                for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_bf(av, pq[qb], o[qb][db]);
+                for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_h(av, as_h8(pq[qb]), o[qb][db]);
             }
+        } else {
+#pragma unroll
+            for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+                for (int db = 0; db < NDBW; ++db) {
+                    const bf8 av = *reinterpret_cast<const bf8 *>(
+                        &ytr[buf][p2][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]);
+#pragma unroll
+                    for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_bf(av, pq[qb], o[qb][db]);
+                }
+        }
         if constexpr (NPART == 2) {
 #pragma unroll
             for (int qb = 0; qb < NW; ++qb) pq[qb] = pw[1][qb][lane];
@@ -701,7 +782,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
     for (int qb = 0; qb < NW; ++qb) {
         const int64_t r = blk0 + qb * 16 + li;
         if (r >= nq) continue;
-        const float inv = 1.f / lw[qb * 16 + li];
+        const float inv = (NPART == 1 ? *yt_unscale : 1.f) / lw[qb * 16 + li];
 #pragma unroll
         for (int db = 0; db < NDBW; ++db) {
             const int f0 = (wave * NDBW + db) * 16 + 4 * lq;
@@ -756,6 +837,46 @@ __global__ __launch_bounds__(256) void bf16_transpose(const float *__restrict__ 
     yt[mp * D + e] = (__bf16)(y - (float)h);
 }
 
+// max |y| over a cloud, as the bits of a non-negative float (which order like
+// the floats), combined with atomicMax into *out (zeroed beforehand).
+__global__ __launch_bounds__(256) void absmax_f32(const float *__restrict__ Y, int64_t count,
+                                                  unsigned *__restrict__ out) {
+    float v = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
+        v = fmaxf(v, fabsf(Y[i]));
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(v));
+}
+
+// The transposed copy of the plain BF16 form's projection: one FP16 part,
+// Y scaled by 2^k with k the largest integer such that max |y| 2^k <= 2^14
+// (exact scaling; far from FP16's overflow and subnormal ranges), in the
+// layout of bf16_transpose.  unscale = 2^-k undoes it after the product.
+__global__ __launch_bounds__(256) void f16_transpose(const float *__restrict__ Y, int64_t m, int d,
+                                                     int D, int64_t mp, const unsigned *__restrict__ amax,
+                                                     _Float16 *__restrict__ yt, float *__restrict__ unscale) {
+    const float mx = __uint_as_float(*amax);
+    int k = 0;
+    if (mx > 0.f && mx < INFINITY) {
+        int e;
+        (void)frexpf(16384.f / mx, &e);   // 16384 / mx = f 2^e, f in [0.5, 1)
+        k = min(e - 1, 126);
+    }
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e == 0) *unscale = ldexpf(1.f, -k);
+    if (e >= mp * D) return;
+    const int nblk = D / 4;
+    const int64_t rest = e >> 7;
+    const int blk = (int)(rest % nblk);
+    const int64_t t = rest / nblk;
+    const int dim = (blk >> 2) * 16 + (int)((e >> 3) & 15);
+    const int q = (blk & 3) * 8 + (int)(e & 7);
+    const int64_t j = 32 * t + perm32(q);
+    const float y = (j < m && dim < d) ? Y[j * d + dim] : 0.f;
+    yt[e] = (_Float16)ldexpf(y, k);
+}
+
 template <int D, int QB, int NPART>
 hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     // the plan must cover every row tile of this kernel variant, and splits
@@ -773,9 +894,10 @@ template <int D, int NPART>
 hipError_t map_bf16_wide_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     if (a.mp != bf16_mpad(a.m) || a.out_sqn) return hipErrorInvalidValue;
     const int64_t tiles = (a.nq + 127) / 128;
+    if (NPART == 1 && !a.yt_unscale) return hipErrorInvalidValue;
     timed_launch(1, entropic_map_bf16_wide<D, NPART>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
                  a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
-                 scale2, bscale, a.alpha, a.Xout);
+                 scale2, bscale, a.alpha, a.Xout, a.yt_unscale);
     return hipGetLastError();
 }
 
@@ -783,9 +905,10 @@ template <int D, int QB, int NPART>
 hipError_t map_bf16_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     if (a.mp != bf16_mpad(a.m)) return hipErrorInvalidValue;
     const int64_t tiles = (a.nq + 64 * QB - 1) / (64 * QB);
+    if (NPART == 1 && !a.yt_unscale) return hipErrorInvalidValue;
     timed_launch(1, entropic_map_bf16<D, QB, NPART>, dim3((unsigned)tiles), dim3(256), 0, s, a.Xq,
                  a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
-                 scale2, bscale, a.alpha, a.Xout, a.out_sqn);
+                 scale2, bscale, a.alpha, a.Xout, a.out_sqn, a.yt_unscale);
     return hipGetLastError();
 }
 
@@ -846,6 +969,21 @@ hipError_t launch_bf16_rows(const float *X, int64_t n, int d, void *lp, hipStrea
     const int64_t tot = np * D;
     hipLaunchKernelGGL(bf16_split_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, n, d, D,
                        np, (__bf16 *)lp);
+    return hipGetLastError();
+}
+
+hipError_t launch_f16_transpose(const float *Y, int64_t m, int d, void *yt, float *scale2, hipStream_t s) {
+    const int D = bf16_dim(d);
+    const int64_t mp = bf16_mpad(m);
+    const int64_t tot = mp * D;
+    unsigned *amax = reinterpret_cast<unsigned *>(scale2);
+    hipError_t e = hipMemsetAsync(amax, 0, sizeof(unsigned), s);
+    if (e != hipSuccess) return e;
+    const int64_t cnt = m * (int64_t)d;
+    const int64_t blocks = std::min<int64_t>((cnt + 255) / 256, 4096);
+    hipLaunchKernelGGL(absmax_f32, dim3((unsigned)blocks), dim3(256), 0, s, Y, cnt, amax);
+    hipLaunchKernelGGL(f16_transpose, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Y, m, d, D, mp,
+                       amax, (_Float16 *)yt, scale2 + 1);
     return hipGetLastError();
 }
 

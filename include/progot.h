@@ -37,6 +37,22 @@
  * Errors.  Arguments are validated on the host before any launch; invalid
  * arguments return POT_ERR_INVALID and enqueue nothing.  A positive status is
  * a warning with valid outputs.  No C++ exception crosses the ABI.
+ *
+ * Host-side state.  The library keeps three pieces of process state, none of
+ * it device memory a caller must manage: a small pinned, device-mapped host
+ * buffer per host thread into which the Sinkhorn loop's kernels store their
+ * error sums (with the event marking the end of that thread's last solve);
+ * the process-wide switch and event lists of pot_timing_*; and the per-device
+ * address of pot_sinkhorn_divergence_noalloc's static scratch array.
+ *
+ * Shape of the interface.  The convergence read-back has no check_every
+ * argument: the loop reads the error back with a lag it picks from the cost
+ * of one iteration (a stream never waits on the host for cheap iterations,
+ * and no update past convergence runs for expensive ones), and returns the
+ * first iterate with err <= tau in every case.  Continuous batching is the
+ * pot_server_* family (admission, ticks, polling) rather than a single
+ * group-step call, because admission and the per-request ProgOT schedule need
+ * state between ticks.
  */
 #ifndef PROGOT_H
 #define PROGOT_H

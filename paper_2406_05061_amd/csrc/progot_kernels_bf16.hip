@@ -838,15 +838,20 @@ __global__ __launch_bounds__(256) void bf16_transpose(const float *__restrict__ 
 }
 
 // max |y| over a cloud, as the bits of a non-negative float (which order like
-// the floats), combined with atomicMax into *out (zeroed beforehand).
+// the floats): each workgroup reduces its grid-stride share and combines it
+// with one atomicMax into *out (zeroed beforehand).
 __global__ __launch_bounds__(256) void absmax_f32(const float *__restrict__ Y, int64_t count,
                                                   unsigned *__restrict__ out) {
+    __shared__ float wmax[4];
     float v = 0.f;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256)
         v = fmaxf(v, fabsf(Y[i]));
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(v));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(out, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
 }
 
 // The transposed copy of the plain BF16 form's projection: one FP16 part,
@@ -980,7 +985,7 @@ hipError_t launch_f16_transpose(const float *Y, int64_t m, int d, void *yt, floa
     hipError_t e = hipMemsetAsync(amax, 0, sizeof(unsigned), s);
     if (e != hipSuccess) return e;
     const int64_t cnt = m * (int64_t)d;
-    const int64_t blocks = std::min<int64_t>((cnt + 255) / 256, 4096);
+    const int64_t blocks = std::min<int64_t>((cnt + 255) / 256, 1024);
     hipLaunchKernelGGL(absmax_f32, dim3((unsigned)blocks), dim3(256), 0, s, Y, cnt, amax);
     hipLaunchKernelGGL(f16_transpose, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Y, m, d, D, mp,
                        amax, (_Float16 *)yt, scale2 + 1);

@@ -85,7 +85,6 @@ __device__ __forceinline__ h8 weights_f16(const f4 (&acc)[2], float shift) {
 }
 
 __device__ __forceinline__ h8 as_h8(bf8 x) { return __builtin_bit_cast(h8, x); }
-__device__ __forceinline__ bf8 as_bf8(h8 x) { return __builtin_bit_cast(bf8, x); }
 
 // Keeps an operand computed before the tile loop in its registers: without
 // this the compiler re-derives the BF16 row operands from the FP32 rows in
@@ -559,7 +558,7 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     }
 }
 
-// Wide form of the map kernel, used for D = 256: a workgroup of 8 waves maps
+// Wide form of the map kernel, used for D = 256 in the BF16X3 form: a workgroup of 8 waves maps
 // 128 queries.  Wave w computes the scores and the softmax of query block w
 // (16 queries) against each 32-column tile, publishes its BF16 weights (and
 // their per-query rescale factors) in LDS, and after a barrier applies the
@@ -567,17 +566,18 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 // output accumulators hold 8 blocks x D/8 dimensions (64 VGPRs at D = 256
 // instead of 16 x D/4 x 4 = 256 for four blocks over all D), and each
 // transposed fragment is read by one wave instead of all of them.  Measured
-// at n = m = 65536: 9.2 ms instead of 14.6 (BF16) and 12.6 instead of 21.5
-// (BF16X3) at D = 256; at D = 128 the two barriers per tile cost more than
-// they save (6.2 ms instead of 3.4), so D = 128 keeps the narrow kernel.
+// at n = m = 65536: 12.6 ms instead of 21.5 at D = 256 (plain BF16 had 9.2
+// instead of 14.6 with BF16 projection weights; with FP16 ones the narrow
+// kernel is faster there); at D = 128 the two barriers per tile cost more
+// than they save (6.2 ms instead of 3.4), so D = 128 keeps the narrow kernel.
 // Arithmetic per pair is the same as in entropic_map_bf16 (same products,
 // normaliser and rescale rule), so the two agree to rounding order.
-template <int D, int NPART>
+template <int D>
 __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
     const float *Xq, int64_t nq, int d, const __bf16 *__restrict__ Ylp,
     const __bf16 *__restrict__ YTlp, int64_t m, int64_t mp, const float *__restrict__ ysq,
-    const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout,
-    const float *__restrict__ yt_unscale) {
+    const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout) {
+    constexpr int NPART = 2;               // hi/lo split of rows and weights
     constexpr int BN = kMapBN;
     constexpr int KS = D / 32, C = D / 8;
     constexpr int NW = 8;                  // waves = query blocks of 16
@@ -585,10 +585,9 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
     constexpr int NDBW = D / NW / 16;      // output dimension blocks per wave
     constexpr int NCH = BN * C;            // 16-byte chunks per part of a tile
     constexpr int PER_T = NCH / 512;
-    constexpr int NYT = NPART == 2 ? 2 : 1;  // parts of the transposed copy (FP16: one)
     static_assert(NDBW >= 1 && NCH % 512 == 0, "wide map needs D >= 128");
     __shared__ __bf16 yr[2][NPART][BN * D];
-    __shared__ __bf16 ytr[2][NYT][D * BN];
+    __shared__ __bf16 ytr[2][2][D * BN];
     __shared__ float bt[2][BN];
     __shared__ bf8 pw[NPART][NW][64];      // B operands (weights) of the 8 blocks
     __shared__ float csw[NW][16];          // rescale factor of each query this tile
@@ -604,13 +603,9 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
     bf8 ub[NPART][KS];
     scaled_row_operand<D, NPART>(Xq, nq, d, row, lq, scale2, ub);
     bf8 ones = bf8_zero();
-    h8 ones16 = as_h8(bf8_zero());
     if (li == 0) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            ones[e] = (__bf16)1.f;
-            ones16[e] = (_Float16)1.f;
-        }
+        for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
     }
 
     float m_used = kNegBig;
@@ -622,7 +617,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
         for (int db = 0; db < NDBW; ++db) o[qb][db] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int ntiles = (int)((m + BN - 1) / BN);
-    u4 pre[NPART][PER_T], pret[NYT][PER_T];
+    u4 pre[NPART][PER_T], pret[2][PER_T];
     float bpre = 0.f;
     auto fetch = [&](int t) {
         const int64_t j0 = (int64_t)t * BN;
@@ -633,7 +628,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
             for (int p = 0; p < NPART; ++p)
                 pre[p][r] = *reinterpret_cast<const u4 *>(Ylp + (p * mp + j0) * D + c * 8);
 #pragma unroll
-            for (int p = 0; p < NYT; ++p)
+            for (int p = 0; p < 2; ++p)
                 pret[p][r] = *reinterpret_cast<const u4 *>(YTlp + (p * mp + j0) * D + c * 8);
         }
         if (tid < BN) {
@@ -648,7 +643,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
 #pragma unroll
             for (int p = 0; p < NPART; ++p) *reinterpret_cast<u4 *>(&yr[buf][p][c * 8]) = pre[p][r];
 #pragma unroll
-            for (int p = 0; p < NYT; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
+            for (int p = 0; p < 2; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
         }
         if (tid < BN) bt[buf][tid] = bpre;
     };
@@ -707,24 +702,18 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
             m_used = mn;
             on *= csf;
         }
-        if constexpr (NPART == 1) {
-            const h8 w = weights_f16(acc, m_used - kF16Shift);
-            on = mfma_h(ones16, w, on);
-            pw[0][wave][lane] = as_bf8(w);
-        } else {
-            bf8 pb, pl;
+        bf8 pb, pl;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float v = ex2(acc[e >> 2][e & 3] - m_used);
-                const __bf16 h = (__bf16)v;
-                pb[e] = h;
-                pl[e] = (__bf16)(v - (float)h);
-            }
-            on = mfma_bf(ones, pb, on);
-            on = mfma_bf(ones, pl, on);
-            pw[0][wave][lane] = pb;
-            pw[1][wave][lane] = pl;
+        for (int e = 0; e < 8; ++e) {
+            const float v = ex2(acc[e >> 2][e & 3] - m_used);
+            const __bf16 h = (__bf16)v;
+            pb[e] = h;
+            pl[e] = (__bf16)(v - (float)h);
         }
+        on = mfma_bf(ones, pb, on);
+        on = mfma_bf(ones, pl, on);
+        pw[0][wave][lane] = pb;
+        pw[1][wave][lane] = pl;
         if (lq == 0) csw[wave][li] = csf;
         if (lane == 0) upw[wave] = any;
         __syncthreads();
@@ -740,36 +729,24 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
         bf8 pq[NW];
 #pragma unroll
         for (int qb = 0; qb < NW; ++qb) pq[qb] = pw[0][qb][lane];
-        if constexpr (NPART == 1) {
-            // one FP16 product against the scaled FP16 copy
 #pragma unroll
-            for (int db = 0; db < NDBW; ++db) {
-                const h8 av = as_h8(*reinterpret_cast<const bf8 *>(
-                    &ytr[buf][0][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]));
-#pragma unroll
-                for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_h(av, as_h8(pq[qb]), o[qb][db]);
-            }
-        } else {
-#pragma unroll
-            for (int p2 = 0; p2 < 2; ++p2)
-#pragma unroll
-                for (int db = 0; db < NDBW; ++db) {
-                    const bf8 av = *reinterpret_cast<const bf8 *>(
-                        &ytr[buf][p2][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]);
-#pragma unroll
-                    for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_bf(av, pq[qb], o[qb][db]);
-                }
-        }
-        if constexpr (NPART == 2) {
-#pragma unroll
-            for (int qb = 0; qb < NW; ++qb) pq[qb] = pw[1][qb][lane];
+        for (int p2 = 0; p2 < 2; ++p2)
 #pragma unroll
             for (int db = 0; db < NDBW; ++db) {
                 const bf8 av = *reinterpret_cast<const bf8 *>(
-                    &ytr[buf][0][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]);
+                    &ytr[buf][p2][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]);
 #pragma unroll
                 for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_bf(av, pq[qb], o[qb][db]);
             }
+        // the lo weights against the hi copy: the third product of the split
+#pragma unroll
+        for (int qb = 0; qb < NW; ++qb) pq[qb] = pw[1][qb][lane];
+#pragma unroll
+        for (int db = 0; db < NDBW; ++db) {
+            const bf8 av = *reinterpret_cast<const bf8 *>(
+                &ytr[buf][0][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]);
+#pragma unroll
+            for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_bf(av, pq[qb], o[qb][db]);
         }
         if (more) store(buf ^ 1);
         __syncthreads();
@@ -782,7 +759,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
     for (int qb = 0; qb < NW; ++qb) {
         const int64_t r = blk0 + qb * 16 + li;
         if (r >= nq) continue;
-        const float inv = (NPART == 1 ? *yt_unscale : 1.f) / lw[qb * 16 + li];
+        const float inv = 1.f / lw[qb * 16 + li];
 #pragma unroll
         for (int db = 0; db < NDBW; ++db) {
             const int f0 = (wave * NDBW + db) * 16 + 4 * lq;
@@ -895,14 +872,13 @@ hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int D, int NPART>
+template <int D>
 hipError_t map_bf16_wide_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     if (a.mp != bf16_mpad(a.m) || a.out_sqn) return hipErrorInvalidValue;
     const int64_t tiles = (a.nq + 127) / 128;
-    if (NPART == 1 && !a.yt_unscale) return hipErrorInvalidValue;
-    timed_launch(1, entropic_map_bf16_wide<D, NPART>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
+    timed_launch(1, entropic_map_bf16_wide<D>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
                  a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
-                 scale2, bscale, a.alpha, a.Xout, a.yt_unscale);
+                 scale2, bscale, a.alpha, a.Xout);
     return hipGetLastError();
 }
 
@@ -961,9 +937,11 @@ hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStre
         case 32: return x3 ? map_bf16_t<32, 2, 2>(a, scale2, bscale, s) : map_bf16_t<32, 2, 1>(a, scale2, bscale, s);
         case 64: return x3 ? map_bf16_t<64, 2, 2>(a, scale2, bscale, s) : map_bf16_t<64, 2, 1>(a, scale2, bscale, s);
         case 128: return x3 ? map_bf16_t<128, 2, 2>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1>(a, scale2, bscale, s);
+        // D = 256: BF16X3 takes the wide kernel (12.6 ms instead of 21.5 at
+        // 65536^2); plain BF16, whose projection is one FP16 product, the
+        // narrow one (6.2 ms against 7.5 for the wide kernel)
         default:
-            if (!a.out_sqn)
-                return x3 ? map_bf16_wide_t<256, 2>(a, scale2, bscale, s) : map_bf16_wide_t<256, 1>(a, scale2, bscale, s);
+            if (x3 && !a.out_sqn) return map_bf16_wide_t<256>(a, scale2, bscale, s);
             return x3 ? map_bf16_t<256, 1, 2>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1>(a, scale2, bscale, s);
     }
 }

@@ -40,8 +40,16 @@ namespace {
 // The XOR makes the map's projection read conflict-free as well: there lane
 // (li, lq) takes feature 16 db + li of row 16 s + 4 lq + r (a ds_read_b32),
 // and the permuted row 4 lq + (r ^ (li / 4)) puts the 64 lanes on 64
-// distinct banks.  Thread t fills LDS chunk t (+ 256 k), so the stores are
-// contiguous too; its global load is chunk c of one row of a 16-row block.
+// distinct banks.
+//
+// The loader (tile_coords) gives each wave whole row segments: a wave reads
+// 4 rows x 256 bytes (D >= 64), 8 rows x 128 or 16 rows x 64 bytes of
+// consecutive rows (D = 32, 16), and each group of 16 lanes stores 4 rows x 4
+// chunks, i.e. 4 blocks of LDS (4-way).  Reading 16 rows x 64 bytes per wave
+// instead, with conflict-free stores, measured 1 % slower for the potential
+// kernel and 7 % slower for the map at d = 64: the tiles stream from L2 on
+// every workgroup, and their cache-line efficiency counts for more than the
+// stores, which are a quarter of the LDS instructions.
 template <int D, int BN_ = (D >= 256 ? 32 : 64)> struct Tile {
     static constexpr int BN = BN_;                 // columns per LDS tile
     static constexpr int NSUB = BN / 16;           // 16-column subtiles
@@ -58,8 +66,31 @@ __device__ __forceinline__ int tchunk(int j, int c) {
     return (((j >> 4) * (D / 4) + c) * 16 + ((j & 15) ^ (c & 3))) * 4;
 }
 
+// Tile row and chunk loaded by the e-th chunk slot of the loader (e = thread
+// + 256 k): wave w covers whole row segments, quarter q of it 4 rows x 4
+// chunks (layout comment above).
+template <int D>
+__device__ __forceinline__ void tile_coords(int e, int &row, int &cc) {
+    constexpr int C = D / 4;
+    if constexpr (C >= 16) {           // 16-row blocks of 16 C chunks, 256 chunks per round
+        const int blk = e / (16 * C), off = e % (16 * C);
+        const int h = off >> 8, t = off & 255;
+        row = blk * 16 + 4 * (t >> 6) + ((t & 15) >> 2);
+        cc = 16 * h + 4 * ((t >> 4) & 3) + (t & 3);
+    } else if constexpr (C == 8) {     // a block is 128 chunks: two waves of 8 rows
+        const int blk = e >> 7, t = e & 127;
+        const int w = t >> 6, q = (t >> 4) & 3, u = t & 15;
+        row = blk * 16 + 8 * w + 4 * (q >> 1) + (u >> 2);
+        cc = 4 * (q & 1) + (u & 3);
+    } else {                           // C == 4: a block is one wave of 16 rows
+        const int blk = e >> 6, t = e & 63;
+        row = blk * 16 + 4 * (t >> 4) + ((t & 15) >> 2);
+        cc = t & 3;
+    }
+}
+
 // Load one BN x D column tile (rows j0.., zero-padded beyond nv and beyond
-// feature d) into registers: thread t takes LDS chunks t, t + 256, ...
+// feature d) into registers: thread t takes loader slots t, t + 256, ...
 template <int D, int BN>
 __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t nv, int d,
                                            int64_t j0, int tid, f4 (&pre)[Tile<D, BN>::PER_T]) {
@@ -69,8 +100,8 @@ __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t 
         const int e = tid + 256 * r;
         f4 v = {0.f, 0.f, 0.f, 0.f};
         if (T::NCH % 256 == 0 || e < T::NCH) {
-            const int cc = (e >> 4) % T::C;
-            const int row = (e / (16 * T::C)) * 16 + ((e & 15) ^ (cc & 3));
+            int row, cc;
+            tile_coords<D>(e, row, cc);
             const int c = cc * 4;
             const int64_t j = j0 + row;
             if (j < nv) {
@@ -96,7 +127,11 @@ __device__ __forceinline__ void tile_store(float *__restrict__ lds, int tid,
 #pragma unroll
     for (int r = 0; r < T::PER_T; ++r) {
         const int e = tid + 256 * r;
-        if (T::NCH % 256 == 0 || e < T::NCH) *reinterpret_cast<f4 *>(lds + 4 * e) = pre[r];
+        if (T::NCH % 256 == 0 || e < T::NCH) {
+            int row, cc;
+            tile_coords<D>(e, row, cc);
+            *reinterpret_cast<f4 *>(lds + tchunk<D>(row, cc)) = pre[r];
+        }
     }
 }
 

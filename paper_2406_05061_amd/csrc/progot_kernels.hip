@@ -42,14 +42,15 @@ namespace {
 // and the permuted row 4 lq + (r ^ (li / 4)) puts the 64 lanes on 64
 // distinct banks.
 //
-// The loader (tile_coords) gives each wave whole row segments: a wave reads
+// The loader (TileSlot) gives each wave whole row segments: a wave reads
 // 4 rows x 256 bytes (D >= 64), 8 rows x 128 or 16 rows x 64 bytes of
 // consecutive rows (D = 32, 16), and each group of 16 lanes stores 4 rows x 4
 // chunks, i.e. 4 blocks of LDS (4-way).  Reading 16 rows x 64 bytes per wave
 // instead, with conflict-free stores, measured 1 % slower for the potential
-// kernel and 7 % slower for the map at d = 64: the tiles stream from L2 on
-// every workgroup, and their cache-line efficiency counts for more than the
-// stores, which are a quarter of the LDS instructions.
+// kernel and 6 % slower for the map at d = 64, 7-8 % slower for the potential
+// kernel at d = 128 and 256: the tiles stream from L2 on every workgroup, and
+// their cache-line efficiency counts for more than the stores, which are a
+// quarter of the LDS instructions.
 template <int D, int BN_ = (D >= 256 ? 32 : 64)> struct Tile {
     static constexpr int BN = BN_;                 // columns per LDS tile
     static constexpr int NSUB = BN / 16;           // 16-column subtiles
@@ -66,28 +67,33 @@ __device__ __forceinline__ int tchunk(int j, int c) {
     return (((j >> 4) * (D / 4) + c) * 16 + ((j & 15) ^ (c & 3))) * 4;
 }
 
-// Tile row and chunk loaded by the e-th chunk slot of the loader (e = thread
-// + 256 k): wave w covers whole row segments, quarter q of it 4 rows x 4
-// chunks (layout comment above).
-template <int D>
-__device__ __forceinline__ void tile_coords(int e, int &row, int &cc) {
-    constexpr int C = D / 4;
-    if constexpr (C >= 16) {           // 16-row blocks of 16 C chunks, 256 chunks per round
-        const int blk = e / (16 * C), off = e % (16 * C);
-        const int h = off >> 8, t = off & 255;
-        row = blk * 16 + 4 * (t >> 6) + ((t & 15) >> 2);
-        cc = 16 * h + 4 * ((t >> 4) & 3) + (t & 3);
-    } else if constexpr (C == 8) {     // a block is 128 chunks: two waves of 8 rows
-        const int blk = e >> 7, t = e & 127;
-        const int w = t >> 6, q = (t >> 4) & 3, u = t & 15;
-        row = blk * 16 + 8 * w + 4 * (q >> 1) + (u >> 2);
-        cc = 4 * (q & 1) + (u & 3);
-    } else {                           // C == 4: a block is one wave of 16 rows
-        const int blk = e >> 6, t = e & 63;
-        row = blk * 16 + 4 * (t >> 4) + ((t & 15) >> 2);
-        cc = t & 3;
+// Loader slot (thread tid, round r): tile row row0 + row_step(r), chunk
+// cc0 + chunk_step(r).  Wave w covers whole row segments, each quarter of it
+// 4 rows x 4 chunks (layout comment above); the round only adds compile-time
+// offsets, so one base address per thread serves every round.
+template <int D> struct TileSlot {
+    static constexpr int C = D / 4;
+    int row0, cc0;
+    __device__ __forceinline__ explicit TileSlot(int tid) {
+        if constexpr (C >= 16) {       // 16-row blocks of 16 C chunks, 256 chunks per round
+            row0 = 4 * (tid >> 6) + ((tid & 15) >> 2);
+            cc0 = 4 * ((tid >> 4) & 3) + (tid & 3);
+        } else if constexpr (C == 8) { // waves of 8 rows x 8 chunks
+            row0 = 16 * (tid >> 7) + 8 * ((tid >> 6) & 1) + 4 * ((tid >> 5) & 1) + ((tid & 15) >> 2);
+            cc0 = 4 * ((tid >> 4) & 1) + (tid & 3);
+        } else {                       // C == 4: waves of 16 rows x 4 chunks
+            row0 = 16 * (tid >> 6) + 4 * ((tid >> 4) & 3) + ((tid & 15) >> 2);
+            cc0 = tid & 3;
+        }
     }
-}
+    static constexpr int row_step(int r) {
+        return C >= 16 ? 16 * (r / (C / 16)) : C == 8 ? 32 * r : 64 * r;
+    }
+    static constexpr int chunk_step(int r) { return C >= 16 ? 16 * (r % (C / 16)) : 0; }
+    // LDS float offset of round r relative to round 0 (row steps are whole
+    // 16-row blocks and chunk steps multiples of 4, so the XOR term is fixed)
+    static constexpr int lds_step(int r) { return ((row_step(r) >> 4) * C + chunk_step(r)) * 64; }
+};
 
 // Load one BN x D column tile (rows j0.., zero-padded beyond nv and beyond
 // feature d) into registers: thread t takes loader slots t, t + 256, ...
@@ -95,25 +101,26 @@ template <int D, int BN>
 __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t nv, int d,
                                            int64_t j0, int tid, f4 (&pre)[Tile<D, BN>::PER_T]) {
     using T = Tile<D, BN>;
+    using S = TileSlot<D>;
+    static_assert(T::NCH % 256 == 0, "a tile is whole loader rounds");
+    const S slot(tid);
+    const int64_t jb = j0 + slot.row0;
+    const int cb = 4 * slot.cc0;
 #pragma unroll
     for (int r = 0; r < T::PER_T; ++r) {
-        const int e = tid + 256 * r;
         f4 v = {0.f, 0.f, 0.f, 0.f};
-        if (T::NCH % 256 == 0 || e < T::NCH) {
-            int row, cc;
-            tile_coords<D>(e, row, cc);
-            const int c = cc * 4;
-            const int64_t j = j0 + row;
-            if (j < nv) {
-                if (d == D) {
-                    v = ldg(reinterpret_cast<const f4 *>(V + j * D + c));
-                } else {
-                    const float *p = V + j * d;
-                    v.x = c + 0 < d ? ldg(p + c + 0) : 0.f;
-                    v.y = c + 1 < d ? ldg(p + c + 1) : 0.f;
-                    v.z = c + 2 < d ? ldg(p + c + 2) : 0.f;
-                    v.w = c + 3 < d ? ldg(p + c + 3) : 0.f;
-                }
+        const int64_t j = jb + S::row_step(r);
+        const int c = cb + 4 * S::chunk_step(r);
+        if (j < nv) {
+            if (d == D) {
+                v = ldg(reinterpret_cast<const f4 *>(V + jb * D + cb) +
+                        (S::row_step(r) * D + 4 * S::chunk_step(r)) / 4);
+            } else {
+                const float *p = V + j * d;
+                v.x = c + 0 < d ? ldg(p + c + 0) : 0.f;
+                v.y = c + 1 < d ? ldg(p + c + 1) : 0.f;
+                v.z = c + 2 < d ? ldg(p + c + 2) : 0.f;
+                v.w = c + 3 < d ? ldg(p + c + 3) : 0.f;
             }
         }
         pre[r] = v;
@@ -124,15 +131,11 @@ template <int D, int BN>
 __device__ __forceinline__ void tile_store(float *__restrict__ lds, int tid,
                                            const f4 (&pre)[Tile<D, BN>::PER_T]) {
     using T = Tile<D, BN>;
+    using S = TileSlot<D>;
+    const S slot(tid);
+    float *base = lds + tchunk<D>(slot.row0, slot.cc0);
 #pragma unroll
-    for (int r = 0; r < T::PER_T; ++r) {
-        const int e = tid + 256 * r;
-        if (T::NCH % 256 == 0 || e < T::NCH) {
-            int row, cc;
-            tile_coords<D>(e, row, cc);
-            *reinterpret_cast<f4 *>(lds + tchunk<D>(row, cc)) = pre[r];
-        }
-    }
+    for (int r = 0; r < T::PER_T; ++r) *reinterpret_cast<f4 *>(base + S::lds_step(r)) = pre[r];
 }
 
 // The thread id, hidden from loop-invariant code motion: in the persistent

@@ -84,9 +84,16 @@ typedef enum {
  * FP32 accumulation.  BF16: BF16 MFMA on copies rounded to nearest even,
  * FP32 accumulation.  BF16X3: each value split as hi + lo (hi = bf16(x),
  * lo = bf16(x - hi)) and the cross term formed as hi*hi + hi*lo + lo*hi on
- * BF16 MFMA (~2^-16 relative).  In the BF16 forms the projection product of
- * the entropic map uses BF16 weights times (Y_hi + Y_lo).  Norms, the
- * log-sum-exp, potentials and marginal errors stay FP32 in every form. */
+ * BF16 MFMA (~2^-16 relative).  The projection product of the entropic map
+ * is FP16 weights times a scaled FP16 copy of Y in the BF16 form, and split
+ * weights times split targets (three products) in BF16X3.  Norms, the
+ * log-sum-exp, potentials and marginal errors stay FP32 in every form.
+ * In the BF16 forms the potential kernels shift each row's exponents by the
+ * log-sum-exp of its previous potential (from the second Sinkhorn iteration
+ * on) and fall back to a running maximum where a sum leaves [2^-64, 2^64];
+ * the environment variable PROGOT_BF16_SHIFT, read at every launch, selects
+ * the running maximum only ("off") or makes every fallback run ("recheck",
+ * the same bits as "off"). */
 typedef enum { POT_PREC_FP32 = 0, POT_PREC_BF16 = 1, POT_PREC_BF16X3 = 2 } pot_precision;
 
 #define POT_MAX_D 256      /* largest supported dimension d                    */

@@ -455,6 +455,7 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
         fa.vpot = t == 1 ? g_init : gb[(t - 1) % kRing];
         fa.gamma = t == 1 ? gamma : 1.f;
         fa.pot_old = t == 1 ? nullptr : fb[(t - 1) % kRing];
+        fa.shift_pot = fa.pot_old;
         fa.pot_out = fb[t % kRing];
         int nparts = 0;
         if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) return POT_ERR_DEVICE;
@@ -464,6 +465,7 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
             return status;
         if (lag == 0 && t > 1 && check(t - 1, &status)) return status;
         ga.vpot = fb[t % kRing];
+        ga.shift_pot = t == 1 ? nullptr : gb[(t - 1) % kRing];
         ga.pot_out = gb[t % kRing];
         const bool carry = fold && t > 1;
         ga.esum_in = carry ? at<float>(c, L.errp) : nullptr;
@@ -480,7 +482,7 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
                 if (check(k, &status)) return status;
             // err of the last iterate: one more f-update into the free slot
             fa.vpot = gb[t % kRing]; fa.gamma = 1.f;
-            fa.pot_old = fb[t % kRing]; fa.pot_out = fb[(t + 1) % kRing];
+            fa.pot_old = fb[t % kRing]; fa.shift_pot = fa.pot_old; fa.pot_out = fb[(t + 1) % kRing];
             if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) return POT_ERR_DEVICE;
             if ((status = enqueue_err_readback(c, L, nparts, hdev + t % kRing, E.ev[t % kRing], s)) !=
                 POT_OK)

@@ -74,6 +74,11 @@ struct LseJob {
     const float *esum_in;
     int esum_n;
     float *esum_out;
+    // Previous potential of the rows at the same eps and clouds (NULL: none).
+    // The BF16 partial kernels take the log-sum-exp it implies as a fixed
+    // exponent shift instead of a running maximum; a workgroup whose sums
+    // leave the safe range redoes its split with the running maximum.
+    const float *shift_pot;
 };
 
 typedef LseJob LseArgs;

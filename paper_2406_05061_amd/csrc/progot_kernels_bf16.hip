@@ -40,6 +40,9 @@
 #include "progot_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
 #include "progot_device.h"
 
 namespace pot {
@@ -147,15 +150,34 @@ template <int D, int NPART> struct TileH {
     static_assert(NCH % 256 == 0, "tile chunks must cover the workgroup");
 };
 
+// Sums of a fixed-shift sweep must land in [kSumLo, kSumHi]: then no term
+// that matters against the row's largest overflowed or fell below FP32's
+// normal range (every term is at most the sum, and terms under 2^-126 are
+// below 2^-62 of a sum of at least 2^-64).  The upper bound is a kernel
+// argument so that the host can fail every check (sum_hi < 0) and run the
+// fallback on purpose.
+constexpr float kSumLo = 0x1p-64f, kSumHi = 0x1p64f;
+
 // Partial log-sum-exp over one column split (BF16 cross term).  Splits start
 // on multiples of 64 columns and the column copy is padded to 64 rows, so
 // every tile load is in bounds; columns past the split get beta = kNegBig.
+//
+// Exponent shift: with shift_pot (the rows' previous potential at this eps)
+// each row i is shifted by the log-sum-exp that potential implies,
+// L_i = (eps log w_i + |u_i|^2 - shift_pot_i) / (eps ln 2), the value the
+// merge inverts.  Between Sinkhorn iterations L_i moves little, so the sum
+// of 2^(t_ij - L_i) stays near 1 and no running maximum (a max per pair and
+// a rescale per tile) is needed; the partial is written as (L_i, sum).  If
+// any row's sum over the split leaves [kSumLo, kSumHi] (a stale potential, a
+// non-finite value), the workgroup sweeps its split again with the running
+// maximum, which is what runs without shift_pot.
 template <int D, int QB, int NPART>
 __global__ __launch_bounds__(256) void lse_partial_bf16(
     const float *__restrict__ U, int64_t nu, int d, const __bf16 *__restrict__ Vlp, int64_t nv,
     int64_t vstride, const float *__restrict__ vsq, const float *__restrict__ vpot, float gamma,
     float scale2, float bscale, int S, int64_t cols_per_split, float *__restrict__ part_m,
-    float *__restrict__ part_s) {
+    float *__restrict__ part_s, const float *__restrict__ shift_pot, const float *__restrict__ usq,
+    const float *__restrict__ logw, float eps, float sum_hi) {
     using T = TileH<D, NPART>;
     constexpr int ROWS = 64 * QB;
     __shared__ __bf16 vt[2][NPART][T::BN * D];
@@ -173,9 +195,15 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
     for (int qb = 0; qb < QB; ++qb)
         scaled_row_operand<D, NPART>(U, nu, d, row0 + qb * 16 + li, lq, scale2, ub[qb]);
 
-    float run_m[QB], run_s[QB];
+    float sh[QB];
+    if (shift_pot) {
+        const float inv = 1.f / (eps * kLn2);
 #pragma unroll
-    for (int qb = 0; qb < QB; ++qb) { run_m[qb] = kNegBig; run_s[qb] = 0.f; }
+        for (int qb = 0; qb < QB; ++qb) {
+            const int64_t row = row0 + qb * 16 + li;
+            sh[qb] = row < nu ? (fmaf(eps, logw[row], usq[row]) - shift_pot[row]) * inv : 0.f;
+        }
+    }
 
     const int64_t c0 = (int64_t)split * cols_per_split;
     const int64_t c1 = c0 + cols_per_split < nv ? c0 + cols_per_split : nv;
@@ -205,94 +233,133 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
         if (tid < T::BN) bt[buf][tid] = bpre;
     };
 
-    if (ntiles > 0) {
-        fetch(0);
-        store(0);
-    }
-    __syncthreads();
+    // One sweep over the split's column tiles; (run_m, run_s) per row,
+    // combined over the four lane groups that share it.
+    float run_m[QB], run_s[QB];
+    auto sweep = [&](auto fixed_tag) {
+        constexpr bool FIXED = decltype(fixed_tag)::value;
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) { run_m[qb] = FIXED ? sh[qb] : kNegBig; run_s[qb] = 0.f; }
+        if (ntiles > 0) {
+            fetch(0);
+            store(0);
+        }
+        __syncthreads();
 
-    for (int t = 0; t < ntiles; ++t) {
-        const int buf = t & 1;
-        const bool more = t + 1 < ntiles;
-        if (more) fetch(t + 1);
-        // accumulators start at beta_j: the MFMA output is the exponent
-        f4 acc[QB][T::NSUB];
+        for (int t = 0; t < ntiles; ++t) {
+            const int buf = t & 1;
+            const bool more = t + 1 < ntiles;
+            if (more) fetch(t + 1);
+            // accumulators start at beta_j: the MFMA output is the exponent
+            f4 acc[QB][T::NSUB];
 #pragma unroll
-        for (int sub = 0; sub < T::NSUB; ++sub) {
-            const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
+            for (int sub = 0; sub < T::NSUB; ++sub) {
+                const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = beta;
-        }
-        // k outer; the column fragments of step s + 1 are read while step s
-        // runs, and each product term sweeps all NSUB x QB accumulators, so
-        // consecutive MFMAs are independent.
-        bf8 a[2][NPART][T::NSUB];
-        auto read_a = [&](int s, bf8 (&dst)[NPART][T::NSUB]) {
-#pragma unroll
-            for (int p = 0; p < NPART; ++p)
-#pragma unroll
-                for (int sub = 0; sub < T::NSUB; ++sub)
-                    dst[p][sub] = *reinterpret_cast<const bf8 *>(
-                        &vt[buf][p][tile_chunk(sub, T::C, lq * T::KS + s, li) * 8]);
-        };
-        read_a(0, a[0]);
-#pragma unroll
-        for (int s = 0; s < T::KS; ++s) {
-            if (s + 1 < T::KS) read_a(s + 1, a[(s + 1) & 1]);
-            const int cs = s & 1;
-#pragma unroll
-            for (int sub = 0; sub < T::NSUB; ++sub)
-#pragma unroll
-                for (int qb = 0; qb < QB; ++qb)
-                    acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][0][s], acc[qb][sub]);
-            if constexpr (NPART == 2) {
-#pragma unroll
-                for (int sub = 0; sub < T::NSUB; ++sub)
-#pragma unroll
-                    for (int qb = 0; qb < QB; ++qb)
-                        acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][1][s], acc[qb][sub]);
-#pragma unroll
-                for (int sub = 0; sub < T::NSUB; ++sub)
-#pragma unroll
-                    for (int qb = 0; qb < QB; ++qb)
-                        acc[qb][sub] = mfma_bf(a[cs][1][sub], ub[qb][0][s], acc[qb][sub]);
+                for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = beta;
             }
+            // k outer; the column fragments of step s + 1 are read while step
+            // s runs, and each product term sweeps all NSUB x QB
+            // accumulators, so consecutive MFMAs are independent.
+            bf8 a[2][NPART][T::NSUB];
+            auto read_a = [&](int s, bf8 (&dst)[NPART][T::NSUB]) {
+#pragma unroll
+                for (int p = 0; p < NPART; ++p)
+#pragma unroll
+                    for (int sub = 0; sub < T::NSUB; ++sub)
+                        dst[p][sub] = *reinterpret_cast<const bf8 *>(
+                            &vt[buf][p][tile_chunk(sub, T::C, lq * T::KS + s, li) * 8]);
+            };
+            read_a(0, a[0]);
+#pragma unroll
+            for (int s = 0; s < T::KS; ++s) {
+                if (s + 1 < T::KS) read_a(s + 1, a[(s + 1) & 1]);
+                const int cs = s & 1;
+#pragma unroll
+                for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                    for (int qb = 0; qb < QB; ++qb)
+                        acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][0][s], acc[qb][sub]);
+                if constexpr (NPART == 2) {
+#pragma unroll
+                    for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                        for (int qb = 0; qb < QB; ++qb)
+                            acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][1][s], acc[qb][sub]);
+#pragma unroll
+                    for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                        for (int qb = 0; qb < QB; ++qb)
+                            acc[qb][sub] = mfma_bf(a[cs][1][sub], ub[qb][0][s], acc[qb][sub]);
+                }
+            }
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) {
+                float s4[4] = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (FIXED) {
+#pragma unroll
+                    for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) s4[r] += ex2(acc[qb][sub][r] - sh[qb]);
+                    run_s[qb] += (s4[0] + s4[1]) + (s4[2] + s4[3]);
+                } else {
+                    float mx = kNegBig;
+#pragma unroll
+                    for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
+                    const float mn = fmaxf(run_m[qb], mx);
+#pragma unroll
+                    for (int sub = 0; sub < T::NSUB; ++sub)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) s4[r] += ex2(acc[qb][sub][r] - mn);
+                    run_s[qb] = fmaf(run_s[qb], ex2(run_m[qb] - mn), (s4[0] + s4[1]) + (s4[2] + s4[3]));
+                    run_m[qb] = mn;
+                }
+            }
+            if (more) store(buf ^ 1);
+            __syncthreads();
         }
+
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
-            float mx = kNegBig;
+            float m = run_m[qb], s = run_s[qb];
 #pragma unroll
-            for (int sub = 0; sub < T::NSUB; ++sub)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
-            const float mn = fmaxf(run_m[qb], mx);
-            float s4[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int sub = 0; sub < T::NSUB; ++sub)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) s4[r] += ex2(acc[qb][sub][r] - mn);
-            run_s[qb] = fmaf(run_s[qb], ex2(run_m[qb] - mn), (s4[0] + s4[1]) + (s4[2] + s4[3]));
-            run_m[qb] = mn;
+            for (int off = 16; off <= 32; off <<= 1) {
+                const float so = __shfl_xor(s, off);
+                if constexpr (FIXED) {
+                    s += so;
+                } else {
+                    const float mo = __shfl_xor(m, off);
+                    const float mn = fmaxf(m, mo);
+                    s = s * ex2(m - mn) + so * ex2(mo - mn);
+                    m = mn;
+                }
+            }
+            run_m[qb] = m;
+            run_s[qb] = s;
         }
-        if (more) store(buf ^ 1);
-        __syncthreads();
+    };
+
+    bool redo = true;
+    if (shift_pot) {
+        sweep(std::true_type{});
+        int bad = 0;
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+            const bool in_range = run_s[qb] <= sum_hi && (ntiles == 0 || run_s[qb] >= kSumLo);
+            if (row0 + qb * 16 + li < nu && !in_range) bad = 1;
+        }
+        redo = __syncthreads_or(bad) != 0;
     }
+    if (redo) sweep(std::false_type{});
 
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-        float m = run_m[qb], s = run_s[qb];
-#pragma unroll
-        for (int off = 16; off <= 32; off <<= 1) {
-            const float mo = __shfl_xor(m, off);
-            const float so = __shfl_xor(s, off);
-            const float mn = fmaxf(m, mo);
-            s = s * ex2(m - mn) + so * ex2(mo - mn);
-            m = mn;
-        }
         const int64_t row = row0 + qb * 16 + li;
         if (lq == 0 && row < nu) {
-            part_m[split * nu + row] = m;
-            part_s[split * nu + row] = s;
+            part_m[split * nu + row] = run_m[qb];
+            part_s[split * nu + row] = run_s[qb];
         }
     }
 }
@@ -859,6 +926,20 @@ __global__ __launch_bounds__(256) void f16_transpose(const float *__restrict__ Y
     yt[e] = (_Float16)ldexpf(y, k);
 }
 
+// PROGOT_BF16_SHIFT (read at every launch): unset, the fixed exponent shift
+// wherever the job carries the previous potential; "off", the running
+// maximum only; "recheck", every fixed-shift sweep fails its range check and
+// is redone with the running maximum (the fallback, which then computes the
+// same bits as "off").
+enum class ShiftMode { kAuto, kOff, kRecheck };
+ShiftMode shift_mode() {
+    const char *e = std::getenv("PROGOT_BF16_SHIFT");
+    if (!e) return ShiftMode::kAuto;
+    if (!std::strcmp(e, "off")) return ShiftMode::kOff;
+    if (!std::strcmp(e, "recheck")) return ShiftMode::kRecheck;
+    return ShiftMode::kAuto;
+}
+
 template <int D, int QB, int NPART>
 hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     // the plan must cover every row tile of this kernel variant, and splits
@@ -866,9 +947,12 @@ hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     if (a.blocks != (a.nu + 64 * QB - 1) / (64 * QB) * a.S || a.cps % 64 != 0)
         return hipErrorInvalidValue;
     const int64_t vstride = bf16_mpad(a.nv) * D;
+    const ShiftMode mode = shift_mode();
+    const float *shift = mode == ShiftMode::kOff ? nullptr : a.shift_pot;
+    const float sum_hi = mode == ShiftMode::kRecheck ? -1.f : kSumHi;
     timed_launch(0, lse_partial_bf16<D, QB, NPART>, dim3((unsigned)a.blocks), dim3(256), 0, s, a.U,
                  a.nu, a.d, (const __bf16 *)a.V_lp, a.nv, vstride, a.vsq, a.vpot, a.gamma, a.scale2,
-                 a.bscale, a.S, a.cps, a.part_m, a.part_s);
+                 a.bscale, a.S, a.cps, a.part_m, a.part_s, shift, a.usq, a.logw, a.eps, sum_hi);
     return hipGetLastError();
 }
 

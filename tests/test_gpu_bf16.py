@@ -48,6 +48,40 @@ def test_bf16x3_fixed_iterations(P, n, m, d):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("n,m,d", [(1000, 777, 64), (300, 513, 100), (200, 700, 256),
+                                   # n << m: > 32 column splits, the last ones empty
+                                   (130, 40000, 64)])
+def test_fixed_shift_and_its_fallback(P, monkeypatch, prec, n, m, d):
+    """From the second iteration the BF16 partial kernels shift each row by
+    the log-sum-exp of its previous potential instead of a running maximum.
+    With PROGOT_BF16_SHIFT=recheck every fixed-shift sweep fails its range
+    check and is redone with the running maximum: the same bits as =off
+    (running maximum only).  The default (fixed shift) agrees with both to
+    FP32 rounding of the exponents, and BF16X3 meets the oracle bar."""
+    X, Y = workloads.sphere(seed=500 + d, n=n, m=m, d=d, n_clusters=6)
+    a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+    eps = float(np.float32(oracle.mean_cost(X, Y) / 20.0))
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=prec)
+    res = {}
+    for mode in ("off", "recheck", "auto"):
+        print(f"case {prec} n={n} m={m} d={d} shift={mode}", flush=True)
+        if mode == "auto":
+            monkeypatch.delenv("PROGOT_BF16_SHIFT", raising=False)
+        else:
+            monkeypatch.setenv("PROGOT_BF16_SHIFT", mode)
+        f, g, _ = P.sinkhorn_solve(cl, eps, tau=0.0, max_iter=11)
+        res[mode] = (f.cpu().numpy(), g.cpu().numpy())
+    monkeypatch.delenv("PROGOT_BF16_SHIFT", raising=False)
+    assert np.array_equal(res["recheck"][0], res["off"][0])
+    assert np.array_equal(res["recheck"][1], res["off"][1])
+    for k in (0, 1):
+        assert pot_err(res["auto"][k], res["off"][k], eps) < 1e-5
+    if prec == "bf16x3":
+        ref = oracle.sinkhorn(a, X, b, Y, eps, 0.0, n_iter=11)
+        assert pot_err(res["auto"][0], ref.f, eps) < 1e-4 and pot_err(res["auto"][1], ref.g, eps) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
 @pytest.mark.parametrize("nq,m,d", [(300, 1000, 128), (333, 999, 200), (129, 1025, 256), (1, 33, 256)])
 def test_bf16_map_ragged(P, prec, nq, m, d):
     """Entropic map of both BF16 forms on ragged sizes (query blocks and the

@@ -140,8 +140,25 @@ __device__ __forceinline__ int tile_chunk(int blk16, int C, int c, int li) {
     return ((blk16 * C) + c) * 16 + li;
 }
 
-template <int D, int NPART> struct TileH {
-    static constexpr int BN = (D * NPART >= 512) ? 32 : 64;  // columns per LDS tile
+// Shape of the potential kernel per (D, NPART): QB 16-row blocks per wave
+// and BN columns per LDS tile.  A wave holds 16 QB rows in registers and
+// reads every column fragment of a tile from LDS once, so LDS traffic per
+// MFMA flop is 1 / (16 QB) bytes for BF16 operands: at QB = 2 the MFMA peak
+// would take ~127 bytes of LDS reads per clock per CU, of the order of the
+// LDS read rate, and the kernel was co-bound by it.  QB = 4 with 32-column
+// tiles (the same accumulator registers, half the LDS per workgroup)
+// measured 7-11 % faster at D = 128 and 256 (BF16) and D = 64 and 128
+// (BF16X3), 2 % at D = 64 (BF16).  BF16X3 at D = 256 keeps QB = 2 (its row
+// operand alone would take 256 registers at QB = 4); D = 32 keeps 64-column
+// tiles (a tile must be whole loader rounds); QB = 8 at D = 64 would halve
+// the waves per SIMD.
+struct LseShape { int qb, bn; };
+constexpr LseShape lse_shape(int D, int npart) {
+    return (D >= 64 && D * npart <= 256) ? LseShape{4, 32} : LseShape{2, D * npart >= 512 ? 32 : 64};
+}
+
+template <int D, int NPART, int BN_ = lse_shape(D, NPART).bn> struct TileH {
+    static constexpr int BN = BN_;           // columns per LDS tile
     static constexpr int NSUB = BN / 16;
     static constexpr int KS = D / 32;        // MFMA k-steps over the features
     static constexpr int C = D / 8;          // 16-byte chunks per column
@@ -171,14 +188,14 @@ constexpr float kSumLo = 0x1p-64f, kSumHi = 0x1p64f;
 // any row's sum over the split leaves [kSumLo, kSumHi] (a stale potential, a
 // non-finite value), the workgroup sweeps its split again with the running
 // maximum, which is what runs without shift_pot.
-template <int D, int QB, int NPART>
+template <int D, int QB, int NPART, int BN>
 __global__ __launch_bounds__(256) void lse_partial_bf16(
     const float *__restrict__ U, int64_t nu, int d, const __bf16 *__restrict__ Vlp, int64_t nv,
     int64_t vstride, const float *__restrict__ vsq, const float *__restrict__ vpot, float gamma,
     float scale2, float bscale, int S, int64_t cols_per_split, float *__restrict__ part_m,
     float *__restrict__ part_s, const float *__restrict__ shift_pot, const float *__restrict__ usq,
     const float *__restrict__ logw, float eps, float sum_hi) {
-    using T = TileH<D, NPART>;
+    using T = TileH<D, NPART, BN>;
     constexpr int ROWS = 64 * QB;
     __shared__ __bf16 vt[2][NPART][T::BN * D];
     __shared__ float bt[2][T::BN];
@@ -940,8 +957,9 @@ ShiftMode shift_mode() {
     return ShiftMode::kAuto;
 }
 
-template <int D, int QB, int NPART>
+template <int D, int NPART>
 hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
+    constexpr int QB = lse_shape(D, NPART).qb, BN = lse_shape(D, NPART).bn;
     // the plan must cover every row tile of this kernel variant, and splits
     // must start on the 64-column boundaries of the padded copy
     if (a.blocks != (a.nu + 64 * QB - 1) / (64 * QB) * a.S || a.cps % 64 != 0)
@@ -950,7 +968,7 @@ hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     const ShiftMode mode = shift_mode();
     const float *shift = mode == ShiftMode::kOff ? nullptr : a.shift_pot;
     const float sum_hi = mode == ShiftMode::kRecheck ? -1.f : kSumHi;
-    timed_launch(0, lse_partial_bf16<D, QB, NPART>, dim3((unsigned)a.blocks), dim3(256), 0, s, a.U,
+    timed_launch(0, lse_partial_bf16<D, QB, NPART, BN>, dim3((unsigned)a.blocks), dim3(256), 0, s, a.U,
                  a.nu, a.d, (const __bf16 *)a.V_lp, a.nv, vstride, a.vsq, a.vpot, a.gamma, a.scale2,
                  a.bscale, a.S, a.cps, a.part_m, a.part_s, shift, a.usq, a.logw, a.eps, sum_hi);
     return hipGetLastError();
@@ -988,26 +1006,18 @@ int bf16_dim(int d) {
 
 int64_t bf16_mpad(int64_t m) { return (m + 63) / 64 * 64; }
 
-// Rows per workgroup: 4 waves x QB x 16.  Each column fragment read from LDS
-// feeds QB (x3 for the split form) MFMAs; QB = 2 keeps two waves per SIMD
-// (measured faster than QB = 4 at one wave per SIMD on d = 256).
-constexpr int lse_qb(int npart) { (void)npart; return 2; }
+// Rows per workgroup: 4 waves x QB x 16 (lse_shape).
 int lse_bf16_rows_per_block(int d, int precision) {
-    (void)d;
-    return 64 * lse_qb(precision == 2 ? 2 : 1);
+    return 64 * lse_shape(bf16_dim(d), precision == 2 ? 2 : 1).qb;
 }
 
 hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s) {
     const bool x3 = a.precision == 2;
     switch (bf16_dim(a.d)) {
-        case 32: return x3 ? lse_bf16_t<32, lse_qb(2), 2>(a, s)
-                           : lse_bf16_t<32, lse_qb(1), 1>(a, s);
-        case 64: return x3 ? lse_bf16_t<64, lse_qb(2), 2>(a, s)
-                           : lse_bf16_t<64, lse_qb(1), 1>(a, s);
-        case 128: return x3 ? lse_bf16_t<128, lse_qb(2), 2>(a, s)
-                            : lse_bf16_t<128, lse_qb(1), 1>(a, s);
-        default: return x3 ? lse_bf16_t<256, lse_qb(2), 2>(a, s)
-                           : lse_bf16_t<256, lse_qb(1), 1>(a, s);
+        case 32: return x3 ? lse_bf16_t<32, 2>(a, s) : lse_bf16_t<32, 1>(a, s);
+        case 64: return x3 ? lse_bf16_t<64, 2>(a, s) : lse_bf16_t<64, 1>(a, s);
+        case 128: return x3 ? lse_bf16_t<128, 2>(a, s) : lse_bf16_t<128, 1>(a, s);
+        default: return x3 ? lse_bf16_t<256, 2>(a, s) : lse_bf16_t<256, 1>(a, s);
     }
 }
 

@@ -29,6 +29,21 @@ __device__ __forceinline__ void stg(T *p, T v) {
     *(__attribute__((address_space(1))) T *)p = v;
 }
 
+// Maximum of v over the lanes l, l ^ 16, l ^ 32 and l ^ 48 (the four lane
+// groups that share an MFMA output column) with the cross-row swaps of
+// gfx950, which stay in the VALU: v_permlane16_swap of v with itself leaves
+// v[l & ~16] in one result and v[l | 16] in the other, v_permlane32_swap the
+// same for bit 5.  A __shfl_xor is an LDS round trip (ds_bpermute) on the
+// critical path of every tile.  All 64 lanes must be active.
+__device__ __forceinline__ float max_lane_groups(float v) {
+    const unsigned u = __float_as_uint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    const float m = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    const unsigned w = __float_as_uint(m);
+    const auto b = __builtin_amdgcn_permlane32_swap(w, w, false, false);
+    return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }

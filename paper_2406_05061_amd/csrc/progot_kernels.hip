@@ -619,8 +619,7 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
             for (int sub = 0; sub < T::NSUB; ++sub)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
-            mx = fmaxf(mx, __shfl_xor(mx, 16));
-            mx = fmaxf(mx, __shfl_xor(mx, 32));
+            mx = max_lane_groups(mx);
             const float mn = fmaxf(run_m[qb], mx);
             // rescale every tile: a wave-uniform test to skip it when no
             // maximum rose measured 2 % slower than the multiplies it saves

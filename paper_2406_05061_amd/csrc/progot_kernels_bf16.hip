@@ -551,8 +551,7 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
             for (int sub = 0; sub < 2; ++sub)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
-            mx = fmaxf(mx, __shfl_xor(mx, 16));
-            mx = fmaxf(mx, __shfl_xor(mx, 32));
+            mx = max_lane_groups(mx);
             const bool up = mx > m_used[qb] + kLazy;
             if (__builtin_amdgcn_ballot_w64(up)) {
                 const float mn = up ? mx : m_used[qb];
@@ -775,8 +774,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_wide(
         for (int sub = 0; sub < 2; ++sub)
 #pragma unroll
             for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[sub][r]);
-        mx = fmaxf(mx, __shfl_xor(mx, 16));
-        mx = fmaxf(mx, __shfl_xor(mx, 32));
+        mx = max_lane_groups(mx);
         const bool up = mx > m_used + kLazy;
         const bool any = __builtin_amdgcn_ballot_w64(up) != 0;
         float csf = 1.f;

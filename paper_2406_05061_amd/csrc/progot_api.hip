@@ -408,7 +408,7 @@ struct Events {
 // The iterates and the returned one are the same as with the mapped slots.
 int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, int max_iter,
                   const float *g_init, float gamma, SinkResult *out, hipStream_t s,
-                  bool copy_rb = false) {
+                  bool copy_rb = false, const float *f_warm = nullptr) {
     float *fb[kRing] = {at<float>(c, L.f0), at<float>(c, L.f1), at<float>(c, L.f2)};
     float *gb[kRing] = {at<float>(c, L.g0), at<float>(c, L.g1), at<float>(c, L.g2)};
     float *hdev = nullptr;
@@ -455,7 +455,8 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
         fa.vpot = t == 1 ? g_init : gb[(t - 1) % kRing];
         fa.gamma = t == 1 ? gamma : 1.f;
         fa.pot_old = t == 1 ? nullptr : fb[(t - 1) % kRing];
-        fa.shift_pot = fa.pot_old;
+        fa.shift_pot = t == 1 ? f_warm : fa.pot_old;
+        fa.shift_gamma = t == 1 ? gamma : 1.f;
         fa.pot_out = fb[t % kRing];
         int nparts = 0;
         if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) return POT_ERR_DEVICE;
@@ -465,7 +466,8 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
             return status;
         if (lag == 0 && t > 1 && check(t - 1, &status)) return status;
         ga.vpot = fb[t % kRing];
-        ga.shift_pot = t == 1 ? nullptr : gb[(t - 1) % kRing];
+        ga.shift_pot = t == 1 ? g_init : gb[(t - 1) % kRing];
+        ga.shift_gamma = t == 1 ? gamma : 1.f;
         ga.pot_out = gb[t % kRing];
         const bool carry = fold && t > 1;
         ga.esum_in = carry ? at<float>(c, L.errp) : nullptr;
@@ -482,7 +484,8 @@ int sinkhorn_core(const pot_clouds *c, const Layout &L, float eps, float tau, in
                 if (check(k, &status)) return status;
             // err of the last iterate: one more f-update into the free slot
             fa.vpot = gb[t % kRing]; fa.gamma = 1.f;
-            fa.pot_old = fb[t % kRing]; fa.shift_pot = fa.pot_old; fa.pot_out = fb[(t + 1) % kRing];
+            fa.pot_old = fb[t % kRing]; fa.shift_pot = fa.pot_old; fa.shift_gamma = 1.f;
+            fa.pot_out = fb[(t + 1) % kRing];
             if (pot::launch_lse_update(fa, s, &nparts) != hipSuccess) return POT_ERR_DEVICE;
             if ((status = enqueue_err_readback(c, L, nparts, hdev + t % kRing, E.ev[t % kRing], s)) !=
                 POT_OK)
@@ -658,14 +661,18 @@ int pot_progot_solve(pot_clouds *c, const pot_progot_params *p, float *f, float 
     pot_progot_info loc{};
     loc.K = K;
     loc.converged = 1;
+    const float *f_prev = nullptr;   // the previous step's f (a ring slot of the workspace)
     for (int k = 0; k < K; ++k) {
         float eps, tau, gamma;
         st = step_values(p, alpha, k, c->mean_cost, &eps, &tau, &gamma);
         if (st != POT_OK) return st;
         const float *g_init = k == 0 ? nullptr : G + (size_t)(k - 1) * m;
         SinkResult r;
-        st = sinkhorn_core(c, L, eps, tau, p->max_iter, g_init, gamma, &r, s);
+        // the warm start of both potentials also serves as the exponent
+        // shift of the first iteration (BF16 forms)
+        st = sinkhorn_core(c, L, eps, tau, p->max_iter, g_init, gamma, &r, s, false, f_prev);
         if (st != POT_OK) return st;
+        f_prev = r.f;
         POT_TRY(hipMemcpyAsync(G + (size_t)k * m, r.g, m * sizeof(float), hipMemcpyDeviceToDevice, s));
         loc.iters[k] = r.iters; loc.err[k] = r.err; loc.eps[k] = eps; loc.alpha[k] = alpha[k];
         if (!r.converged) loc.converged = 0;

@@ -74,11 +74,16 @@ struct LseJob {
     const float *esum_in;
     int esum_n;
     float *esum_out;
-    // Previous potential of the rows at the same eps and clouds (NULL: none).
-    // The BF16 partial kernels take the log-sum-exp it implies as a fixed
-    // exponent shift instead of a running maximum; a workgroup whose sums
-    // leave the safe range redoes its split with the running maximum.
+    // An estimate of the rows' new potential, times shift_gamma (NULL: none):
+    // the previous iterate's at the same eps and clouds, or at the first
+    // iteration of a ProgOT step the warm start (1 - alpha_k) times the
+    // previous step's.  The BF16 partial kernels take the log-sum-exp it
+    // implies as a fixed exponent shift instead of a running maximum; a
+    // workgroup whose sums leave the safe range redoes its split with the
+    // running maximum, so the estimate decides speed, never the result's
+    // validity.
     const float *shift_pot;
+    float shift_gamma;
 };
 
 typedef LseJob LseArgs;

@@ -179,12 +179,14 @@ constexpr float kSumLo = 0x1p-64f, kSumHi = 0x1p64f;
 // on multiples of 64 columns and the column copy is padded to 64 rows, so
 // every tile load is in bounds; columns past the split get beta = kNegBig.
 //
-// Exponent shift: with shift_pot (the rows' previous potential at this eps)
-// each row i is shifted by the log-sum-exp that potential implies,
-// L_i = (eps log w_i + |u_i|^2 - shift_pot_i) / (eps ln 2), the value the
-// merge inverts.  Between Sinkhorn iterations L_i moves little, so the sum
-// of 2^(t_ij - L_i) stays near 1 and no running maximum (a max per pair and
-// a rescale per tile) is needed; the partial is written as (L_i, sum).  If
+// Exponent shift: with shift_pot (an estimate of the rows' new potential,
+// scaled by shift_gamma: the previous iterate's, or a ProgOT step's warm
+// start) each row i is shifted by the log-sum-exp that potential implies,
+// L_i = (eps log w_i + |u_i|^2 - shift_gamma shift_pot_i) / (eps ln 2), the
+// value the merge inverts.  Between Sinkhorn iterations, and from a warm
+// start to the first iterate, L_i moves little, so the sum of 2^(t_ij - L_i)
+// stays near 1 and no running maximum (a max per pair and a rescale per
+// tile) is needed; the partial is written as (L_i, sum).  If
 // any row's sum over the split leaves [kSumLo, kSumHi] (a stale potential, a
 // non-finite value), the workgroup sweeps its split again with the running
 // maximum, which is what runs without shift_pot.
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
     int64_t vstride, const float *__restrict__ vsq, const float *__restrict__ vpot, float gamma,
     float scale2, float bscale, int S, int64_t cols_per_split, float *__restrict__ part_m,
     float *__restrict__ part_s, const float *__restrict__ shift_pot, const float *__restrict__ usq,
-    const float *__restrict__ logw, float eps, float sum_hi) {
+    const float *__restrict__ logw, float eps, float sum_hi, float shift_gamma) {
     using T = TileH<D, NPART, BN>;
     constexpr int ROWS = 64 * QB;
     __shared__ __bf16 vt[2][NPART][T::BN * D];
@@ -218,7 +220,7 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
             const int64_t row = row0 + qb * 16 + li;
-            sh[qb] = row < nu ? (fmaf(eps, logw[row], usq[row]) - shift_pot[row]) * inv : 0.f;
+            sh[qb] = row < nu ? (fmaf(eps, logw[row], usq[row]) - shift_gamma * shift_pot[row]) * inv : 0.f;
         }
     }
 
@@ -968,7 +970,8 @@ hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     const float sum_hi = mode == ShiftMode::kRecheck ? -1.f : kSumHi;
     timed_launch(0, lse_partial_bf16<D, QB, NPART, BN>, dim3((unsigned)a.blocks), dim3(256), 0, s, a.U,
                  a.nu, a.d, (const __bf16 *)a.V_lp, a.nv, vstride, a.vsq, a.vpot, a.gamma, a.scale2,
-                 a.bscale, a.S, a.cps, a.part_m, a.part_s, shift, a.usq, a.logw, a.eps, sum_hi);
+                 a.bscale, a.S, a.cps, a.part_m, a.part_s, shift, a.usq, a.logw, a.eps, sum_hi,
+                 a.shift_gamma);
     return hipGetLastError();
 }
 

@@ -82,6 +82,36 @@ def test_fixed_shift_and_its_fallback(P, monkeypatch, prec, n, m, d):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+def test_progot_warm_start_shift(P, monkeypatch, prec):
+    """From the second ProgOT step the first iteration's exponent shift comes
+    from the warm start, (1 - alpha_k) times the previous step's potentials.
+    Over a whole solve PROGOT_BF16_SHIFT=recheck (every fixed-shift sweep
+    redone with the running maximum) reproduces =off bit for bit, and the
+    default meets the ProgOT bars against the oracle (BF16X3)."""
+    n, m, d = 1500, 1200, 64
+    X, Y = workloads.sphere(seed=640, n=n, m=m, d=d, n_clusters=6)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=prec)
+    res = {}
+    for mode in ("off", "recheck", "auto"):
+        print(f"case ProgOT {prec} n={n} m={m} d={d} shift={mode}", flush=True)
+        if mode == "auto":
+            monkeypatch.delenv("PROGOT_BF16_SHIFT", raising=False)
+        else:
+            monkeypatch.setenv("PROGOT_BF16_SHIFT", mode)
+        f, G, TX, info = P.progot_solve(cl, 4, tau_first=1e-3, tau_last=1e-3)
+        res[mode] = (f.cpu().numpy(), G.cpu().numpy(), TX.cpu().numpy(), list(info.iters))
+    monkeypatch.delenv("PROGOT_BF16_SHIFT", raising=False)
+    for k in range(3):
+        assert np.array_equal(res["recheck"][k], res["off"][k])
+    assert res["recheck"][3] == res["off"][3]
+    if prec == "bf16x3":
+        a, b = np.full(n, 1.0 / n), np.full(m, 1.0 / m)
+        ref = oracle.progot(a, X, b, Y, 4, tau=1e-3)
+        assert all(abs(p - q) <= 2 for p, q in zip(res["auto"][3], ref.iters))
+        assert map_err(res["auto"][2], ref.TX, Y) < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
 @pytest.mark.parametrize("nq,m,d", [(300, 1000, 128), (333, 999, 200), (129, 1025, 256), (1, 33, 256)])
 def test_bf16_map_ragged(P, prec, nq, m, d):
     """Entropic map of both BF16 forms on ragged sizes (query blocks and the

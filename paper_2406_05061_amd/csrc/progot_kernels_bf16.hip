@@ -392,12 +392,15 @@ __host__ __device__ constexpr int perm32(int k) {
     return (k & 7) < 4 ? 4 * (k >> 3) + (k & 7) : 16 + 4 * (k >> 3) + (k & 7) - 4;
 }
 
-// Entropic map + McCann-type step.  The projection product is P x (Y_hi +
-// Y_lo) with P rounded to BF16 (NPART = 1) or split as P_hi + P_lo with the
-// three products P_hi Y_hi + P_hi Y_lo + P_lo Y_hi (NPART = 2, so both
-// products of the split form carry ~16 bits).  The normaliser is the same
-// product against a row of ones, so it sums exactly the weights applied to
-// the targets: T is a convex combination of the targets.
+// Entropic map + McCann-type step.  The projection product is FP16 weights
+// times one FP16 copy of Y scaled by a power of two (NPART = 1), or P split
+// as P_hi + P_lo with the three products P_hi Y_hi + P_hi Y_lo + P_lo Y_hi
+// (NPART = 2, so both products of the split form carry ~16 bits).  The
+// normaliser is the same product against a row of ones, so it sums exactly
+// the weights applied to the targets: T is a convex combination of the
+// targets.  A tile is NG groups of 32 columns (kMapBN); the transposed copy
+// holds each group in the perm32 order, and the softmax (maximum, rescale,
+// weights) runs once per tile.
 // P = 2^(t - m_used) with m_used the running maximum.  The output
 // accumulator is rescaled only in tiles where some row of the wave sets a new
 // maximum (a row does so about log(tiles) times for columns in random
@@ -407,13 +410,14 @@ __host__ __device__ constexpr int perm32(int k) {
 constexpr int kMapBN = 32;
 constexpr float kLazy = 0.f;
 
-template <int D, int QB, int NPART>
+template <int D, int QB, int NPART, int NG>
 __global__ __launch_bounds__(256) void entropic_map_bf16(
     const float *Xq, int64_t nq, int d, const __bf16 *__restrict__ Ylp,
     const __bf16 *__restrict__ YTlp, int64_t m, int64_t mp, const float *__restrict__ ysq,
     const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout,
     float *__restrict__ out_sqn, const float *__restrict__ yt_unscale) {
-    constexpr int BN = kMapBN;
+    constexpr int BN = kMapBN * NG;            // NG groups of 32 columns per tile
+    constexpr int NS = 2 * NG;                 // 16-column score subtiles
     constexpr int KS = D / 32, C = D / 8;
     constexpr int NDB = D / 16;
     constexpr int ROWS = 64 * QB;
@@ -503,21 +507,21 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
         const int buf = t & 1;
         const bool more = t + 1 < ntiles;
         if (more) fetch(t + 1);
-        f4 acc[QB][2];
+        f4 acc[QB][NS];
 #pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
+        for (int sub = 0; sub < NS; ++sub) {
             const f4 beta = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
             for (int qb = 0; qb < QB; ++qb) acc[qb][sub] = beta;
         }
         // k outer with the next step's fragments read ahead; each product
-        // term sweeps the 2 x QB accumulators (independent consecutive MFMAs)
-        bf8 a[2][NPART][2];
-        auto read_a = [&](int s, bf8 (&dst)[NPART][2]) {
+        // term sweeps the NS x QB accumulators (independent consecutive MFMAs)
+        bf8 a[2][NPART][NS];
+        auto read_a = [&](int s, bf8 (&dst)[NPART][NS]) {
 #pragma unroll
             for (int p = 0; p < NPART; ++p)
 #pragma unroll
-                for (int sub = 0; sub < 2; ++sub)
+                for (int sub = 0; sub < NS; ++sub)
                     dst[p][sub] = *reinterpret_cast<const bf8 *>(
                         &yr[buf][p][tile_chunk(sub, C, lq * KS + s, li) * 8]);
         };
@@ -527,30 +531,30 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
             if (s + 1 < KS) read_a(s + 1, a[(s + 1) & 1]);
             const int cs = s & 1;
 #pragma unroll
-            for (int sub = 0; sub < 2; ++sub)
+            for (int sub = 0; sub < NS; ++sub)
 #pragma unroll
                 for (int qb = 0; qb < QB; ++qb)
                     acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][0][s], acc[qb][sub]);
             if constexpr (NPART == 2) {
 #pragma unroll
-                for (int sub = 0; sub < 2; ++sub)
+                for (int sub = 0; sub < NS; ++sub)
 #pragma unroll
                     for (int qb = 0; qb < QB; ++qb)
                         acc[qb][sub] = mfma_bf(a[cs][0][sub], ub[qb][1][s], acc[qb][sub]);
 #pragma unroll
-                for (int sub = 0; sub < 2; ++sub)
+                for (int sub = 0; sub < NS; ++sub)
 #pragma unroll
                     for (int qb = 0; qb < QB; ++qb)
                         acc[qb][sub] = mfma_bf(a[cs][1][sub], ub[qb][0][s], acc[qb][sub]);
             }
         }
-        bf8 pb[QB], pl[NPART == 2 ? QB : 1];
-        h8 p16[QB];
+        bf8 pb[QB][NG], pl[NPART == 2 ? QB : 1][NG];
+        h8 p16[QB][NG];
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
             float mx = kNegBig;
 #pragma unroll
-            for (int sub = 0; sub < 2; ++sub)
+            for (int sub = 0; sub < NS; ++sub)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
             mx = max_lane_groups(mx);
@@ -563,50 +567,58 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 #pragma unroll
                 for (int db = 0; db < NDB; ++db) o[qb][db] *= cs;
             }
-            if constexpr (NPART == 1) {
-                p16[qb] = weights_f16(acc[qb], m_used[qb] - kF16Shift);
-            } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const float v = ex2(acc[qb][e >> 2][e & 3] - m_used[qb]);
-                    const __bf16 h = (__bf16)v;
-                    pb[qb][e] = h;
-                    pl[qb][e] = (__bf16)(v - (float)h);
+            for (int g2 = 0; g2 < NG; ++g2) {
+                const f4 pair[2] = {acc[qb][2 * g2], acc[qb][2 * g2 + 1]};
+                if constexpr (NPART == 1) {
+                    p16[qb][g2] = weights_f16(pair, m_used[qb] - kF16Shift);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float v = ex2(pair[e >> 2][e & 3] - m_used[qb]);
+                        const __bf16 h = (__bf16)v;
+                        pb[qb][g2][e] = h;
+                        pl[qb][g2][e] = (__bf16)(v - (float)h);
+                    }
                 }
             }
         }
-        // O^T += Y^T P^T: each Y^T fragment (16 dims x 32 columns) is read
-        // once and feeds the QB row blocks; the hi part of every dimension
-        // block is applied before the lo part, so an accumulator is not
-        // touched by consecutive MFMAs
-        if constexpr (NPART == 1) {
-            // one FP16 product against the scaled FP16 copy
+        // O^T += Y^T P^T per 32-column group: each Y^T fragment (16 dims x 32
+        // columns) is read once and feeds the QB row blocks; the hi part of
+        // every dimension block is applied before the lo part, so an
+        // accumulator is not touched by consecutive MFMAs
 #pragma unroll
-            for (int db = 0; db < NDB; ++db) {
-                const h8 av =
-                    as_h8(*reinterpret_cast<const bf8 *>(&ytr[buf][0][tile_chunk(db, 4, lq, li) * 8]));
-#pragma unroll
-                for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_h(av, p16[qb], o[qb][db]);
-            }
-#pragma unroll
-            for (int qb = 0; qb < QB; ++qb) on[qb] = mfma_h(ones16, p16[qb], on[qb]);
-        } else {
-#pragma unroll
-            for (int p2 = 0; p2 < 2; ++p2)
+        for (int g2 = 0; g2 < NG; ++g2) {
+            const int goff = g2 * D * kMapBN;
+            if constexpr (NPART == 1) {
+                // one FP16 product against the scaled FP16 copy
 #pragma unroll
                 for (int db = 0; db < NDB; ++db) {
-                    const bf8 av =
-                        *reinterpret_cast<const bf8 *>(&ytr[buf][p2][tile_chunk(db, 4, lq, li) * 8]);
+                    const h8 av = as_h8(
+                        *reinterpret_cast<const bf8 *>(&ytr[buf][0][goff + tile_chunk(db, 4, lq, li) * 8]));
 #pragma unroll
-                    for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pb[qb], o[qb][db]);
-                    if (p2 == 0)
-#pragma unroll
-                        for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pl[qb], o[qb][db]);
+                    for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_h(av, p16[qb][g2], o[qb][db]);
                 }
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) {
-                on[qb] = mfma_bf(ones, pb[qb], on[qb]);
-                on[qb] = mfma_bf(ones, pl[qb], on[qb]);
+                for (int qb = 0; qb < QB; ++qb) on[qb] = mfma_h(ones16, p16[qb][g2], on[qb]);
+            } else {
+#pragma unroll
+                for (int p2 = 0; p2 < 2; ++p2)
+#pragma unroll
+                    for (int db = 0; db < NDB; ++db) {
+                        const bf8 av = *reinterpret_cast<const bf8 *>(
+                            &ytr[buf][p2][goff + tile_chunk(db, 4, lq, li) * 8]);
+#pragma unroll
+                        for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pb[qb][g2], o[qb][db]);
+                        if (p2 == 0)
+#pragma unroll
+                            for (int qb = 0; qb < QB; ++qb) o[qb][db] = mfma_bf(av, pl[qb][g2], o[qb][db]);
+                    }
+#pragma unroll
+                for (int qb = 0; qb < QB; ++qb) {
+                    on[qb] = mfma_bf(ones, pb[qb][g2], on[qb]);
+                    on[qb] = mfma_bf(ones, pl[qb][g2], on[qb]);
+                }
             }
         }
         if (more) store(buf ^ 1);
@@ -985,12 +997,12 @@ hipError_t map_bf16_wide_t(const MapArgs &a, float scale2, float bscale, hipStre
     return hipGetLastError();
 }
 
-template <int D, int QB, int NPART>
+template <int D, int QB, int NPART, int NG>
 hipError_t map_bf16_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     if (a.mp != bf16_mpad(a.m)) return hipErrorInvalidValue;
     const int64_t tiles = (a.nq + 64 * QB - 1) / (64 * QB);
     if (NPART == 1 && !a.yt_unscale) return hipErrorInvalidValue;
-    timed_launch(1, entropic_map_bf16<D, QB, NPART>, dim3((unsigned)tiles), dim3(256), 0, s, a.Xq,
+    timed_launch(1, entropic_map_bf16<D, QB, NPART, NG>, dim3((unsigned)tiles), dim3(256), 0, s, a.Xq,
                  a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
                  scale2, bscale, a.alpha, a.Xout, a.out_sqn, a.yt_unscale);
     return hipGetLastError();
@@ -1028,16 +1040,22 @@ hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStre
         // two 16-row blocks per wave up to D = 128: four at D = 32 and 64
         // measured 23-27 % slower (two waves per SIMD instead of three or
         // four), one at D = 128 35-53 % slower (each LDS fragment then feeds
-        // half the MFMAs)
-        case 32: return x3 ? map_bf16_t<32, 2, 2>(a, scale2, bscale, s) : map_bf16_t<32, 2, 1>(a, scale2, bscale, s);
-        case 64: return x3 ? map_bf16_t<64, 2, 2>(a, scale2, bscale, s) : map_bf16_t<64, 2, 1>(a, scale2, bscale, s);
-        case 128: return x3 ? map_bf16_t<128, 2, 2>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1>(a, scale2, bscale, s);
+        // half the MFMAs).  Columns per tile (32 NG): every tile pays one
+        // dependent score -> softmax -> projection chain, a cross-lane
+        // maximum and a barrier, so wider tiles win where the registers
+        // allow; measured at 65536^2 against 32 columns: plain BF16 128
+        // columns at D = 32 and 64 (-36 %, -24 %), 64 at D = 128 (-5 %);
+        // BF16X3 64 columns at D = 32 and 64 (-6 %, -1 %), 32 at D = 128
+        // (64 would take 1 wave per SIMD)
+        case 32: return x3 ? map_bf16_t<32, 2, 2, 2>(a, scale2, bscale, s) : map_bf16_t<32, 2, 1, 4>(a, scale2, bscale, s);
+        case 64: return x3 ? map_bf16_t<64, 2, 2, 2>(a, scale2, bscale, s) : map_bf16_t<64, 2, 1, 4>(a, scale2, bscale, s);
+        case 128: return x3 ? map_bf16_t<128, 2, 2, 1>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1, 2>(a, scale2, bscale, s);
         // D = 256: BF16X3 takes the wide kernel (12.6 ms instead of 21.5 at
         // 65536^2); plain BF16, whose projection is one FP16 product, the
         // narrow one (6.2 ms against 7.5 for the wide kernel)
         default:
             if (x3 && !a.out_sqn) return map_bf16_wide_t<256>(a, scale2, bscale, s);
-            return x3 ? map_bf16_t<256, 1, 2>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1>(a, scale2, bscale, s);
+            return x3 ? map_bf16_t<256, 1, 2, 1>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1, 1>(a, scale2, bscale, s);
     }
 }
 

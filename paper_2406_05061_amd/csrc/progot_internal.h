@@ -225,7 +225,7 @@ hipError_t launch_fp64_check_pcost(const float *X, int64_t n, const float *Y, in
 
 // BF16 forms (precision 1: one BF16 product; 2: hi/lo split, three products).
 int bf16_dim(int d);                 // padded dimension of the BF16 copies
-int64_t bf16_mpad(int64_t m);        // padded row count of the BF16 copies (multiple of 64)
+int64_t bf16_mpad(int64_t m);        // padded row count of the BF16 copies (multiple of 128)
 int lse_bf16_rows_per_block(int d, int precision);
 hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s);  // planned job
 hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s);

@@ -24,7 +24,7 @@
 //
 // Shadow layouts (device, written by bf16_split_rows / bf16_transpose, both
 // in the tile layout described below):
-//   rows:        [hi | lo], each np x D bf16, np = rows rounded up to 64,
+//   rows:        [hi | lo], each np x D bf16, np = rows rounded up to 128,
 //                D = padded dimension, zero padded
 //   transposed:  [hi | lo], each D x np bf16 in blocks of 32 columns: within
 //                a block, position k holds column perm32(k), the order in
@@ -176,8 +176,9 @@ template <int D, int NPART, int BN_ = lse_shape(D, NPART).bn> struct TileH {
 constexpr float kSumLo = 0x1p-64f, kSumHi = 0x1p64f;
 
 // Partial log-sum-exp over one column split (BF16 cross term).  Splits start
-// on multiples of 64 columns and the column copy is padded to 64 rows, so
-// every tile load is in bounds; columns past the split get beta = kNegBig.
+// on multiples of 64 columns and the column copy is padded to a multiple of
+// 128 rows, so every tile load is in bounds; columns past the split get
+// beta = kNegBig.
 //
 // Exponent shift: with shift_pot (an estimate of the rows' new potential,
 // scaled by shift_gamma: the previous iterate's, or a ProgOT step's warm
@@ -1000,6 +1001,9 @@ hipError_t map_bf16_wide_t(const MapArgs &a, float scale2, float bscale, hipStre
 template <int D, int QB, int NPART, int NG>
 hipError_t map_bf16_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     if (a.mp != bf16_mpad(a.m)) return hipErrorInvalidValue;
+    // every column tile the kernel reads must lie in the padded copies
+    constexpr int64_t BN = (int64_t)kMapBN * NG;
+    if ((a.m + BN - 1) / BN * BN > a.mp) return hipErrorInvalidValue;
     const int64_t tiles = (a.nq + 64 * QB - 1) / (64 * QB);
     if (NPART == 1 && !a.yt_unscale) return hipErrorInvalidValue;
     timed_launch(1, entropic_map_bf16<D, QB, NPART, NG>, dim3((unsigned)tiles), dim3(256), 0, s, a.Xq,
@@ -1017,7 +1021,10 @@ int bf16_dim(int d) {
     return 256;
 }
 
-int64_t bf16_mpad(int64_t m) { return (m + 63) / 64 * 64; }
+// Rows of the BF16 copies: a multiple of 128, so that every column tile the
+// kernels read (potential tiles of up to 64 columns from 64-column split
+// boundaries, map tiles of up to 128 columns from 0) lies in the copy.
+int64_t bf16_mpad(int64_t m) { return (m + 127) / 128 * 128; }
 
 // Rows per workgroup: 4 waves x QB x 16 (lse_shape).
 int lse_bf16_rows_per_block(int d, int precision) {

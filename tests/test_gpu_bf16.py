@@ -112,12 +112,19 @@ def test_progot_warm_start_shift(P, monkeypatch, prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
-@pytest.mark.parametrize("nq,m,d", [(300, 1000, 128), (333, 999, 200), (129, 1025, 256), (1, 33, 256)])
+@pytest.mark.parametrize("nq,m,d", [(300, 1000, 128), (333, 999, 200), (129, 1025, 256), (1, 33, 256),
+                                    # 128- and 64-column map tiles (d <= 64), the last one ragged
+                                    (257, 777, 20), (200, 1000, 64), (65, 130, 48)])
 def test_bf16_map_ragged(P, prec, nq, m, d):
     """Entropic map of both BF16 forms on ragged sizes (query blocks and the
-    last column tile partly filled; d = 200 pads to 256) against FP64, at a
-    converged target potential.  BF16X3 meets the 1e-3 map bar; plain BF16
-    (weights and cross term rounded once) is held to 5e-3."""
+    last column tile partly filled; d = 200 pads to 256, d = 20 and 48 to
+    32 and 64, where the tiles are 64 or 128 columns wide) against FP64, at
+    a converged target potential.  BF16X3 meets the 1e-3 map bar; plain BF16
+    (weights and cross term rounded once) is held to a sanity bound, 5e-3 at
+    d >= 128 and 1e-2 at d <= 64: there eps (mean cost/20) is small against
+    the clusters' internal spread, so a few columns carry each row's weight
+    and their ~2^-8 relative cross-term errors average out less (the same
+    error with 32-column tiles, 7.7e-3 at d = 20)."""
     X, Y = workloads.sphere(seed=400 + d, n=max(nq, 64), m=m, d=d, n_clusters=5)
     Q = X[:nq]
     eps = float(np.float32(oracle.mean_cost(X, Y) / 20.0))
@@ -130,7 +137,7 @@ def test_bf16_map_ragged(P, prec, nq, m, d):
         ref = oracle.entropic_map(Q, Y, g64, eps, alpha=alpha)
         e = map_err(out.cpu().numpy(), ref, Y)
         print(f"  alpha {alpha}: map err {e:.2e}", flush=True)
-        assert e < (1e-3 if prec == "bf16x3" else 5e-3)
+        assert e < (1e-3 if prec == "bf16x3" else 5e-3 if d > 64 else 1e-2)
 
 
 def test_precision_table(P):

@@ -252,9 +252,13 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[qb][sub][r]);
             const float mn = fmaxf(run_m[qb], mx);
-            float s4[4] = {0.f, 0.f, 0.f, 0.f};
+            // partial sums start at the first subtile's terms (an add to 0
+            // cannot be dropped by the compiler; the terms are never -0)
+            float s4[4];
 #pragma unroll
-            for (int sub = 0; sub < T::NSUB; ++sub)
+            for (int r = 0; r < 4; ++r) s4[r] = ex2(acc[qb][0][r] - mn);
+#pragma unroll
+            for (int sub = 1; sub < T::NSUB; ++sub)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) s4[r] += ex2(acc[qb][sub][r] - mn);
             run_s[qb] = fmaf(run_s[qb], ex2(run_m[qb] - mn), (s4[0] + s4[1]) + (s4[2] + s4[3]));

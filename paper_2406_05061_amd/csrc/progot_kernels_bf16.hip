@@ -50,6 +50,12 @@ namespace {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void *lds_ptr;
+// s_waitcnt operand (gfx9 encoding): vector memory count 0, the export and
+// LDS/scalar counts at their maxima, i.e. wait for every vector memory
+// operation of the wave, including loads into LDS
+constexpr int kWaitVmem = 0x0F70;
 
 __device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -662,215 +668,316 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     }
 }
 
-// Wide form of the map kernel, used for D = 256 in the BF16X3 form: a workgroup of 8 waves maps
-// 128 queries.  Wave w computes the scores and the softmax of query block w
-// (16 queries) against each 32-column tile, publishes its BF16 weights (and
-// their per-query rescale factors) in LDS, and after a barrier applies the
-// weights of all 8 blocks to its own D/8 output dimensions.  Per wave the
-// output accumulators hold 8 blocks x D/8 dimensions (64 VGPRs at D = 256
-// instead of 16 x D/4 x 4 = 256 for four blocks over all D), and each
-// transposed fragment is read by one wave instead of all of them.  Measured
-// at n = m = 65536: 12.6 ms instead of 21.5 at D = 256 (plain BF16 had 9.2
-// instead of 14.6 with BF16 projection weights; with FP16 ones the narrow
-// kernel is faster there); at D = 128 the two barriers per tile cost more
-// than they save (6.2 ms instead of 3.4), so D = 128 keeps the narrow kernel.
-// Arithmetic per pair is the same as in entropic_map_bf16 (same products,
-// normaliser and rescale rule), so the two agree to rounding order.
-template <int D>
-__global__ __launch_bounds__(512) void entropic_map_bf16_wide(
+// Warp-specialised form of the BF16X3 map kernel (D = 128 and 256).  A
+// workgroup of 8 waves maps 64 NQB queries in two roles that run one column
+// tile apart:
+//   score waves 0-3 each hold NQB blocks of 16 queries (hi/lo rows in
+//     registers) and, for tile t, compute the exponent-valued scores and the
+//     softmax (running maximum, BF16 hi/lo weights, normaliser), and publish
+//     the weights and rescale factors in LDS buffer t & 1;
+//   projection waves 4-7 each own D/4 output dimensions of every query and,
+//     in the same interval, apply the weights of tile t - 1 with their own
+//     fragments of the transposed copy (read from global memory into
+//     registers a tile ahead: each fragment is used by one wave only), and
+//     load tile t + 1's rows straight from global memory into LDS.
+// Waves w and w + 4 share a SIMD, so its matrix core is fed by one role while
+// the other runs its softmax or waits on memory; the score waves issue at a
+// raised priority so that their products, which the softmax waits for, go
+// first.  One barrier per tile orders the roles through the double buffers.
+// A score wave reads each tile fragment for NQB query blocks, and no wave
+// stages anything through registers.  The products, normaliser and rescale
+// rule are those of entropic_map_bf16, in one fixed order per accumulator.
+// Measured at n = m = 65536 against the previous kernels: D = 256 8.9-9.4 ms
+// instead of 12.5 (one role per wave, 16 queries per wave, 8 waves in
+// lockstep; same bits), D = 128 4.65 ms instead of 5.55 (the narrow kernel);
+// at D = 64 the narrow kernel with 64-column tiles stays faster (3.3 against
+// 3.6 ms).  Interval structure from per-wave clock stamps: the projection
+// waves are the critical path (products of both roles plus the softmax
+// issue on the SIMD), the score waves wait ~1200 cycles of ~4850 at the
+// barrier.
+template <int D, int NQB>
+__global__ __launch_bounds__(512) void entropic_map_bf16_ws(
     const float *Xq, int64_t nq, int d, const __bf16 *__restrict__ Ylp,
     const __bf16 *__restrict__ YTlp, int64_t m, int64_t mp, const float *__restrict__ ysq,
     const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout) {
     constexpr int NPART = 2;               // hi/lo split of rows and weights
     constexpr int BN = kMapBN;
     constexpr int KS = D / 32, C = D / 8;
-    constexpr int NW = 8;                  // waves = query blocks of 16
-    constexpr int ROWS = 16 * NW;
-    constexpr int NDBW = D / NW / 16;      // output dimension blocks per wave
+    constexpr int NSW = 4;                 // score waves; as many projection waves
+    constexpr int NQ = NSW * NQB;          // query blocks of 16 per workgroup
+    constexpr int ROWS = 16 * NQ;
+    constexpr int NDB = D / 16 / NSW;      // output dimension blocks per projection wave
     constexpr int NCH = BN * C;            // 16-byte chunks per part of a tile
-    constexpr int PER_T = NCH / 512;
-    static_assert(NDBW >= 1 && NCH % 512 == 0, "wide map needs D >= 128");
+    constexpr int PER_T = NCH / 256;       // of them per projection thread
+    static_assert(NDB >= 1 && NCH % 256 == 0, "projection waves need D >= 64");
     __shared__ __bf16 yr[2][NPART][BN * D];
-    __shared__ __bf16 ytr[2][2][D * BN];
     __shared__ float bt[2][BN];
-    __shared__ bf8 pw[NPART][NW][64];      // B operands (weights) of the 8 blocks
-    __shared__ float csw[NW][16];          // rescale factor of each query this tile
-    __shared__ int upw[NW];                // block w rescaled this tile
+    __shared__ bf8 pw[2][NPART][NQ][64];   // B operands (weights) of every block
+    __shared__ float csw[2][NQ][16];       // rescale factor of each query
+    __shared__ __align__(16) int upw[2][NQ];  // block rescaled this tile
     __shared__ float lw[ROWS];             // normalisers at the end
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lq = lane >> 4;
     const int64_t blk0 = (int64_t)blockIdx.x * ROWS;
-    const int64_t row = blk0 + wave * 16 + li;   // this lane's query in the score phase
-
-    bf8 ub[NPART][KS];
-    scaled_row_operand<D, NPART>(Xq, nq, d, row, lq, scale2, ub);
-    bf8 ones = bf8_zero();
-    if (li == 0) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
-    }
-
-    float m_used = kNegBig;
-    f4 on = {0.f, 0.f, 0.f, 0.f};
-    f4 o[NW][NDBW];
-#pragma unroll
-    for (int qb = 0; qb < NW; ++qb)
-#pragma unroll
-        for (int db = 0; db < NDBW; ++db) o[qb][db] = f4{0.f, 0.f, 0.f, 0.f};
-
     const int ntiles = (int)((m + BN - 1) / BN);
-    u4 pre[NPART][PER_T], pret[2][PER_T];
-    float bpre = 0.f;
-    auto fetch = [&](int t) {
-        const int64_t j0 = (int64_t)t * BN;
-#pragma unroll
-        for (int r = 0; r < PER_T; ++r) {
-            const int c = tid + 512 * r;
-#pragma unroll
-            for (int p = 0; p < NPART; ++p)
-                pre[p][r] = *reinterpret_cast<const u4 *>(Ylp + (p * mp + j0) * D + c * 8);
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-                pret[p][r] = *reinterpret_cast<const u4 *>(YTlp + (p * mp + j0) * D + c * 8);
-        }
-        if (tid < BN) {
-            const int64_t j = j0 + tid;
-            bpre = j < m ? (g[j] - ysq[j]) * bscale : kNegBig;
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int r = 0; r < PER_T; ++r) {
-            const int c = tid + 512 * r;
-#pragma unroll
-            for (int p = 0; p < NPART; ++p) *reinterpret_cast<u4 *>(&yr[buf][p][c * 8]) = pre[p][r];
-#pragma unroll
-            for (int p = 0; p < 2; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
-        }
-        if (tid < BN) bt[buf][tid] = bpre;
-    };
+    const bool score_role = wave < NSW;
+    const int rw = score_role ? wave : wave - NSW;
 
-    if (ntiles > 0) {
-        fetch(0);
-        store(0);
-    }
-    __syncthreads();
-
-    for (int t = 0; t < ntiles; ++t) {
-        const int buf = t & 1;
-        const bool more = t + 1 < ntiles;
-        if (more) fetch(t + 1);
-        // scores of this wave's block, exponent-valued (bias as the initial value)
-        f4 acc[2];
+    if (score_role) {
+        const int wave = rw;
+        __builtin_amdgcn_s_setprio(1);    // 1-3 % over equal priority
+        bf8 ub[NQB][NPART][KS];
 #pragma unroll
-        for (int sub = 0; sub < 2; ++sub) acc[sub] = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
-        bf8 a[2][NPART][2];
-        auto read_a = [&](int s, bf8 (&dst)[NPART][2]) {
+        for (int b = 0; b < NQB; ++b)
+            scaled_row_operand<D, NPART>(Xq, nq, d, blk0 + (wave * NQB + b) * 16 + li, lq, scale2, ub[b]);
+        bf8 ones = bf8_zero();
+        if (li == 0) {
 #pragma unroll
-            for (int p = 0; p < NPART; ++p)
+            for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
+        }
+        float m_used[NQB];
+        f4 on[NQB];
 #pragma unroll
-                for (int sub = 0; sub < 2; ++sub)
-                    dst[p][sub] = *reinterpret_cast<const bf8 *>(
-                        &yr[buf][p][tile_chunk(sub, C, lq * KS + s, li) * 8]);
+        for (int b = 0; b < NQB; ++b) {
+            m_used[b] = kNegBig;
+            on[b] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+        __syncthreads();                   // tile 0 staged
+        for (int t = 0; t < ntiles; ++t) {
+            {
+                const int buf = t & 1;
+                f4 acc[NQB][2];
+#pragma unroll
+                for (int sub = 0; sub < 2; ++sub) {
+                    const f4 bias = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
+#pragma unroll
+                    for (int b = 0; b < NQB; ++b) acc[b][sub] = bias;
+                }
+                bf8 a[2][NPART][2];
+                auto read_a = [&](int s, bf8 (&dst)[NPART][2]) {
+#pragma unroll
+                    for (int p = 0; p < NPART; ++p)
+#pragma unroll
+                        for (int sub = 0; sub < 2; ++sub)
+                            dst[p][sub] = *reinterpret_cast<const bf8 *>(
+                                &yr[buf][p][tile_chunk(sub, C, lq * KS + s, li) * 8]);
+                };
+                read_a(0, a[0]);
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    if (s + 1 < KS) read_a(s + 1, a[(s + 1) & 1]);
+                    const int cs = s & 1;
+#pragma unroll
+                    for (int b = 0; b < NQB; ++b)
+#pragma unroll
+                        for (int sub = 0; sub < 2; ++sub) acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][0][s], acc[b][sub]);
+#pragma unroll
+                    for (int b = 0; b < NQB; ++b)
+#pragma unroll
+                        for (int sub = 0; sub < 2; ++sub) acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][1][s], acc[b][sub]);
+#pragma unroll
+                    for (int b = 0; b < NQB; ++b)
+#pragma unroll
+                        for (int sub = 0; sub < 2; ++sub) acc[b][sub] = mfma_bf(a[cs][1][sub], ub[b][0][s], acc[b][sub]);
+                }
+#pragma unroll
+                for (int b = 0; b < NQB; ++b) {
+                    const int qb = wave * NQB + b;
+                    float mx = kNegBig;
+#pragma unroll
+                    for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[b][sub][r]);
+                    mx = max_lane_groups(mx);
+                    const bool up = mx > m_used[b] + kLazy;
+                    const bool any = __builtin_amdgcn_ballot_w64(up) != 0;
+                    float csf = 1.f;
+                    if (any) {
+                        const float mn = up ? mx : m_used[b];
+                        csf = ex2(m_used[b] - mn);
+                        m_used[b] = mn;
+                        on[b] *= csf;
+                    }
+                    bf8 pb, pl;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float v = ex2(acc[b][e >> 2][e & 3] - m_used[b]);
+                        const __bf16 h = (__bf16)v;
+                        pb[e] = h;
+                        pl[e] = (__bf16)(v - (float)h);
+                    }
+                    on[b] = mfma_bf(ones, pb, on[b]);
+                    on[b] = mfma_bf(ones, pl, on[b]);
+                    pw[buf][0][qb][lane] = pb;
+                    pw[buf][1][qb][lane] = pl;
+                    if (lq == 0) csw[buf][qb][li] = csf;
+                    if (lane == 0) upw[buf][qb] = any;
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();                   // the interval that applies the last tile's weights
+        // normalisers: output row 0 of each block's ones product
+#pragma unroll
+        for (int b = 0; b < NQB; ++b)
+            if (lq == 0) lw[(wave * NQB + b) * 16 + li] = on[b][0];
+        __syncthreads();
+    } else {
+        const int pv = __builtin_amdgcn_readfirstlane(rw);  // dimension blocks pv NDB .. + NDB - 1
+        const int pt = pv * 64 + lane;     // loader thread 0..255
+        // global addresses: a wave-uniform base (scalar registers) plus one
+        // per-lane byte offset shared by every part
+        const char *const yrow = reinterpret_cast<const char *>(Ylp);
+        const char *const ycol = reinterpret_cast<const char *>(YTlp);
+        const uint32_t loff = (uint32_t)lane * 16u;
+        f4 o[NQ][NDB];
+#pragma unroll
+        for (int qb = 0; qb < NQ; ++qb)
+#pragma unroll
+            for (int db = 0; db < NDB; ++db) o[qb][db] = f4{0.f, 0.f, 0.f, 0.f};
+        constexpr int NLD = NPART * PER_T;  // row chunks per loader thread and tile
+        // rows of tile t straight from global memory into LDS buffer buf:
+        // lane l of a wave writes its 16 bytes at the wave's base + 16 l, so
+        // thread pt's chunk pt + 256 r lands at its place in the tile layout
+        auto load_rows_part = [&](int t, int buf, int k) {
+            const int p = k % NPART, r = k / NPART;
+            const char *base = yrow + ((p * mp + (int64_t)t * BN) * D + (256 * r + 64 * pv) * 8) * 2;
+            __builtin_amdgcn_global_load_lds(
+                (const void *)(base + loff), (lds_ptr)&yr[buf][p][(256 * r + 64 * pv) * 8], 16, 0, 0);
         };
-        read_a(0, a[0]);
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            if (s + 1 < KS) read_a(s + 1, a[(s + 1) & 1]);
-            const int cs = s & 1;
-#pragma unroll
-            for (int sub = 0; sub < 2; ++sub) acc[sub] = mfma_bf(a[cs][0][sub], ub[0][s], acc[sub]);
-            if constexpr (NPART == 2) {
-#pragma unroll
-                for (int sub = 0; sub < 2; ++sub) acc[sub] = mfma_bf(a[cs][0][sub], ub[1][s], acc[sub]);
-#pragma unroll
-                for (int sub = 0; sub < 2; ++sub) acc[sub] = mfma_bf(a[cs][1][sub], ub[0][s], acc[sub]);
+        // column biases of the next tile: loaded at the start of an interval,
+        // combined and stored at its end (index clamped into the cloud, the
+        // value replaced for columns past m)
+        int64_t jb = 0;
+        float gpre = 0.f, ypre = 0.f;
+        auto fetch_bias = [&](int t) {
+            jb = (int64_t)t * BN + pt;
+            if (pt < BN) {
+                const int64_t jc = jb < m ? jb : m - 1;
+                gpre = g[jc];
+                ypre = ysq[jc];
             }
-        }
-        // softmax of the block: running maximum, weights, rescale factor
-        float mx = kNegBig;
+        };
+        auto store_bias = [&](int buf) {
+            if (pt < BN) bt[buf][pt] = jb < m ? (gpre - ypre) * bscale : kNegBig;
+        };
+        // this wave's fragments of the transposed tile (hi, lo): 1 KiB each,
+        // contiguous in the tile layout; two sets, one in use and one loading
+        bf8 yv[2][NDB], yw[2][NDB];
+        auto load_yv_part = [&](int t, bf8 (&dst)[2][NDB], int k) {
+            const int p2 = k / NDB, db = k % NDB;
+            const char *base = ycol + ((p2 * mp + (int64_t)t * BN) * D + (pv * NDB + db) * 64 * 8) * 2;
+            dst[p2][db] = *reinterpret_cast<const bf8 *>(base + loff);
+        };
+        // tile indices below clamp to the last tile (m >= 1): its repeated
+        // loads land where nothing reads them again
+        const int last = ntiles - 1;
 #pragma unroll
-        for (int sub = 0; sub < 2; ++sub)
+        for (int k = 0; k < NLD; ++k) load_rows_part(0, 0, k);
+        fetch_bias(0);
+        store_bias(0);
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
+        __syncthreads();                   // tile 0 staged
+        // Interval t: tile t's fragments (into ynew) and tile t + 1's column
+        // biases load first, then the projection of tile t - 1 with the
+        // fragments in yold, with the loads of tile t + 1's rows into LDS
+        // buffer (t + 1) & 1 issued between the products of the first query
+        // blocks: the copies run while the matrix cores work, and every load
+        // of the wave must be complete at the barrier that ends the interval.
+        auto body = [&](int t, bf8 (&ynew)[2][NDB], bf8 (&yold)[2][NDB]) {
+            const int tn = min(t, last), tr = min(t + 1, last), sb = (t + 1) & 1;
+            fetch_bias(tr);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[sub][r]);
-        mx = max_lane_groups(mx);
-        const bool up = mx > m_used + kLazy;
-        const bool any = __builtin_amdgcn_ballot_w64(up) != 0;
-        float csf = 1.f;
-        if (any) {
-            const float mn = up ? mx : m_used;
-            csf = ex2(m_used - mn);
-            m_used = mn;
-            on *= csf;
-        }
-        bf8 pb, pl;
+            for (int k = 0; k < 2 * NDB; ++k) load_yv_part(tn, ynew, k);
+            {
+                // O^T[this wave's dims] += Y^T P^T for the weights of tile t - 1
+                const int buf = (t - 1) & 1;
+                // the rescale flags of all blocks in one LDS round trip
+                int mask = 0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float v = ex2(acc[e >> 2][e & 3] - m_used);
-            const __bf16 h = (__bf16)v;
-            pb[e] = h;
-            pl[e] = (__bf16)(v - (float)h);
-        }
-        on = mfma_bf(ones, pb, on);
-        on = mfma_bf(ones, pl, on);
-        pw[0][wave][lane] = pb;
-        pw[1][wave][lane] = pl;
-        if (lq == 0) csw[wave][li] = csf;
-        if (lane == 0) upw[wave] = any;
+                for (int k = 0; k < NQ / 4; ++k) {
+                    const i4 f = *reinterpret_cast<const i4 *>(&upw[buf][4 * k]);
+                    mask |= (f[0] << (4 * k)) | (f[1] << (4 * k + 1)) | (f[2] << (4 * k + 2)) |
+                            (f[3] << (4 * k + 3));
+                }
+                mask = __builtin_amdgcn_readfirstlane(mask);
+                if (mask) {
+                    // one branch for all blocks (a factor of 1 leaves a block's
+                    // sums unchanged): per-block branches made the compiler
+                    // copy the accumulators at every join
+#pragma unroll
+                    for (int qb = 0; qb < NQ; ++qb) {
+                        const float c = ((mask >> qb) & 1) ? csw[buf][qb][li] : 1.f;
+#pragma unroll
+                        for (int db = 0; db < NDB; ++db) o[qb][db] *= c;
+                    }
+                }
+                // weights read one block ahead; the scheduling barrier at the
+                // end of each block keeps the compiler from hoisting every
+                // block's reads (64 more registers) above the products
+                bf8 ph = pw[buf][0][0][lane], pl = pw[buf][1][0][lane];
+#pragma unroll
+                for (int qb = 0; qb < NQ; ++qb) {
+                    bf8 phn = ph, pln = pl;
+                    if (qb + 1 < NQ) {
+                        phn = pw[buf][0][qb + 1][lane];
+                        pln = pw[buf][1][qb + 1][lane];
+                    }
+#pragma unroll
+                    for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[0][db], ph, o[qb][db]);
+#pragma unroll
+                    for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[1][db], ph, o[qb][db]);
+                    // the lo weights against the hi copy: the third product of the split
+#pragma unroll
+                    for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[0][db], pl, o[qb][db]);
+                    // the rows go out over the first blocks
+                    if (2 * qb < NLD) load_rows_part(tr, sb, 2 * qb);
+                    if (2 * qb + 1 < NLD) load_rows_part(tr, sb, 2 * qb + 1);
+                    ph = phn;
+                    pl = pln;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int k = 2 * NQ; k < NLD; ++k) load_rows_part(tr, sb, k);
+            }
+            store_bias(sb);
+            // the rows must be in LDS before the score waves pass the barrier
+            __builtin_amdgcn_s_waitcnt(kWaitVmem);
+            __syncthreads();
+        };
+        // interval 0 stages only (tile 1's rows, tile 0's fragments); the
+        // loop runs whole pairs, so no branch in it joins the accumulators
+        fetch_bias(min(1, last));
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) load_rows_part(min(1, last), 1, k);
+#pragma unroll
+        for (int k = 0; k < 2 * NDB; ++k) load_yv_part(0, yv, k);
+        store_bias(1);
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
         __syncthreads();
-        // O^T[this wave's dims] += Y^T P^T over the 8 blocks
-#pragma unroll
-        for (int qb = 0; qb < NW; ++qb) {
-            if (upw[qb]) {
-                const float c = csw[qb][li];
-#pragma unroll
-                for (int db = 0; db < NDBW; ++db) o[qb][db] *= c;
-            }
+        int t = 1;
+        for (; t + 1 <= ntiles; t += 2) {
+            body(t, yw, yv);
+            body(t + 1, yv, yw);
         }
-        bf8 pq[NW];
+        if (t <= ntiles) body(t, yw, yv);
+        __syncthreads();                   // normalisers written
 #pragma unroll
-        for (int qb = 0; qb < NW; ++qb) pq[qb] = pw[0][qb][lane];
+        for (int qb = 0; qb < NQ; ++qb) {
+            const int64_t r = blk0 + qb * 16 + li;
+            if (r >= nq) continue;
+            const float inv = 1.f / lw[qb * 16 + li];
 #pragma unroll
-        for (int p2 = 0; p2 < 2; ++p2)
+            for (int db = 0; db < NDB; ++db) {
+                const int f0 = (pv * NDB + db) * 16 + 4 * lq;
 #pragma unroll
-            for (int db = 0; db < NDBW; ++db) {
-                const bf8 av = *reinterpret_cast<const bf8 *>(
-                    &ytr[buf][p2][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]);
-#pragma unroll
-                for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_bf(av, pq[qb], o[qb][db]);
-            }
-        // the lo weights against the hi copy: the third product of the split
-#pragma unroll
-        for (int qb = 0; qb < NW; ++qb) pq[qb] = pw[1][qb][lane];
-#pragma unroll
-        for (int db = 0; db < NDBW; ++db) {
-            const bf8 av = *reinterpret_cast<const bf8 *>(
-                &ytr[buf][0][tile_chunk(wave * NDBW + db, 4, lq, li) * 8]);
-#pragma unroll
-            for (int qb = 0; qb < NW; ++qb) o[qb][db] = mfma_bf(av, pq[qb], o[qb][db]);
-        }
-        if (more) store(buf ^ 1);
-        __syncthreads();
-    }
-
-    // normalisers (output row 0 of each block's ones product), then the step
-    if (lq == 0) lw[wave * 16 + li] = on[0];
-    __syncthreads();
-#pragma unroll
-    for (int qb = 0; qb < NW; ++qb) {
-        const int64_t r = blk0 + qb * 16 + li;
-        if (r >= nq) continue;
-        const float inv = 1.f / lw[qb * 16 + li];
-#pragma unroll
-        for (int db = 0; db < NDBW; ++db) {
-            const int f0 = (wave * NDBW + db) * 16 + 4 * lq;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (f0 + e < d) {
-                    const float xo = Xq[r * d + f0 + e];
-                    Xout[r * d + f0 + e] = (1.f - alpha) * xo + alpha * (o[qb][db][e] * inv);
+                for (int e = 0; e < 4; ++e) {
+                    if (f0 + e < d) {
+                        const float xo = Xq[r * d + f0 + e];
+                        Xout[r * d + f0 + e] = (1.f - alpha) * xo + alpha * (o[qb][db][e] * inv);
+                    }
                 }
             }
         }
@@ -994,11 +1101,12 @@ hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int D>
-hipError_t map_bf16_wide_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
-    if (a.mp != bf16_mpad(a.m) || a.out_sqn) return hipErrorInvalidValue;
-    const int64_t tiles = (a.nq + 127) / 128;
-    timed_launch(1, entropic_map_bf16_wide<D>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
+template <int D, int NQB>
+hipError_t map_bf16_ws_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
+    if (a.m < 1 || a.mp != bf16_mpad(a.m) || a.out_sqn) return hipErrorInvalidValue;
+    constexpr int ROWS = 64 * NQB;
+    const int64_t tiles = (a.nq + ROWS - 1) / ROWS;
+    timed_launch(1, entropic_map_bf16_ws<D, NQB>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
                  a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
                  scale2, bscale, a.alpha, a.Xout);
     return hipGetLastError();
@@ -1049,6 +1157,11 @@ hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s) {
 
 hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     const bool x3 = a.precision == 2;
+    // BF16X3 at D = 128 and 256 without the squared-norm output: the
+    // warp-specialised kernel (4.65 ms instead of 5.55 at D = 128, 8.9-9.4
+    // ms instead of 12.5 at D = 256, 65536^2)
+    if (x3 && !a.out_sqn && bf16_dim(a.d) == 128) return map_bf16_ws_t<128, 4>(a, scale2, bscale, s);
+    if (x3 && !a.out_sqn && bf16_dim(a.d) == 256) return map_bf16_ws_t<256, 2>(a, scale2, bscale, s);
     switch (bf16_dim(a.d)) {
         // two 16-row blocks per wave up to D = 128: four at D = 32 and 64
         // measured 23-27 % slower (two waves per SIMD instead of three or
@@ -1063,12 +1176,9 @@ hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStre
         case 32: return x3 ? map_bf16_t<32, 2, 2, 2>(a, scale2, bscale, s) : map_bf16_t<32, 2, 1, 4>(a, scale2, bscale, s);
         case 64: return x3 ? map_bf16_t<64, 2, 2, 2>(a, scale2, bscale, s) : map_bf16_t<64, 2, 1, 4>(a, scale2, bscale, s);
         case 128: return x3 ? map_bf16_t<128, 2, 2, 1>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1, 2>(a, scale2, bscale, s);
-        // D = 256: BF16X3 takes the wide kernel (12.6 ms instead of 21.5 at
-        // 65536^2); plain BF16, whose projection is one FP16 product, the
-        // narrow one (6.2 ms against 7.5 for the wide kernel)
-        default:
-            if (x3 && !a.out_sqn) return map_bf16_wide_t<256>(a, scale2, bscale, s);
-            return x3 ? map_bf16_t<256, 1, 2, 1>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1, 1>(a, scale2, bscale, s);
+        // plain BF16, whose projection is one FP16 product, keeps the narrow
+        // kernel at D = 256 (6.2 ms at 65536^2)
+        default: return x3 ? map_bf16_t<256, 1, 2, 1>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1, 1>(a, scale2, bscale, s);
     }
 }
 

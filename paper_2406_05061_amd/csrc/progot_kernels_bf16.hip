@@ -668,13 +668,14 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     }
 }
 
-// Warp-specialised form of the BF16X3 map kernel (D = 128 and 256).  A
-// workgroup of 8 waves maps 64 NQB queries in two roles that run one column
-// tile apart:
-//   score waves 0-3 each hold NQB blocks of 16 queries (hi/lo rows in
-//     registers) and, for tile t, compute the exponent-valued scores and the
-//     softmax (running maximum, BF16 hi/lo weights, normaliser), and publish
-//     the weights and rescale factors in LDS buffer t & 1;
+// Warp-specialised form of the map kernel (BF16X3 at D = 128 and 256, plain
+// BF16 at D = 256).  A workgroup of 8 waves maps 64 NQB queries in two roles
+// that run one column tile apart:
+//   score waves 0-3 each hold NQB blocks of 16 queries (rows in registers,
+//     hi/lo for BF16X3) and, for tile t, compute the exponent-valued scores
+//     and the softmax (running maximum, weights -- BF16 hi/lo, or FP16 for
+//     plain BF16 -- and normaliser), and publish the weights and rescale
+//     factors in LDS buffer t & 1;
 //   projection waves 4-7 each own D/4 output dimensions of every query and,
 //     in the same interval, apply the weights of tile t - 1 with their own
 //     fragments of the transposed copy (read from global memory into
@@ -687,20 +688,22 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 // A score wave reads each tile fragment for NQB query blocks, and no wave
 // stages anything through registers.  The products, normaliser and rescale
 // rule are those of entropic_map_bf16, in one fixed order per accumulator.
-// Measured at n = m = 65536 against the previous kernels: D = 256 8.9-9.4 ms
-// instead of 12.5 (one role per wave, 16 queries per wave, 8 waves in
-// lockstep; same bits), D = 128 4.65 ms instead of 5.55 (the narrow kernel);
-// at D = 64 the narrow kernel with 64-column tiles stays faster (3.3 against
-// 3.6 ms).  Interval structure from per-wave clock stamps: the projection
-// waves are the critical path (products of both roles plus the softmax
-// issue on the SIMD), the score waves wait ~1200 cycles of ~4850 at the
-// barrier.
-template <int D, int NQB>
+// Measured at n = m = 65536 against the previous kernels: BF16X3 D = 256
+// 8.9-9.4 ms instead of 12.5 (one role per wave, 16 queries per wave, 8
+// waves in lockstep; same bits), D = 128 4.65-4.8 ms instead of 5.45-5.55
+// (the narrow kernel); plain BF16 D = 256 3.8 ms instead of 5.8 (the narrow
+// kernel, same bits); at D = 64 (BF16X3) and D = 128 (plain) the narrow
+// kernel with 64-column tiles is as fast or faster.  Interval structure of
+// BF16X3 at D = 256 from per-wave clock stamps: the projection waves are the
+// critical path (products of both roles plus the softmax issue on the
+// SIMD), the score waves wait ~1200 cycles of ~4850 at the barrier.
+template <int D, int NQB, int NPART>
 __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
     const float *Xq, int64_t nq, int d, const __bf16 *__restrict__ Ylp,
     const __bf16 *__restrict__ YTlp, int64_t m, int64_t mp, const float *__restrict__ ysq,
-    const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout) {
-    constexpr int NPART = 2;               // hi/lo split of rows and weights
+    const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout,
+    const float *__restrict__ yt_unscale) {
+    constexpr int NYT = NPART == 2 ? 2 : 1;  // parts of the transposed copy (FP16: one)
     constexpr int BN = kMapBN;
     constexpr int KS = D / 32, C = D / 8;
     constexpr int NSW = 4;                 // score waves; as many projection waves
@@ -733,9 +736,13 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
         for (int b = 0; b < NQB; ++b)
             scaled_row_operand<D, NPART>(Xq, nq, d, blk0 + (wave * NQB + b) * 16 + li, lq, scale2, ub[b]);
         bf8 ones = bf8_zero();
+        h8 ones16 = as_h8(bf8_zero());
         if (li == 0) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.f;
+            for (int e = 0; e < 8; ++e) {
+                ones[e] = (__bf16)1.f;
+                ones16[e] = (_Float16)1.f;
+            }
         }
         float m_used[NQB];
         f4 on[NQB];
@@ -773,14 +780,18 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
                     for (int b = 0; b < NQB; ++b)
 #pragma unroll
                         for (int sub = 0; sub < 2; ++sub) acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][0][s], acc[b][sub]);
+                    if constexpr (NPART == 2) {
 #pragma unroll
-                    for (int b = 0; b < NQB; ++b)
+                        for (int b = 0; b < NQB; ++b)
 #pragma unroll
-                        for (int sub = 0; sub < 2; ++sub) acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][1][s], acc[b][sub]);
+                            for (int sub = 0; sub < 2; ++sub)
+                                acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][1][s], acc[b][sub]);
 #pragma unroll
-                    for (int b = 0; b < NQB; ++b)
+                        for (int b = 0; b < NQB; ++b)
 #pragma unroll
-                        for (int sub = 0; sub < 2; ++sub) acc[b][sub] = mfma_bf(a[cs][1][sub], ub[b][0][s], acc[b][sub]);
+                            for (int sub = 0; sub < 2; ++sub)
+                                acc[b][sub] = mfma_bf(a[cs][1][sub], ub[b][0][s], acc[b][sub]);
+                    }
                 }
 #pragma unroll
                 for (int b = 0; b < NQB; ++b) {
@@ -800,18 +811,26 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
                         m_used[b] = mn;
                         on[b] *= csf;
                     }
-                    bf8 pb, pl;
+                    if constexpr (NPART == 1) {
+                        // FP16 weights scaled by 2^kF16Shift (normaliser alike)
+                        const f4 pair[2] = {acc[b][0], acc[b][1]};
+                        const h8 p16 = weights_f16(pair, m_used[b] - kF16Shift);
+                        on[b] = mfma_h(ones16, p16, on[b]);
+                        pw[buf][0][qb][lane] = __builtin_bit_cast(bf8, p16);
+                    } else {
+                        bf8 pb, pl;
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const float v = ex2(acc[b][e >> 2][e & 3] - m_used[b]);
-                        const __bf16 h = (__bf16)v;
-                        pb[e] = h;
-                        pl[e] = (__bf16)(v - (float)h);
+                        for (int e = 0; e < 8; ++e) {
+                            const float v = ex2(acc[b][e >> 2][e & 3] - m_used[b]);
+                            const __bf16 h = (__bf16)v;
+                            pb[e] = h;
+                            pl[e] = (__bf16)(v - (float)h);
+                        }
+                        on[b] = mfma_bf(ones, pb, on[b]);
+                        on[b] = mfma_bf(ones, pl, on[b]);
+                        pw[buf][0][qb][lane] = pb;
+                        pw[buf][1][qb][lane] = pl;
                     }
-                    on[b] = mfma_bf(ones, pb, on[b]);
-                    on[b] = mfma_bf(ones, pl, on[b]);
-                    pw[buf][0][qb][lane] = pb;
-                    pw[buf][1][qb][lane] = pl;
                     if (lq == 0) csw[buf][qb][li] = csf;
                     if (lane == 0) upw[buf][qb] = any;
                 }
@@ -863,10 +882,11 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
         auto store_bias = [&](int buf) {
             if (pt < BN) bt[buf][pt] = jb < m ? (gpre - ypre) * bscale : kNegBig;
         };
-        // this wave's fragments of the transposed tile (hi, lo): 1 KiB each,
-        // contiguous in the tile layout; two sets, one in use and one loading
-        bf8 yv[2][NDB], yw[2][NDB];
-        auto load_yv_part = [&](int t, bf8 (&dst)[2][NDB], int k) {
+        // this wave's fragments of the transposed tile (hi, lo; or the one
+        // FP16 part): 1 KiB each, contiguous in the tile layout; two sets, one
+        // in use and one loading
+        bf8 yv[NYT][NDB], yw[NYT][NDB];
+        auto load_yv_part = [&](int t, bf8 (&dst)[NYT][NDB], int k) {
             const int p2 = k / NDB, db = k % NDB;
             const char *base = ycol + ((p2 * mp + (int64_t)t * BN) * D + (pv * NDB + db) * 64 * 8) * 2;
             dst[p2][db] = *reinterpret_cast<const bf8 *>(base + loff);
@@ -886,11 +906,11 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
         // buffer (t + 1) & 1 issued between the products of the first query
         // blocks: the copies run while the matrix cores work, and every load
         // of the wave must be complete at the barrier that ends the interval.
-        auto body = [&](int t, bf8 (&ynew)[2][NDB], bf8 (&yold)[2][NDB]) {
+        auto body = [&](int t, bf8 (&ynew)[NYT][NDB], bf8 (&yold)[NYT][NDB]) {
             const int tn = min(t, last), tr = min(t + 1, last), sb = (t + 1) & 1;
             fetch_bias(tr);
 #pragma unroll
-            for (int k = 0; k < 2 * NDB; ++k) load_yv_part(tn, ynew, k);
+            for (int k = 0; k < NYT * NDB; ++k) load_yv_part(tn, ynew, k);
             {
                 // O^T[this wave's dims] += Y^T P^T for the weights of tile t - 1
                 const int buf = (t - 1) & 1;
@@ -917,21 +937,28 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
                 // weights read one block ahead; the scheduling barrier at the
                 // end of each block keeps the compiler from hoisting every
                 // block's reads (64 more registers) above the products
-                bf8 ph = pw[buf][0][0][lane], pl = pw[buf][1][0][lane];
+                bf8 ph = pw[buf][0][0][lane], pl = pw[buf][NPART - 1][0][lane];
 #pragma unroll
                 for (int qb = 0; qb < NQ; ++qb) {
                     bf8 phn = ph, pln = pl;
                     if (qb + 1 < NQ) {
                         phn = pw[buf][0][qb + 1][lane];
-                        pln = pw[buf][1][qb + 1][lane];
+                        if (NPART == 2) pln = pw[buf][1][qb + 1][lane];
                     }
+                    if constexpr (NPART == 1) {
+                        // one FP16 product against the scaled FP16 copy
 #pragma unroll
-                    for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[0][db], ph, o[qb][db]);
+                        for (int db = 0; db < NDB; ++db)
+                            o[qb][db] = mfma_h(as_h8(yold[0][db]), as_h8(ph), o[qb][db]);
+                    } else {
 #pragma unroll
-                    for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[1][db], ph, o[qb][db]);
-                    // the lo weights against the hi copy: the third product of the split
+                        for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[0][db], ph, o[qb][db]);
 #pragma unroll
-                    for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[0][db], pl, o[qb][db]);
+                        for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[1][db], ph, o[qb][db]);
+                        // the lo weights against the hi copy: the third product of the split
+#pragma unroll
+                        for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[0][db], pl, o[qb][db]);
+                    }
                     // the rows go out over the first blocks
                     if (2 * qb < NLD) load_rows_part(tr, sb, 2 * qb);
                     if (2 * qb + 1 < NLD) load_rows_part(tr, sb, 2 * qb + 1);
@@ -953,7 +980,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
 #pragma unroll
         for (int k = 0; k < NLD; ++k) load_rows_part(min(1, last), 1, k);
 #pragma unroll
-        for (int k = 0; k < 2 * NDB; ++k) load_yv_part(0, yv, k);
+        for (int k = 0; k < NYT * NDB; ++k) load_yv_part(0, yv, k);
         store_bias(1);
         __builtin_amdgcn_s_waitcnt(kWaitVmem);
         __syncthreads();
@@ -968,7 +995,8 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
         for (int qb = 0; qb < NQ; ++qb) {
             const int64_t r = blk0 + qb * 16 + li;
             if (r >= nq) continue;
-            const float inv = 1.f / lw[qb * 16 + li];
+            // the FP16 copy holds Y scaled by a power of two: undo it exactly
+            const float inv = (NPART == 1 ? *yt_unscale : 1.f) / lw[qb * 16 + li];
 #pragma unroll
             for (int db = 0; db < NDB; ++db) {
                 const int f0 = (pv * NDB + db) * 16 + 4 * lq;
@@ -1101,14 +1129,15 @@ hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int D, int NQB>
+template <int D, int NQB, int NPART>
 hipError_t map_bf16_ws_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
-    if (a.m < 1 || a.mp != bf16_mpad(a.m) || a.out_sqn) return hipErrorInvalidValue;
+    if (a.m < 1 || a.mp != bf16_mpad(a.m) || a.out_sqn || (NPART == 1 && !a.yt_unscale))
+        return hipErrorInvalidValue;
     constexpr int ROWS = 64 * NQB;
     const int64_t tiles = (a.nq + ROWS - 1) / ROWS;
-    timed_launch(1, entropic_map_bf16_ws<D, NQB>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
+    timed_launch(1, entropic_map_bf16_ws<D, NQB, NPART>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
                  a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
-                 scale2, bscale, a.alpha, a.Xout);
+                 scale2, bscale, a.alpha, a.Xout, a.yt_unscale);
     return hipGetLastError();
 }
 
@@ -1157,11 +1186,14 @@ hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s) {
 
 hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     const bool x3 = a.precision == 2;
-    // BF16X3 at D = 128 and 256 without the squared-norm output: the
-    // warp-specialised kernel (4.65 ms instead of 5.55 at D = 128, 8.9-9.4
-    // ms instead of 12.5 at D = 256, 65536^2)
-    if (x3 && !a.out_sqn && bf16_dim(a.d) == 128) return map_bf16_ws_t<128, 4>(a, scale2, bscale, s);
-    if (x3 && !a.out_sqn && bf16_dim(a.d) == 256) return map_bf16_ws_t<256, 2>(a, scale2, bscale, s);
+    // without the squared-norm output, the warp-specialised kernel for
+    // BF16X3 at D = 128 and 256 (4.65-4.8 ms instead of 5.45-5.55 at D = 128,
+    // 8.9-9.4 ms instead of 12.5 at D = 256, 65536^2) and plain BF16 at D =
+    // 256 (3.8 ms instead of 5.8, same bits); plain BF16 at D = 128 keeps the
+    // narrow kernel's 64-column tiles (within run-to-run noise of it)
+    if (x3 && !a.out_sqn && bf16_dim(a.d) == 128) return map_bf16_ws_t<128, 4, 2>(a, scale2, bscale, s);
+    if (!a.out_sqn && bf16_dim(a.d) == 256)
+        return x3 ? map_bf16_ws_t<256, 2, 2>(a, scale2, bscale, s) : map_bf16_ws_t<256, 2, 1>(a, scale2, bscale, s);
     switch (bf16_dim(a.d)) {
         // two 16-row blocks per wave up to D = 128: four at D = 32 and 64
         // measured 23-27 % slower (two waves per SIMD instead of three or
@@ -1176,8 +1208,6 @@ hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStre
         case 32: return x3 ? map_bf16_t<32, 2, 2, 2>(a, scale2, bscale, s) : map_bf16_t<32, 2, 1, 4>(a, scale2, bscale, s);
         case 64: return x3 ? map_bf16_t<64, 2, 2, 2>(a, scale2, bscale, s) : map_bf16_t<64, 2, 1, 4>(a, scale2, bscale, s);
         case 128: return x3 ? map_bf16_t<128, 2, 2, 1>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1, 2>(a, scale2, bscale, s);
-        // plain BF16, whose projection is one FP16 product, keeps the narrow
-        // kernel at D = 256 (6.2 ms at 65536^2)
         default: return x3 ? map_bf16_t<256, 1, 2, 1>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1, 1>(a, scale2, bscale, s);
     }
 }

@@ -290,13 +290,31 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
     }
 }
 
-// One job; consecutive blocks take consecutive splits (block b runs on XCD
-// b mod 8, so with S = 8 each XCD streams one eighth of the columns).
+// One job.  Block b runs on XCD b mod 8, and each XCD's L2 fetches the rows
+// and columns its blocks touch.  When the grid divides evenly (an even
+// number of row tiles, S a multiple of 4), XCD x takes the row tiles of half
+// x / 4 and the splits of quarter x % 4, row tile major: its L2 streams half
+// the rows and a quarter of the columns.  Otherwise block b takes row tile
+// b / S and split b mod S, which with S a multiple of 8 gives each XCD every
+// row tile and an eighth of the columns (at n = m, 4.5 instead of 3 eighths
+// of both clouds per XCD).  Either way each (row tile, split) pair is one
+// block, so the partials are the same.
 template <int D, int QB>
 __global__ __launch_bounds__(256) void lse_partial_f32(LseJob J) {
     __shared__ float vt[2][LseTile<D>::FLOATS];
     __shared__ float bt[2][LseTile<D>::BN];
-    lse_partial_body<D, QB>(J, blockIdx.x / J.S, blockIdx.x % J.S, vt, bt);
+    const int64_t b = blockIdx.x, tiles = J.blocks / J.S;
+    int64_t rt;
+    int split;
+    if (tiles % 2 == 0 && J.S % 4 == 0) {
+        const int64_t x = b % 8, i = b / 8, sq = J.S / 4;
+        rt = (x / 4) * (tiles / 2) + i / sq;
+        split = (int)((x % 4) * sq + i % sq);
+    } else {
+        rt = b / J.S;
+        split = (int)(b % J.S);
+    }
+    lse_partial_body<D, QB>(J, rt, split, vt, bt);
 }
 
 // Persistent grouped kernels.  A grouped launch covers the work list of many
@@ -812,9 +830,11 @@ void plan_lse_job(LseJob &j) {
     // keeping >= one LDS column tile per split in FP32 (64 columns; small
     // problems such as the 1024-point grid solves of the eps-scheduler need
     // the splits to fill the chip) and >= 256 columns in BF16.  S is a power
-    // of two, so with S >= 8 the blocks an XCD receives (block b goes to XCD
-    // b mod 8, split b mod S) stream a fixed subset of the column splits
-    // through that XCD's L2.
+    // of two, so from S = 4 on (with an even number of row tiles) the FP32
+    // kernel can hand each XCD half of the row tiles and a quarter of the
+    // splits, and from S = 8 on the BF16 blocks an XCD receives (block b goes
+    // to XCD b mod 8, split b mod S) stream a fixed subset of the column
+    // splits through that XCD's L2.
     const int64_t target = j.precision == 0 ? kSplitTargetF32 : kSplitTargetBf16;
     int64_t S = tiles >= target ? 1 : (target + tiles - 1) / tiles;
     const int64_t min_cols = j.precision == 0 ? 64 : 256;

@@ -157,7 +157,10 @@ __device__ __forceinline__ int tile_chunk(int blk16, int C, int c, int li) {
 // (BF16X3), 2 % at D = 64 (BF16).  BF16X3 at D = 256 keeps QB = 2 (its row
 // operand alone would take 256 registers at QB = 4); D = 32 keeps 64-column
 // tiles (a tile must be whole loader rounds); QB = 8 at D = 64 would halve
-// the waves per SIMD.
+// the waves per SIMD.  BF16 at D = 256 runs two waves per SIMD (241
+// registers); QB = 3 there (187 registers, or 168 with 3 waves per SIMD and
+// a small spill) measured 21 % and 14 % slower at 65536^2: the fragment
+// reuse counts for more than the occupancy.
 struct LseShape { int qb, bn; };
 constexpr LseShape lse_shape(int D, int npart) {
     return (D >= 64 && D * npart <= 256) ? LseShape{4, 32} : LseShape{2, D * npart >= 512 ? 32 : 64};

@@ -671,9 +671,10 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     }
 }
 
-// Warp-specialised form of the map kernel (BF16X3 at D = 128 and 256, plain
-// BF16 at D = 256).  A workgroup of 8 waves maps 64 NQB queries in two roles
-// that run one column tile apart:
+// Warp-specialised form of the map kernel (D = 128 and 256).  A workgroup of
+// 8 waves maps 64 NQB queries in two roles that run one column tile apart
+// (NG groups of 32 columns: one for BF16X3, two for plain BF16, whose
+// one-product tiles leave the fixed costs of an interval a larger share):
 //   score waves 0-3 each hold NQB blocks of 16 queries (rows in registers,
 //     hi/lo for BF16X3) and, for tile t, compute the exponent-valued scores
 //     and the softmax (running maximum, weights -- BF16 hi/lo, or FP16 for
@@ -694,20 +695,24 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
 // Measured at n = m = 65536 against the previous kernels: BF16X3 D = 256
 // 8.9-9.4 ms instead of 12.5 (one role per wave, 16 queries per wave, 8
 // waves in lockstep; same bits), D = 128 4.65-4.8 ms instead of 5.45-5.55
-// (the narrow kernel); plain BF16 D = 256 3.8 ms instead of 5.8 (the narrow
-// kernel, same bits); at D = 64 (BF16X3) and D = 128 (plain) the narrow
-// kernel with 64-column tiles is as fast or faster.  Interval structure of
+// (the narrow kernel); plain BF16 D = 256 3.5 ms instead of 5.8 (the narrow
+// kernel; 3.7-3.9 ms, and its bits, with 32-column tiles), D = 128 1.95-2.0
+// ms instead of 2.26-2.49 (the narrow kernel with the same 64-column tiles,
+// same bits); at D = 64 (BF16X3) the narrow kernel with 64-column tiles
+// stays faster.  Interval structure of
 // BF16X3 at D = 256 from per-wave clock stamps: the projection waves are the
 // critical path (products of both roles plus the softmax issue on the
 // SIMD), the score waves wait ~1200 cycles of ~4850 at the barrier.
-template <int D, int NQB, int NPART>
+template <int D, int NQB, int NPART, int NG>
 __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
     const float *Xq, int64_t nq, int d, const __bf16 *__restrict__ Ylp,
     const __bf16 *__restrict__ YTlp, int64_t m, int64_t mp, const float *__restrict__ ysq,
     const float *__restrict__ g, float scale2, float bscale, float alpha, float *Xout,
     const float *__restrict__ yt_unscale) {
-    constexpr int NYT = NPART == 2 ? 2 : 1;  // parts of the transposed copy (FP16: one)
-    constexpr int BN = kMapBN;
+    static_assert(NPART == 1 || NG == 1, "BF16X3 tiles are one group of 32 columns");
+    constexpr int BN = kMapBN * NG;        // NG groups of 32 columns per tile
+    constexpr int NS = 2 * NG;             // 16-column score subtiles
+    constexpr int NYG = NPART == 2 ? 2 : NG;  // transposed fragments per dims block: parts or groups
     constexpr int KS = D / 32, C = D / 8;
     constexpr int NSW = 4;                 // score waves; as many projection waves
     constexpr int NQ = NSW * NQB;          // query blocks of 16 per workgroup
@@ -718,7 +723,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
     static_assert(NDB >= 1 && NCH % 256 == 0, "projection waves need D >= 64");
     __shared__ __bf16 yr[2][NPART][BN * D];
     __shared__ float bt[2][BN];
-    __shared__ bf8 pw[2][NPART][NQ][64];   // B operands (weights) of every block
+    __shared__ bf8 pw[2][NPART * NG][NQ][64];  // weights of every block (hi/lo, or per group)
     __shared__ float csw[2][NQ][16];       // rescale factor of each query
     __shared__ __align__(16) int upw[2][NQ];  // block rescaled this tile
     __shared__ float lw[ROWS];             // normalisers at the end
@@ -758,19 +763,19 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
         for (int t = 0; t < ntiles; ++t) {
             {
                 const int buf = t & 1;
-                f4 acc[NQB][2];
+                f4 acc[NQB][NS];
 #pragma unroll
-                for (int sub = 0; sub < 2; ++sub) {
+                for (int sub = 0; sub < NS; ++sub) {
                     const f4 bias = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
                     for (int b = 0; b < NQB; ++b) acc[b][sub] = bias;
                 }
-                bf8 a[2][NPART][2];
-                auto read_a = [&](int s, bf8 (&dst)[NPART][2]) {
+                bf8 a[2][NPART][NS];
+                auto read_a = [&](int s, bf8 (&dst)[NPART][NS]) {
 #pragma unroll
                     for (int p = 0; p < NPART; ++p)
 #pragma unroll
-                        for (int sub = 0; sub < 2; ++sub)
+                        for (int sub = 0; sub < NS; ++sub)
                             dst[p][sub] = *reinterpret_cast<const bf8 *>(
                                 &yr[buf][p][tile_chunk(sub, C, lq * KS + s, li) * 8]);
                 };
@@ -782,7 +787,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
 #pragma unroll
                     for (int b = 0; b < NQB; ++b)
 #pragma unroll
-                        for (int sub = 0; sub < 2; ++sub) acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][0][s], acc[b][sub]);
+                        for (int sub = 0; sub < NS; ++sub) acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][0][s], acc[b][sub]);
                     if constexpr (NPART == 2) {
 #pragma unroll
                         for (int b = 0; b < NQB; ++b)
@@ -801,7 +806,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
                     const int qb = wave * NQB + b;
                     float mx = kNegBig;
 #pragma unroll
-                    for (int sub = 0; sub < 2; ++sub)
+                    for (int sub = 0; sub < NS; ++sub)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[b][sub][r]);
                     mx = max_lane_groups(mx);
@@ -815,11 +820,15 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
                         on[b] *= csf;
                     }
                     if constexpr (NPART == 1) {
-                        // FP16 weights scaled by 2^kF16Shift (normaliser alike)
-                        const f4 pair[2] = {acc[b][0], acc[b][1]};
-                        const h8 p16 = weights_f16(pair, m_used[b] - kF16Shift);
-                        on[b] = mfma_h(ones16, p16, on[b]);
-                        pw[buf][0][qb][lane] = __builtin_bit_cast(bf8, p16);
+                        // FP16 weights scaled by 2^kF16Shift (normaliser alike),
+                        // one B operand per group of 32 columns
+#pragma unroll
+                        for (int g2 = 0; g2 < NG; ++g2) {
+                            const f4 pair[2] = {acc[b][2 * g2], acc[b][2 * g2 + 1]};
+                            const h8 p16 = weights_f16(pair, m_used[b] - kF16Shift);
+                            on[b] = mfma_h(ones16, p16, on[b]);
+                            pw[buf][g2][qb][lane] = __builtin_bit_cast(bf8, p16);
+                        }
                     } else {
                         bf8 pb, pl;
 #pragma unroll
@@ -885,13 +894,15 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
         auto store_bias = [&](int buf) {
             if (pt < BN) bt[buf][pt] = jb < m ? (gpre - ypre) * bscale : kNegBig;
         };
-        // this wave's fragments of the transposed tile (hi, lo; or the one
-        // FP16 part): 1 KiB each, contiguous in the tile layout; two sets, one
-        // in use and one loading
-        bf8 yv[NYT][NDB], yw[NYT][NDB];
-        auto load_yv_part = [&](int t, bf8 (&dst)[NYT][NDB], int k) {
+        // this wave's fragments of the transposed tile (hi and lo parts of
+        // its one group, or the one FP16 part of each group): 1 KiB each,
+        // contiguous in the tile layout; two sets, one in use and one loading
+        bf8 yv[NYG][NDB], yw[NYG][NDB];
+        auto load_yv_part = [&](int t, bf8 (&dst)[NYG][NDB], int k) {
             const int p2 = k / NDB, db = k % NDB;
-            const char *base = ycol + ((p2 * mp + (int64_t)t * BN) * D + (pv * NDB + db) * 64 * 8) * 2;
+            const int part = NPART == 2 ? p2 : 0, grp = NPART == 2 ? 0 : p2;
+            const char *base =
+                ycol + ((part * mp + (int64_t)t * BN + grp * kMapBN) * D + (pv * NDB + db) * 64 * 8) * 2;
             dst[p2][db] = *reinterpret_cast<const bf8 *>(base + loff);
         };
         // tile indices below clamp to the last tile (m >= 1): its repeated
@@ -909,11 +920,11 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
         // buffer (t + 1) & 1 issued between the products of the first query
         // blocks: the copies run while the matrix cores work, and every load
         // of the wave must be complete at the barrier that ends the interval.
-        auto body = [&](int t, bf8 (&ynew)[NYT][NDB], bf8 (&yold)[NYT][NDB]) {
+        auto body = [&](int t, bf8 (&ynew)[NYG][NDB], bf8 (&yold)[NYG][NDB]) {
             const int tn = min(t, last), tr = min(t + 1, last), sb = (t + 1) & 1;
             fetch_bias(tr);
 #pragma unroll
-            for (int k = 0; k < NYT * NDB; ++k) load_yv_part(tn, ynew, k);
+            for (int k = 0; k < NYG * NDB; ++k) load_yv_part(tn, ynew, k);
             {
                 // O^T[this wave's dims] += Y^T P^T for the weights of tile t - 1
                 const int buf = (t - 1) & 1;
@@ -940,19 +951,25 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
                 // weights read one block ahead; the scheduling barrier at the
                 // end of each block keeps the compiler from hoisting every
                 // block's reads (64 more registers) above the products
-                bf8 ph = pw[buf][0][0][lane], pl = pw[buf][NPART - 1][0][lane];
+                // ph, pl: the hi and lo weights (BF16X3) or those of groups 0, 1
+                bf8 ph = pw[buf][0][0][lane], pl = pw[buf][NPART * NG - 1][0][lane];
 #pragma unroll
                 for (int qb = 0; qb < NQ; ++qb) {
                     bf8 phn = ph, pln = pl;
                     if (qb + 1 < NQ) {
                         phn = pw[buf][0][qb + 1][lane];
-                        if (NPART == 2) pln = pw[buf][1][qb + 1][lane];
+                        if (NPART * NG == 2) pln = pw[buf][1][qb + 1][lane];
                     }
                     if constexpr (NPART == 1) {
                         // one FP16 product against the scaled FP16 copy
 #pragma unroll
                         for (int db = 0; db < NDB; ++db)
                             o[qb][db] = mfma_h(as_h8(yold[0][db]), as_h8(ph), o[qb][db]);
+                        if constexpr (NG == 2) {
+#pragma unroll
+                            for (int db = 0; db < NDB; ++db)
+                                o[qb][db] = mfma_h(as_h8(yold[1][db]), as_h8(pl), o[qb][db]);
+                        }
                     } else {
 #pragma unroll
                         for (int db = 0; db < NDB; ++db) o[qb][db] = mfma_bf(yold[0][db], ph, o[qb][db]);
@@ -983,7 +1000,7 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
 #pragma unroll
         for (int k = 0; k < NLD; ++k) load_rows_part(min(1, last), 1, k);
 #pragma unroll
-        for (int k = 0; k < NYT * NDB; ++k) load_yv_part(0, yv, k);
+        for (int k = 0; k < NYG * NDB; ++k) load_yv_part(0, yv, k);
         store_bias(1);
         __builtin_amdgcn_s_waitcnt(kWaitVmem);
         __syncthreads();
@@ -1132,13 +1149,16 @@ hipError_t lse_bf16_t(const LseJob &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int D, int NQB, int NPART>
+template <int D, int NQB, int NPART, int NG = 1>
 hipError_t map_bf16_ws_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     if (a.m < 1 || a.mp != bf16_mpad(a.m) || a.out_sqn || (NPART == 1 && !a.yt_unscale))
         return hipErrorInvalidValue;
+    // every column tile the kernel reads must lie in the padded copies
+    constexpr int64_t BN = (int64_t)kMapBN * NG;
+    if ((a.m + BN - 1) / BN * BN > a.mp) return hipErrorInvalidValue;
     constexpr int ROWS = 64 * NQB;
     const int64_t tiles = (a.nq + ROWS - 1) / ROWS;
-    timed_launch(1, entropic_map_bf16_ws<D, NQB, NPART>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
+    timed_launch(1, entropic_map_bf16_ws<D, NQB, NPART, NG>, dim3((unsigned)tiles), dim3(512), 0, s, a.Xq,
                  a.nq, a.d, (const __bf16 *)a.Y_lp, (const __bf16 *)a.YT_lp, a.m, a.mp, a.ysq, a.g,
                  scale2, bscale, a.alpha, a.Xout, a.yt_unscale);
     return hipGetLastError();
@@ -1189,14 +1209,16 @@ hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s) {
 
 hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     const bool x3 = a.precision == 2;
-    // without the squared-norm output, the warp-specialised kernel for
-    // BF16X3 at D = 128 and 256 (4.65-4.8 ms instead of 5.45-5.55 at D = 128,
-    // 8.9-9.4 ms instead of 12.5 at D = 256, 65536^2) and plain BF16 at D =
-    // 256 (3.8 ms instead of 5.8, same bits); plain BF16 at D = 128 keeps the
-    // narrow kernel's 64-column tiles (within run-to-run noise of it)
-    if (x3 && !a.out_sqn && bf16_dim(a.d) == 128) return map_bf16_ws_t<128, 4, 2>(a, scale2, bscale, s);
+    // without the squared-norm output, the warp-specialised kernel at D = 128
+    // and 256, 65536^2: BF16X3 4.65-4.8 ms instead of 5.45-5.55 at D = 128,
+    // 8.9-9.4 ms instead of 12.5 at D = 256; plain BF16 with 64-column tiles
+    // 1.95-2.0 ms instead of 2.26-2.49 at D = 128 (the narrow kernel's
+    // 64-column tiles, same bits) and 3.5 ms instead of 5.8 at D = 256 (3.7-3.9
+    // with 32-column tiles)
+    if (!a.out_sqn && bf16_dim(a.d) == 128)
+        return x3 ? map_bf16_ws_t<128, 4, 2>(a, scale2, bscale, s) : map_bf16_ws_t<128, 4, 1, 2>(a, scale2, bscale, s);
     if (!a.out_sqn && bf16_dim(a.d) == 256)
-        return x3 ? map_bf16_ws_t<256, 2, 2>(a, scale2, bscale, s) : map_bf16_ws_t<256, 2, 1>(a, scale2, bscale, s);
+        return x3 ? map_bf16_ws_t<256, 2, 2>(a, scale2, bscale, s) : map_bf16_ws_t<256, 2, 1, 2>(a, scale2, bscale, s);
     switch (bf16_dim(a.d)) {
         // two 16-row blocks per wave up to D = 128: four at D = 32 and 64
         // measured 23-27 % slower (two waves per SIMD instead of three or

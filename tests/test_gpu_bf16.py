@@ -140,20 +140,23 @@ def test_bf16_map_ragged(P, prec, nq, m, d):
         assert e < (1e-3 if prec == "bf16x3" else 5e-3 if d > 64 else 1e-2)
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
 @pytest.mark.parametrize("nq,m,d", [(257, 1, 128), (7, 1, 256), (100, 65, 100), (300, 65, 256),
-                                    (129, 33, 128), (513, 97, 200)])
-def test_bf16x3_map_tile_counts(P, nq, m, d):
-    """The BF16X3 map at d = 128 and 256 runs the weights of column tile t one
-    interval after its scores, in pairs of intervals with one left over for
-    an odd tile count: one tile (m = 1, the left-over interval alone), two
-    (a pair), three (a pair and the left-over one), on ragged query counts.
+                                    (129, 33, 128), (513, 97, 200), (70, 129, 128), (33, 200, 256)])
+def test_map_tile_counts(P, prec, nq, m, d):
+    """The BF16 maps at d = 128 and 256 (warp-specialised) run the weights of
+    column tile t one interval after its scores, in pairs of intervals with
+    one left over for an odd tile count: one tile (m = 1, the left-over
+    interval alone), two (a pair), three (a pair and the left-over one), on
+    ragged query counts; tiles are 32 columns (BF16X3) or 64 (plain BF16).
     For m = 1 the map is the single target point whatever the potential, so
-    that case takes a zero potential instead of a solve."""
+    that case takes a zero potential instead of a solve.  Bars as in
+    test_bf16_map_ragged."""
     X, Y = workloads.sphere(seed=500 + d + m, n=max(nq, 64), m=m, d=d, n_clusters=3)
     Q = X[:nq]
     eps = float(np.float32(max(oracle.mean_cost(X, Y), 1e-3) / 20.0))
-    print(f"case bf16x3 map nq={nq} m={m} d={d}", flush=True)
-    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision="bf16x3")
+    print(f"case {prec} map nq={nq} m={m} d={d}", flush=True)
+    cl = P.prepare_clouds(P.to_device(X), P.to_device(Y), precision=prec)
     if m == 1:
         g = torch.zeros(1, dtype=torch.float32, device="cuda")
     else:
@@ -164,7 +167,7 @@ def test_bf16x3_map_tile_counts(P, nq, m, d):
         ref = oracle.entropic_map(Q, Y, g64, eps, alpha=alpha)
         e = map_err(out.cpu().numpy(), ref, Y)
         print(f"  alpha {alpha}: map err {e:.2e}", flush=True)
-        assert e < 1e-3
+        assert e < (1e-3 if prec == "bf16x3" else 5e-3)
 
 
 def test_precision_table(P):

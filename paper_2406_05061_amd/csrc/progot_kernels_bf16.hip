@@ -95,6 +95,26 @@ __device__ __forceinline__ h8 weights_f16(const f4 (&acc)[2], float shift) {
 
 __device__ __forceinline__ h8 as_h8(bf8 x) { return __builtin_bit_cast(h8, x); }
 
+// The BF16X3 weights of 8 values: hi = v rounded to BF16, lo = v - hi
+// rounded to BF16, as B operands.  One packed conversion rounds two values;
+// the hi halves come back to FP32 by a shift and a mask, so each value is
+// rounded once per part.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split_weights(const float (&v)[8], bf8 &hi, bf8 &lo) {
+    u4 h, l;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const f2v x = {v[2 * q], v[2 * q + 1]};
+        const unsigned hb = __builtin_bit_cast(unsigned, __builtin_convertvector(x, b2v));
+        const f2v xh = {__builtin_bit_cast(float, hb << 16), __builtin_bit_cast(float, hb & 0xFFFF0000u)};
+        h[q] = hb;
+        l[q] = __builtin_bit_cast(unsigned, __builtin_convertvector(x - xh, b2v));
+    }
+    hi = __builtin_bit_cast(bf8, h);
+    lo = __builtin_bit_cast(bf8, l);
+}
+
 // Keeps an operand computed before the tile loop in its registers: without
 // this the compiler re-derives the BF16 row operands from the FP32 rows in
 // every iteration (a v_mul and a v_cvt_pk per element).
@@ -589,13 +609,10 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
                 if constexpr (NPART == 1) {
                     p16[qb][g2] = weights_f16(pair, m_used[qb] - kF16Shift);
                 } else {
+                    float v[8];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const float v = ex2(pair[e >> 2][e & 3] - m_used[qb]);
-                        const __bf16 h = (__bf16)v;
-                        pb[qb][g2][e] = h;
-                        pl[qb][g2][e] = (__bf16)(v - (float)h);
-                    }
+                    for (int e = 0; e < 8; ++e) v[e] = ex2(pair[e >> 2][e & 3] - m_used[qb]);
+                    split_weights(v, pb[qb][g2], pl[qb][g2]);
                 }
             }
         }
@@ -830,14 +847,11 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
                             pw[buf][g2][qb][lane] = __builtin_bit_cast(bf8, p16);
                         }
                     } else {
-                        bf8 pb, pl;
+                        float v[8];
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const float v = ex2(acc[b][e >> 2][e & 3] - m_used[b]);
-                            const __bf16 h = (__bf16)v;
-                            pb[e] = h;
-                            pl[e] = (__bf16)(v - (float)h);
-                        }
+                        for (int e = 0; e < 8; ++e) v[e] = ex2(acc[b][e >> 2][e & 3] - m_used[b]);
+                        bf8 pb, pl;
+                        split_weights(v, pb, pl);
                         on[b] = mfma_bf(ones, pb, on[b]);
                         on[b] = mfma_bf(ones, pl, on[b]);
                         pw[buf][0][qb][lane] = pb;

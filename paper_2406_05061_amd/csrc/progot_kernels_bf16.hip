@@ -1223,31 +1223,25 @@ hipError_t launch_lse_partial_bf16(const LseJob &a, hipStream_t s) {
 
 hipError_t launch_map_bf16(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     const bool x3 = a.precision == 2;
-    // without the squared-norm output, the warp-specialised kernel at D = 128
-    // and 256, 65536^2: BF16X3 4.65-4.8 ms instead of 5.45-5.55 at D = 128,
-    // 8.9-9.4 ms instead of 12.5 at D = 256; plain BF16 with 64-column tiles
-    // 1.95-2.0 ms instead of 2.26-2.49 at D = 128 (the narrow kernel's
-    // 64-column tiles, same bits) and 3.5 ms instead of 5.8 at D = 256 (3.7-3.9
-    // with 32-column tiles)
-    if (!a.out_sqn && bf16_dim(a.d) == 128)
-        return x3 ? map_bf16_ws_t<128, 4, 2>(a, scale2, bscale, s) : map_bf16_ws_t<128, 4, 1, 2>(a, scale2, bscale, s);
-    if (!a.out_sqn && bf16_dim(a.d) == 256)
-        return x3 ? map_bf16_ws_t<256, 2, 2>(a, scale2, bscale, s) : map_bf16_ws_t<256, 2, 1, 2>(a, scale2, bscale, s);
     switch (bf16_dim(a.d)) {
-        // two 16-row blocks per wave up to D = 128: four at D = 32 and 64
-        // measured 23-27 % slower (two waves per SIMD instead of three or
-        // four), one at D = 128 35-53 % slower (each LDS fragment then feeds
-        // half the MFMAs).  Columns per tile (32 NG): every tile pays one
-        // dependent score -> softmax -> projection chain, a cross-lane
-        // maximum and a barrier, so wider tiles win where the registers
-        // allow; measured at 65536^2 against 32 columns: plain BF16 128
-        // columns at D = 32 and 64 (-36 %, -24 %), 64 at D = 128 (-5 %);
-        // BF16X3 64 columns at D = 32 and 64 (-6 %, -1 %), 32 at D = 128
-        // (64 would take 1 wave per SIMD)
+        // D <= 64: the narrow kernel, two 16-row blocks per wave (four
+        // measured 23-27 % slower: two waves per SIMD instead of three or
+        // four).  Columns per tile (32 NG): every tile pays one dependent
+        // score -> softmax -> projection chain, a cross-lane maximum and a
+        // barrier, so wider tiles win where the registers allow; measured at
+        // 65536^2 against 32 columns: plain BF16 128 columns (-36 % at D = 32,
+        // -24 % at D = 64), BF16X3 64 (-6 %, -1 %)
         case 32: return x3 ? map_bf16_t<32, 2, 2, 2>(a, scale2, bscale, s) : map_bf16_t<32, 2, 1, 4>(a, scale2, bscale, s);
         case 64: return x3 ? map_bf16_t<64, 2, 2, 2>(a, scale2, bscale, s) : map_bf16_t<64, 2, 1, 4>(a, scale2, bscale, s);
-        case 128: return x3 ? map_bf16_t<128, 2, 2, 1>(a, scale2, bscale, s) : map_bf16_t<128, 2, 1, 2>(a, scale2, bscale, s);
-        default: return x3 ? map_bf16_t<256, 1, 2, 1>(a, scale2, bscale, s) : map_bf16_t<256, 1, 1, 1>(a, scale2, bscale, s);
+        // D = 128 and 256: the warp-specialised kernel (it writes no
+        // |Xout_i|^2, which the library asks of the FP32 maps only), 65536^2:
+        // BF16X3 4.65-4.8 ms instead of 5.45-5.55 for the narrow kernel at
+        // D = 128, 8.9-9.4 ms instead of 12.5 for the previous D = 256 kernel;
+        // plain BF16 with 64-column tiles 1.95-2.0 ms instead of 2.26-2.49 at
+        // D = 128 (the narrow kernel's 64-column tiles, same bits) and 3.5 ms
+        // instead of 5.8 at D = 256 (3.7-3.9 with 32-column tiles)
+        case 128: return x3 ? map_bf16_ws_t<128, 4, 2>(a, scale2, bscale, s) : map_bf16_ws_t<128, 4, 1, 2>(a, scale2, bscale, s);
+        default: return x3 ? map_bf16_ws_t<256, 2, 2>(a, scale2, bscale, s) : map_bf16_ws_t<256, 2, 1, 2>(a, scale2, bscale, s);
     }
 }
 

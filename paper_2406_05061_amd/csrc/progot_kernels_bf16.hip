@@ -778,88 +778,86 @@ __global__ __launch_bounds__(512) void entropic_map_bf16_ws(
         }
         __syncthreads();                   // tile 0 staged
         for (int t = 0; t < ntiles; ++t) {
-            {
-                const int buf = t & 1;
-                f4 acc[NQB][NS];
+            const int buf = t & 1;
+            f4 acc[NQB][NS];
 #pragma unroll
-                for (int sub = 0; sub < NS; ++sub) {
-                    const f4 bias = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
+            for (int sub = 0; sub < NS; ++sub) {
+                const f4 bias = *reinterpret_cast<const f4 *>(&bt[buf][sub * 16 + lq * 4]);
 #pragma unroll
-                    for (int b = 0; b < NQB; ++b) acc[b][sub] = bias;
-                }
-                bf8 a[2][NPART][NS];
-                auto read_a = [&](int s, bf8 (&dst)[NPART][NS]) {
+                for (int b = 0; b < NQB; ++b) acc[b][sub] = bias;
+            }
+            bf8 a[2][NPART][NS];
+            auto read_a = [&](int s, bf8 (&dst)[NPART][NS]) {
 #pragma unroll
-                    for (int p = 0; p < NPART; ++p)
+                for (int p = 0; p < NPART; ++p)
 #pragma unroll
-                        for (int sub = 0; sub < NS; ++sub)
-                            dst[p][sub] = *reinterpret_cast<const bf8 *>(
-                                &yr[buf][p][tile_chunk(sub, C, lq * KS + s, li) * 8]);
-                };
-                read_a(0, a[0]);
+                    for (int sub = 0; sub < NS; ++sub)
+                        dst[p][sub] = *reinterpret_cast<const bf8 *>(
+                            &yr[buf][p][tile_chunk(sub, C, lq * KS + s, li) * 8]);
+            };
+            read_a(0, a[0]);
 #pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    if (s + 1 < KS) read_a(s + 1, a[(s + 1) & 1]);
-                    const int cs = s & 1;
+            for (int s = 0; s < KS; ++s) {
+                if (s + 1 < KS) read_a(s + 1, a[(s + 1) & 1]);
+                const int cs = s & 1;
+#pragma unroll
+                for (int b = 0; b < NQB; ++b)
+#pragma unroll
+                    for (int sub = 0; sub < NS; ++sub) acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][0][s], acc[b][sub]);
+                if constexpr (NPART == 2) {
 #pragma unroll
                     for (int b = 0; b < NQB; ++b)
 #pragma unroll
-                        for (int sub = 0; sub < NS; ++sub) acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][0][s], acc[b][sub]);
-                    if constexpr (NPART == 2) {
+                        for (int sub = 0; sub < 2; ++sub)
+                            acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][1][s], acc[b][sub]);
 #pragma unroll
-                        for (int b = 0; b < NQB; ++b)
+                    for (int b = 0; b < NQB; ++b)
 #pragma unroll
-                            for (int sub = 0; sub < 2; ++sub)
-                                acc[b][sub] = mfma_bf(a[cs][0][sub], ub[b][1][s], acc[b][sub]);
-#pragma unroll
-                        for (int b = 0; b < NQB; ++b)
-#pragma unroll
-                            for (int sub = 0; sub < 2; ++sub)
-                                acc[b][sub] = mfma_bf(a[cs][1][sub], ub[b][0][s], acc[b][sub]);
-                    }
+                        for (int sub = 0; sub < 2; ++sub)
+                            acc[b][sub] = mfma_bf(a[cs][1][sub], ub[b][0][s], acc[b][sub]);
                 }
+            }
 #pragma unroll
-                for (int b = 0; b < NQB; ++b) {
-                    const int qb = wave * NQB + b;
-                    float mx = kNegBig;
+            for (int b = 0; b < NQB; ++b) {
+                const int qb = wave * NQB + b;
+                float mx = kNegBig;
 #pragma unroll
-                    for (int sub = 0; sub < NS; ++sub)
+                for (int sub = 0; sub < NS; ++sub)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[b][sub][r]);
-                    mx = max_lane_groups(mx);
-                    const bool up = mx > m_used[b] + kLazy;
-                    const bool any = __builtin_amdgcn_ballot_w64(up) != 0;
-                    float csf = 1.f;
-                    if (any) {
-                        const float mn = up ? mx : m_used[b];
-                        csf = ex2(m_used[b] - mn);
-                        m_used[b] = mn;
-                        on[b] *= csf;
-                    }
-                    if constexpr (NPART == 1) {
-                        // FP16 weights scaled by 2^kF16Shift (normaliser alike),
-                        // one B operand per group of 32 columns
-#pragma unroll
-                        for (int g2 = 0; g2 < NG; ++g2) {
-                            const f4 pair[2] = {acc[b][2 * g2], acc[b][2 * g2 + 1]};
-                            const h8 p16 = weights_f16(pair, m_used[b] - kF16Shift);
-                            on[b] = mfma_h(ones16, p16, on[b]);
-                            pw[buf][g2][qb][lane] = __builtin_bit_cast(bf8, p16);
-                        }
-                    } else {
-                        float v[8];
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) v[e] = ex2(acc[b][e >> 2][e & 3] - m_used[b]);
-                        bf8 pb, pl;
-                        split_weights(v, pb, pl);
-                        on[b] = mfma_bf(ones, pb, on[b]);
-                        on[b] = mfma_bf(ones, pl, on[b]);
-                        pw[buf][0][qb][lane] = pb;
-                        pw[buf][1][qb][lane] = pl;
-                    }
-                    if (lq == 0) csw[buf][qb][li] = csf;
-                    if (lane == 0) upw[buf][qb] = any;
+                    for (int r = 0; r < 4; ++r) mx = fmaxf(mx, acc[b][sub][r]);
+                mx = max_lane_groups(mx);
+                const bool up = mx > m_used[b] + kLazy;
+                const bool any = __builtin_amdgcn_ballot_w64(up) != 0;
+                float csf = 1.f;
+                if (any) {
+                    const float mn = up ? mx : m_used[b];
+                    csf = ex2(m_used[b] - mn);
+                    m_used[b] = mn;
+                    on[b] *= csf;
                 }
+                if constexpr (NPART == 1) {
+                    // FP16 weights scaled by 2^kF16Shift (normaliser alike),
+                    // one B operand per group of 32 columns
+#pragma unroll
+                    for (int g2 = 0; g2 < NG; ++g2) {
+                        const f4 pair[2] = {acc[b][2 * g2], acc[b][2 * g2 + 1]};
+                        const h8 p16 = weights_f16(pair, m_used[b] - kF16Shift);
+                        on[b] = mfma_h(ones16, p16, on[b]);
+                        pw[buf][g2][qb][lane] = __builtin_bit_cast(bf8, p16);
+                    }
+                } else {
+                    float v[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) v[e] = ex2(acc[b][e >> 2][e & 3] - m_used[b]);
+                    bf8 pb, pl;
+                    split_weights(v, pb, pl);
+                    on[b] = mfma_bf(ones, pb, on[b]);
+                    on[b] = mfma_bf(ones, pl, on[b]);
+                    pw[buf][0][qb][lane] = pb;
+                    pw[buf][1][qb][lane] = pl;
+                }
+                if (lq == 0) csw[buf][qb][li] = csf;
+                if (lane == 0) upw[buf][qb] = any;
             }
             __syncthreads();
         }

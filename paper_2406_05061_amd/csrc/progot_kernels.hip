@@ -805,7 +805,9 @@ int padded_dim(int d) {
 
 // Row blocks per wave of the potential kernel: four for D <= 64 (each column
 // fragment read from LDS feeds four MFMA chains; measured 5 % faster on the
-// benchmark workload than two, at two waves per SIMD instead of three).
+// benchmark workload than two, at two waves per SIMD instead of three, and
+// 13 % faster than three, at two waves per SIMD or, with the registers
+// capped, three).
 constexpr int lse_qb(int D) { return D <= 64 ? 4 : (D >= 256 ? 1 : 2); }
 
 }  // namespace

@@ -201,18 +201,29 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
     const int ntiles = c0 < c1 ? (int)((c1 - c0 + T::BN - 1) / T::BN) : 0;
 
     f4 pre[T::PER_T];
-    float bpre = 0.f;
+    // Column biases of the next tile: the raw values load with the tile and
+    // are combined where they are stored, after the tile's products, so that
+    // no wave waits on its loads (nor on the tile's, issued before them)
+    // ahead of its MFMAs.  Index clamped into the split; past it the bias is
+    // -inf.  The product is rounded on its own, as the plain expression is.
+    int64_t jpre = 0;
+    float gpre = 0.f, ypre = 0.f;
     auto fetch_beta = [&](int64_t j0) {
+        jpre = j0 + tid;
         if (tid < T::BN) {
-            const int64_t j = j0 + tid;
-            bpre = j < c1 ? ((vpot ? gamma * ldg(vpot + j) : 0.f) - ldg(vsq + j)) * bscale : -INFINITY;
+            const int64_t jc = jpre < c1 ? jpre : c1 - 1;
+            gpre = vpot ? ldg(vpot + jc) : 0.f;
+            ypre = ldg(vsq + jc);
         }
+    };
+    auto beta_pre = [&]() {
+        return jpre < c1 ? ((vpot ? __fmul_rn(gamma, gpre) : 0.f) - ypre) * bscale : -INFINITY;
     };
     if (ntiles > 0) {
         tile_fetch<D, T::BN>(V, c1, d, c0, tid, pre);
         fetch_beta(c0);
         tile_store<D, T::BN>(vt[0], tid, pre);
-        if (tid < T::BN) bt[0][tid] = bpre;
+        if (tid < T::BN) bt[0][tid] = beta_pre();
     }
     __syncthreads();
 
@@ -266,7 +277,7 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
         }
         if (more) {
             tile_store<D, T::BN>(vt[buf ^ 1], tid, pre);
-            if (tid < T::BN) bt[buf ^ 1][tid] = bpre;
+            if (tid < T::BN) bt[buf ^ 1][tid] = beta_pre();
         }
         __syncthreads();
     }
@@ -587,18 +598,24 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
 
     const int ntiles = (int)((m + T::BN - 1) / T::BN);
     f4 pre[T::PER_T];
-    float bpre = 0.f;
+    // column biases of the next tile, combined where they are stored (as in
+    // the potential kernel)
+    int64_t jpre = 0;
+    float gpre = 0.f, ypre = 0.f;
     auto fetch_beta = [&](int64_t j0) {
+        jpre = j0 + tid;
         if (tid < T::BN) {
-            const int64_t j = j0 + tid;
-            bpre = j < m ? (ldg(g + j) - ldg(ysq + j)) * bscale : -INFINITY;
+            const int64_t jc = jpre < m ? jpre : m - 1;
+            gpre = ldg(g + jc);
+            ypre = ldg(ysq + jc);
         }
     };
+    auto beta_pre = [&]() { return jpre < m ? (gpre - ypre) * bscale : -INFINITY; };
     if (ntiles > 0) {
         tile_fetch<D, T::BN>(Y, m, d, 0, tid, pre);
         fetch_beta(0);
         tile_store<D, T::BN>(vt[0], tid, pre);
-        if (tid < T::BN) bt[0][tid] = bpre;
+        if (tid < T::BN) bt[0][tid] = beta_pre();
     }
     __syncthreads();
 
@@ -672,7 +689,7 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
         }
         if (more) {
             tile_store<D, T::BN>(vt[buf ^ 1], tid, pre);
-            if (tid < T::BN) bt[buf ^ 1][tid] = bpre;
+            if (tid < T::BN) bt[buf ^ 1][tid] = beta_pre();
         }
         __syncthreads();
     }

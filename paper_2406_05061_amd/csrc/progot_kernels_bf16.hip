@@ -258,7 +258,11 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
     const int64_t c1 = c0 + cols_per_split < nv ? c0 + cols_per_split : nv;
     const int ntiles = c0 < c1 ? (int)((c1 - c0 + T::BN - 1) / T::BN) : 0;
     u4 pre[NPART][T::PER_T];
-    float bpre = 0.f;
+    // column biases: raw values loaded with the tile, combined where they are
+    // stored, so that no wave waits on the loads ahead of its MFMAs (index
+    // clamped into the split, -inf past it; the product rounded on its own)
+    int64_t jpre = 0;
+    float gpre = 0.f, ypre = 0.f;
     auto fetch = [&](int t) {
         // uniform tile base, 32-bit per-lane offsets
 #pragma unroll
@@ -268,9 +272,11 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
             for (int r = 0; r < T::PER_T; ++r)
                 pre[p][r] = *reinterpret_cast<const u4 *>(src + (tid + 256 * r) * 8);
         }
+        jpre = c0 + (int64_t)t * T::BN + tid;
         if (tid < T::BN) {
-            const int64_t j = c0 + (int64_t)t * T::BN + tid;
-            bpre = j < c1 ? ((vpot ? gamma * vpot[j] : 0.f) - vsq[j]) * bscale : kNegBig;
+            const int64_t jc = jpre < c1 ? jpre : c1 - 1;
+            gpre = vpot ? vpot[jc] : 0.f;
+            ypre = vsq[jc];
         }
     };
     auto store = [&](int buf) {
@@ -279,7 +285,8 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
 #pragma unroll
             for (int r = 0; r < T::PER_T; ++r)
                 *reinterpret_cast<u4 *>(&vt[buf][p][(tid + 256 * r) * 8]) = pre[p][r];
-        if (tid < T::BN) bt[buf][tid] = bpre;
+        if (tid < T::BN)
+            bt[buf][tid] = jpre < c1 ? ((vpot ? __fmul_rn(gamma, gpre) : 0.f) - ypre) * bscale : kNegBig;
     };
 
     // One sweep over the split's column tiles; (run_m, run_s) per row,
@@ -499,7 +506,9 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
     const int ntiles = (int)((m + BN - 1) / BN);
     u4 pre[NPART][PER_T];
     u4 pret[NYT][PER_T];
-    float bpre = 0.f;
+    // column biases: raw values with the tile, combined where stored
+    int64_t jpre = 0;
+    float gpre = 0.f, ypre = 0.f;
     auto fetch = [&](int t) {
         const int64_t j0 = (int64_t)t * BN;
 #pragma unroll
@@ -514,9 +523,11 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
                     pret[p][r] = *reinterpret_cast<const u4 *>(YTlp + (p * mp + j0) * D + c * 8);
             }
         }
+        jpre = j0 + tid;
         if (tid < BN) {
-            const int64_t j = j0 + tid;
-            bpre = j < m ? (g[j] - ysq[j]) * bscale : kNegBig;
+            const int64_t jc = jpre < m ? jpre : m - 1;
+            gpre = g[jc];
+            ypre = ysq[jc];
         }
     };
     auto store = [&](int buf) {
@@ -530,7 +541,7 @@ __global__ __launch_bounds__(256) void entropic_map_bf16(
                 for (int p = 0; p < NYT; ++p) *reinterpret_cast<u4 *>(&ytr[buf][p][c * 8]) = pret[p][r];
             }
         }
-        if (tid < BN) bt[buf][tid] = bpre;
+        if (tid < BN) bt[buf][tid] = jpre < m ? (gpre - ypre) * bscale : kNegBig;
     };
 
     if (ntiles > 0) {

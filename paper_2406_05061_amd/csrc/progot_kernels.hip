@@ -142,10 +142,11 @@ __device__ __forceinline__ void tile_store(float *__restrict__ lds, int tid,
 // kernels the bodies run once per work item, and without this the compiler
 // hoists every lane-dependent address out of the item loop and keeps it live
 // across items, which pushed the D = 128 kernels into register spills.
+template <int NT = 256>
 __device__ __forceinline__ int item_tid() {
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
-    __builtin_assume(t >= 0 && t < 256);
+    __builtin_assume(t >= 0 && t < NT);
     return t;
 }
 
@@ -551,20 +552,32 @@ __global__ __launch_bounds__(256) void scale_vec(const float *__restrict__ in, f
 // scale2 and the column bias beta_j is the accumulator's initial value, so
 // the score MFMA yields the log2-domain exponent t_ij itself.  The online
 // softmax keeps a running maximum per query (shared by the 4 lane groups).
-template <int D, int QB>
+// With KS = 2 the workgroup is two groups of four waves on the same queries,
+// each streaming every other column tile through LDS tiles of its own, and
+// their online-softmax states merge at the end: twice the waves per query
+// tile, for maps whose query count alone gives the chip one wave per SIMD
+// (16384 queries are 256 workgroups).
+template <int D, int QB, int KS>
 __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, int d,
                                                   const float *__restrict__ Y,
                                                   const float *__restrict__ ysq,
                                                   const float *__restrict__ g, int64_t m,
                                                   float scale2, float bscale, float alpha, float *Xout,
                                                   float *__restrict__ out_sqn, int64_t tile,
-                                                  float (&vt)[2][Tile<D>::FLOATS],
-                                                  float (&bt)[2][Tile<D>::BN]) {
+                                                  float (&vts)[KS][2][Tile<D>::FLOATS],
+                                                  float (&bts)[KS][2][Tile<D>::BN]) {
     using T = Tile<D>;
     constexpr int ROWS = 64 * QB;
     constexpr int NDB = D / 16;   // 16-feature blocks of the output
+    static_assert(KS == 1 || (KS == 2 && QB == 1), "two column groups, one row block per wave");
+    static_assert(KS == 1 || (2 + 4 * NDB) * 256 <= KS * 2 * T::FLOATS, "the group exchange fits in the tiles");
 
-    const int tid = item_tid();
+    // column group (KS = 2: threads 256 grp .. 256 grp + 255) and its tiles
+    const int tid_all = item_tid<256 * KS>();
+    const int grp = KS == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid_all >> 8);   // wave-uniform
+    const int tid = tid_all & 255;
+    float (&vt)[2][T::FLOATS] = vts[grp];
+    float (&bt)[2][T::BN] = bts[grp];
     const int lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lq = lane >> 4;
     const int64_t row0 = tile * ROWS + wave * (QB * 16);
@@ -596,7 +609,13 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
     for (int r = 0; r < 4; ++r)
         pv_off[r] = ((li >> 2) * 16 + 4 * lq + (r ^ (li >> 2))) * 4 + (li & 3);
 
+    // group grp takes column tiles grp, grp + KS, grp + 2 KS, ...; both
+    // groups run niter iterations (one barrier each), a group past its last
+    // tile idling through them
     const int ntiles = (int)((m + T::BN - 1) / T::BN);
+    const int niter = (ntiles + KS - 1) / KS;
+    auto has_tile = [&](int t) { return KS * t + grp < ntiles; };
+    auto tile_col = [&](int t) { return (int64_t)(KS * t + grp) * T::BN; };
     f4 pre[T::PER_T];
     // column biases of the next tile, combined where they are stored (as in
     // the potential kernel)
@@ -611,22 +630,24 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
         }
     };
     auto beta_pre = [&]() { return jpre < m ? (gpre - ypre) * bscale : -INFINITY; };
-    if (ntiles > 0) {
-        tile_fetch<D, T::BN>(Y, m, d, 0, tid, pre);
-        fetch_beta(0);
+    if (has_tile(0)) {
+        tile_fetch<D, T::BN>(Y, m, d, tile_col(0), tid, pre);
+        fetch_beta(tile_col(0));
         tile_store<D, T::BN>(vt[0], tid, pre);
         if (tid < T::BN) bt[0][tid] = beta_pre();
     }
     __syncthreads();
 
-    for (int t = 0; t < ntiles; ++t) {
+    for (int t = 0; t < niter; ++t) {
         const int buf = t & 1;
-        const bool more = t + 1 < ntiles;
+        const bool more = has_tile(t + 1);
         if (more) {
-            const int64_t jn = (int64_t)(t + 1) * T::BN;
+            const int64_t jn = tile_col(t + 1);
             tile_fetch<D, T::BN>(Y, m, d, jn, tid, pre);
             fetch_beta(jn);
         }
+        // KS = 1: always true (t < niter = ntiles)
+        if (KS == 1 || has_tile(t)) {
         const float *vb = vt[buf];
         // accumulators start at beta_j; k outer, (column subtile, row block)
         // inner: NSUB x QB independent accumulation chains
@@ -687,6 +708,7 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
                         o[qb][db] = mfma4(yb[db * 256], p[sub * 4 + r], o[qb][db]);
                 }
         }
+        }
         if (more) {
             tile_store<D, T::BN>(vt[buf ^ 1], tid, pre);
             if (tid < T::BN) bt[buf ^ 1][tid] = beta_pre();
@@ -694,18 +716,52 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
         __syncthreads();
     }
 
+    if constexpr (KS == 2) {
+        // group 1 hands its (max, sum, output) to group 0 through the tiles,
+        // free after the loop's last barrier; group 0 rescales both to the
+        // larger maximum and adds them
+        float *xch = &vts[0][0][0];
+        if (grp == 1) {
+            xch[tid] = run_m[0];
+            xch[256 + tid] = run_l[0];
+#pragma unroll
+            for (int db = 0; db < NDB; ++db)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xch[(2 + 4 * db + r) * 256 + tid] = o[0][db][r];
+        }
+        __syncthreads();
+        if (grp == 0) {
+            const float m1 = xch[tid];
+            const float mn = fmaxf(run_m[0], m1);
+            const float c0 = ex2(run_m[0] - mn), c1 = ex2(m1 - mn);
+            run_l[0] = run_l[0] * c0 + xch[256 + tid] * c1;
+#pragma unroll
+            for (int db = 0; db < NDB; ++db)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    o[0][db][r] = o[0][db][r] * c0 + xch[(2 + 4 * db + r) * 256 + tid] * c1;
+            run_m[0] = mn;
+        }
+    }
+
+    if (grp != 0) return;   // the merged state is group 0's; no barrier follows
+    // the epilogue's lane coordinates, taken afresh so that no lane address
+    // formed before the loop stays live through it
+    const int etid = item_tid<256 * KS>() & 255;
+    const int eli = etid & 15, elq = (etid & 63) >> 4;
+    const int64_t erow0 = tile * ROWS + (etid >> 6) * (QB * 16);
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
         float l = run_l[qb];
         l += __shfl_xor(l, 16);
         l += __shfl_xor(l, 32);
         const float inv = 1.f / l;
-        const int64_t row = row0 + qb * 16 + li;
+        const int64_t row = erow0 + qb * 16 + eli;
         double sq = 0.0;
         if (row < nq) {
 #pragma unroll
             for (int db = 0; db < NDB; ++db) {
-                const int f0 = db * 16 + 4 * lq;
+                const int f0 = db * 16 + 4 * elq;
                 if (f0 >= d) continue;
                 float xo[4], xn[4];
                 if (f0 + 3 < d && (d & 3) == 0) {
@@ -731,33 +787,40 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
         }
         sq += __shfl_xor(sq, 16);
         sq += __shfl_xor(sq, 32);
-        if (out_sqn && lq == 0 && row < nq) stg(out_sqn + row, (float)sq);
+        if (out_sqn && elq == 0 && row < nq) stg(out_sqn + row, (float)sq);
     }
 }
 
+// Column groups of the FP32 map per padded dimension: two at D <= 64, held
+// to 128 VGPRs (4 waves per SIMD: two 8-wave workgroups per CU hold as many
+// waves as four of 4 waves did); one at D = 128 and 256, whose 240-252
+// VGPRs leave no room for the 512-thread launch bound.
+constexpr int map_ks(int D) { return D <= 64 ? 2 : 1; }
+constexpr int map_waves_per_simd(int D) { return D <= 64 ? 4 : 1; }
+
 template <int D, int QB>
-__global__ __launch_bounds__(256) void entropic_map_f32(
+__global__ __launch_bounds__(256 * map_ks(D), map_waves_per_simd(D)) void entropic_map_f32(
     const float *Xq, int64_t nq, int d, const float *__restrict__ Y,
     const float *__restrict__ ysq, const float *__restrict__ g, int64_t m, float scale2,
     float bscale, float alpha, float *Xout, float *__restrict__ out_sqn) {
-    __shared__ float vt[2][Tile<D>::FLOATS];
-    __shared__ float bt[2][Tile<D>::BN];
-    entropic_map_body<D, QB>(Xq, nq, d, Y, ysq, g, m, scale2, bscale, alpha, Xout, out_sqn,
-                             blockIdx.x, vt, bt);
+    __shared__ float vt[map_ks(D)][2][Tile<D>::FLOATS];
+    __shared__ float bt[map_ks(D)][2][Tile<D>::BN];
+    entropic_map_body<D, QB, map_ks(D)>(Xq, nq, d, Y, ysq, g, m, scale2, bscale, alpha, Xout, out_sqn,
+                                        blockIdx.x, vt, bt);
 }
 
 // Grouped map: the (job, 64-query tile) items of many maps in one launch
 // (the McCann steps and final maps of the serving form).
 template <int D>
-__global__ __launch_bounds__(256) void entropic_map_f32_group(const MapJob *__restrict__ jobs, int njobs,
-                                                              int64_t total) {
-    __shared__ float vt[2][Tile<D>::FLOATS];
-    __shared__ float bt[2][Tile<D>::BN];
+__global__ __launch_bounds__(256 * map_ks(D), map_waves_per_simd(D)) void entropic_map_f32_group(const MapJob *__restrict__ jobs,
+                                                                         int njobs, int64_t total) {
+    __shared__ float vt[map_ks(D)][2][Tile<D>::FLOATS];
+    __shared__ float bt[map_ks(D)][2][Tile<D>::BN];
     int j = 0;
     for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
         while (j + 1 < njobs && jobs[j + 1].blk_begin <= item) ++j;
         const MapJob &J = jobs[j];
-        entropic_map_body<D, 1>(J.Xq, J.nq, J.d, J.Y, J.ysq, J.g, J.m, J.scale2, J.bscale, J.alpha,
+        entropic_map_body<D, 1, map_ks(D)>(J.Xq, J.nq, J.d, J.Y, J.ysq, J.g, J.m, J.scale2, J.bscale, J.alpha,
                                 J.Xout, J.out_sqn, item - J.blk_begin, vt, bt);
         __syncthreads();
     }
@@ -766,11 +829,11 @@ __global__ __launch_bounds__(256) void entropic_map_f32_group(const MapJob *__re
 // Workgroups of `kernel` the chip holds at once (the grid of a persistent
 // launch), for the current device; computed once per kernel.
 template <typename K>
-int64_t resident_blocks(K kernel) {
+int64_t resident_blocks(K kernel, int threads = 256) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
         cus < 1 || per_cu < 1)
         return 1024;   // a safe default; any grid size gives the same results
     return (int64_t)cus * per_cu;
@@ -798,8 +861,8 @@ hipError_t lse_group_launch_t(const LseJob *jobs_dev, int njobs, int64_t total, 
 
 template <int D>
 hipError_t map_group_launch_t(const MapJob *jobs_dev, int njobs, int64_t total, hipStream_t s) {
-    static const int64_t cap = resident_blocks(entropic_map_f32_group<D>);
-    timed_launch(1, entropic_map_f32_group<D>, dim3(group_grid(total, cap)), dim3(256), 0, s, jobs_dev,
+    static const int64_t cap = resident_blocks(entropic_map_f32_group<D>, 256 * map_ks(D));
+    timed_launch(1, entropic_map_f32_group<D>, dim3(group_grid(total, cap)), dim3(256 * map_ks(D)), 0, s, jobs_dev,
                  njobs, total);
     return hipGetLastError();
 }
@@ -807,7 +870,7 @@ hipError_t map_group_launch_t(const MapJob *jobs_dev, int njobs, int64_t total, 
 template <int D, int QB>
 hipError_t map_launch_t(const MapArgs &a, float scale2, float bscale, hipStream_t s) {
     const int64_t tiles = (a.nq + 64 * QB - 1) / (64 * QB);
-    timed_launch(1, entropic_map_f32<D, QB>, dim3((unsigned)tiles), dim3(256), 0, s, a.Xq, a.nq, a.d,
+    timed_launch(1, entropic_map_f32<D, QB>, dim3((unsigned)tiles), dim3(256 * map_ks(D)), 0, s, a.Xq, a.nq, a.d,
                  a.Y, a.ysq, a.g, a.m, scale2, bscale, a.alpha, a.Xout, a.out_sqn);
     return hipGetLastError();
 }

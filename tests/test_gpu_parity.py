@@ -95,9 +95,13 @@ def test_sinkhorn_converged(P, n, m, d, gen):
     assert abs(chk[2] - dual) <= 1e-9 * max(1.0, abs(dual)) + 1e-7 * abs(dual)
 
 
+# At d <= 64 the map runs two column groups per workgroup (alternate column
+# tiles, merged at the end): 1, 2 and 3 tiles of 64 columns (one group idle,
+# one tile each, an odd count) are among the cases, as is the 15-tile case.
 @pytest.mark.parametrize("nq,m,d,alpha", [(700, 900, 4, 1.0), (513, 1000, 64, 0.3),
                                           (100, 3000, 128, 0.7), (64, 257, 256, 1.0),
-                                          (1, 33, 5, 1.0)])
+                                          (1, 33, 5, 1.0), (300, 64, 64, 1.0),
+                                          (130, 65, 60, 1.0), (257, 129, 32, 0.5)])
 def test_entropic_map(P, nq, m, d, alpha):
     X, Y = workloads.gmm(seed=40 + d, n=nq, m=m, d=d, n_comp=4)
     Q = workloads.gmm(seed=41 + d, n=nq, m=4, d=d, n_comp=4)[0]

@@ -237,6 +237,10 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
             fetch_beta(jn);
         }
         const float *vb = vt[buf];
+        // raised wave priority while the products issue, so that a SIMD's
+        // other wave, in its exponentials, yields the issue slot to them
+        // (same bits; d = 256 1.7 % faster, d = 64 0-0.3 %)
+        __builtin_amdgcn_s_setprio(1);
         // accumulators start at beta_j: the MFMA output is the exponent t_ij
         f4 acc[QB][T::NSUB];
 #pragma unroll
@@ -256,6 +260,7 @@ __device__ __forceinline__ void lse_partial_body(const LseJob &J, int64_t tile, 
                 acc[qb][sub] = c;
             }
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
             float mx = kNegBig;

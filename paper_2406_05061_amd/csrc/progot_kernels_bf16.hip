@@ -306,6 +306,9 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
             const int buf = t & 1;
             const bool more = t + 1 < ntiles;
             if (more) fetch(t + 1);
+            // raised priority while the products issue (as in the FP32
+            // kernel; same bits, 0.5-1 % at d = 256)
+            __builtin_amdgcn_s_setprio(1);
             // accumulators start at beta_j: the MFMA output is the exponent
             f4 acc[QB][T::NSUB];
 #pragma unroll
@@ -349,6 +352,7 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
                             acc[qb][sub] = mfma_bf(a[cs][1][sub], ub[qb][0][s], acc[qb][sub]);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int qb = 0; qb < QB; ++qb) {
                 // partial sums start at the first subtile's terms (an add to

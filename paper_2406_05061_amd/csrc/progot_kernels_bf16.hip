@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void lse_partial_bf16(
             const bool more = t + 1 < ntiles;
             if (more) fetch(t + 1);
             // raised priority while the products issue (as in the FP32
-            // kernel; same bits, 0.5-1 % at d = 256)
+            // kernel; same bits, 0.5-1.5 % at d = 128 and 256)
             __builtin_amdgcn_s_setprio(1);
             // accumulators start at beta_j: the MFMA output is the exponent
             f4 acc[QB][T::NSUB];

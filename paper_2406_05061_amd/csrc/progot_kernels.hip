@@ -127,6 +127,33 @@ __device__ __forceinline__ void tile_fetch(const float *__restrict__ V, int64_t 
     }
 }
 
+// The loads of tile_fetch with the full-width test taken once for the
+// tile: with the two forms side by side in every round, the map's register
+// allocation at D <= 64 had the narrow form's targets share registers with
+// the wide form's address, and the compiler waited for every earlier load
+// before each round's 16-byte load, one round trip per round.
+template <int D, int BN>
+__device__ __forceinline__ void tile_fetch_wide_first(const float *__restrict__ V, int64_t nv, int d,
+                                                      int64_t j0, int tid,
+                                                      f4 (&pre)[Tile<D, BN>::PER_T]) {
+    using T = Tile<D, BN>;
+    using S = TileSlot<D>;
+    const S slot(tid);
+    const int64_t jb = j0 + slot.row0;
+    const int cb = 4 * slot.cc0;
+    if (d == D) {
+        const f4 *base = reinterpret_cast<const f4 *>(V + jb * D + cb);
+#pragma unroll
+        for (int r = 0; r < T::PER_T; ++r) {
+            f4 v = {0.f, 0.f, 0.f, 0.f};
+            if (jb + S::row_step(r) < nv) v = ldg(base + (S::row_step(r) * D + 4 * S::chunk_step(r)) / 4);
+            pre[r] = v;
+        }
+    } else {
+        tile_fetch<D, BN>(V, nv, d, j0, tid, pre);
+    }
+}
+
 template <int D, int BN>
 __device__ __forceinline__ void tile_store(float *__restrict__ lds, int tid,
                                            const f4 (&pre)[Tile<D, BN>::PER_T]) {
@@ -636,7 +663,7 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
     };
     auto beta_pre = [&]() { return jpre < m ? (gpre - ypre) * bscale : -INFINITY; };
     if (has_tile(0)) {
-        tile_fetch<D, T::BN>(Y, m, d, tile_col(0), tid, pre);
+        tile_fetch_wide_first<D, T::BN>(Y, m, d, tile_col(0), tid, pre);
         fetch_beta(tile_col(0));
         tile_store<D, T::BN>(vt[0], tid, pre);
         if (tid < T::BN) bt[0][tid] = beta_pre();
@@ -648,7 +675,7 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
         const bool more = has_tile(t + 1);
         if (more) {
             const int64_t jn = tile_col(t + 1);
-            tile_fetch<D, T::BN>(Y, m, d, jn, tid, pre);
+            tile_fetch_wide_first<D, T::BN>(Y, m, d, jn, tid, pre);
             fetch_beta(jn);
         }
         // KS = 1: always true (t < niter = ntiles)
@@ -764,21 +791,31 @@ __device__ __forceinline__ void entropic_map_body(const float *Xq, int64_t nq, i
         const int64_t row = erow0 + qb * 16 + eli;
         double sq = 0.0;
         if (row < nq) {
+            // the row's features of every block load first, together
+            float xo[NDB][4];
+            if (d == D) {
+#pragma unroll
+                for (int db = 0; db < NDB; ++db) {
+                    const f4 v = ldg(reinterpret_cast<const f4 *>(Xq + row * D + db * 16 + 4 * elq));
+                    xo[db][0] = v.x; xo[db][1] = v.y; xo[db][2] = v.z; xo[db][3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int db = 0; db < NDB; ++db)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int f = db * 16 + 4 * elq + r;
+                        xo[db][r] = f < d ? ldg(Xq + row * d + f) : 0.f;
+                    }
+            }
 #pragma unroll
             for (int db = 0; db < NDB; ++db) {
                 const int f0 = db * 16 + 4 * elq;
                 if (f0 >= d) continue;
-                float xo[4], xn[4];
-                if (f0 + 3 < d && (d & 3) == 0) {
-                    f4 v = ldg(reinterpret_cast<const f4 *>(Xq + row * d + f0));
-                    xo[0] = v.x; xo[1] = v.y; xo[2] = v.z; xo[3] = v.w;
-                } else {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) xo[r] = f0 + r < d ? ldg(Xq + row * d + f0 + r) : 0.f;
-                }
+                float xn[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    xn[r] = (1.f - alpha) * xo[r] + alpha * (o[qb][db][r] * inv);
+                    xn[r] = (1.f - alpha) * xo[db][r] + alpha * (o[qb][db][r] * inv);
                     if (f0 + r < d) sq += (double)xn[r] * xn[r];
                 }
                 if (f0 + 3 < d && (d & 3) == 0) {
